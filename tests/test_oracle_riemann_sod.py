@@ -1,0 +1,103 @@
+"""Pins of the exact Riemann solver and of a full oracle leapfrog run (Sect. 4, Sod test;
+Sect. 2.4 integrator; Sect. 4.5 energy error).
+
+The exact solver is pinned to the textbook star states (Toro, Riemann Solvers
+and Numerical Methods for Fluid Dynamics, 3rd ed., Table 4.3, tests 1-3,
+printed to 5-6 significant digits), to the Rankine-Hugoniot jump conditions
+across its shock and to the Riemann invariants across its rarefaction.
+
+The oracle's integrator (predict, density, force, correct, Courant dt) is
+pinned by running a reduced-resolution shock tube to t = 0.1 and grading the
+regions the SPH solution resolves against the exact solution, and by the
+total-energy error dE = (E0 - Et)/E0.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import riemann
+from paper_1909_07439_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_riemann_textbook_star_states():
+    g = json.load(open(os.path.join(GOLDEN, "riemann_toro_table_4_3.json")))
+    for case in g["cases"]:
+        st = riemann.star_state(case["left"], case["right"], g["gamma"])
+        for k in ("p_star", "u_star", "rho_star_L", "rho_star_R"):
+            txt = case[k]
+            ref = float(txt)
+            decimals = len(txt.split(".")[1]) if "." in txt else 0
+            tol = 0.5 * 10.0 ** (-decimals) * (1 + 1e-9)
+            assert abs(st[k] - ref) <= tol, (case["name"], k, st[k], ref)
+
+
+@pytest.mark.parametrize("gamma", [1.4, 5.0 / 3.0])
+def test_riemann_jump_conditions(gamma):
+    L, R = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    st = riemann.star_state(L, R, gamma)
+    S = st["S_R"]
+    rR, uR, pR = R
+    rs, us, ps = st["rho_star_R"], st["u_star"], st["p_star"]
+    # mass, momentum, energy flux in the shock frame
+    assert abs(rR * (uR - S) - rs * (us - S)) < 1e-12
+    assert abs(rR * (uR - S) ** 2 + pR - (rs * (us - S) ** 2 + ps)) < 1e-12
+    e = lambda r, u, p: p / ((gamma - 1) * r) + 0.5 * (u - S) ** 2 + p / r
+    assert abs(e(rR, uR, pR) - e(rs, us, ps)) < 1e-11
+    # across the left rarefaction: entropy and the left Riemann invariant
+    rL, uL, pL = L
+    rl = st["rho_star_L"]
+    assert abs(ps / rl ** gamma - pL / rL ** gamma) < 1e-12
+    cL, cs = math.sqrt(gamma * pL / rL), math.sqrt(gamma * ps / rl)
+    assert abs(uL + 2 * cL / (gamma - 1) - (us + 2 * cs / (gamma - 1))) < 1e-12
+    xi = np.linspace(st["S_HL"], st["S_TL"], 7)
+    r, u, p = riemann.sample(xi, L, R, gamma)
+    c = np.sqrt(gamma * p / r)
+    np.testing.assert_allclose(u + 2 * c / (gamma - 1), uL + 2 * cL / (gamma - 1), rtol=1e-12)
+    np.testing.assert_allclose(u - c, xi, atol=1e-12)  # C- characteristic = fan ray
+
+
+def sod_exact_periodic(x, t, gamma):
+    """The periodic tube holds the main problem at x=0 and its mirror image at
+    x=+-1/2; the two do not interact before t ~ 0.13."""
+    L, R = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    xm = np.where(x > 0.25, x - 0.5, np.where(x < -0.25, x + 0.5, x))
+    mirror = np.abs(x) > 0.25
+    xi = np.where(mirror, -xm, xm) / t
+    r, u, p = riemann.sample(xi, L, R, gamma)
+    u = np.where(mirror, -u, u)
+    return r, u, p
+
+
+@pytest.mark.slow
+def test_oracle_shock_tube_t01():
+    c = inputs.sod(dx_left=1.0 / 128, width=1.0 / 8)
+    p = oracle.make_params(c)
+    s = oracle.evaluate(c, p)
+    e0 = oracle.reduce(s)[0]
+    t, dt, nstep = 0.0, s["dt_next"], 0
+    assert abs(dt - 0.3 * 1.2 / 128 / math.sqrt(5.0 / 3.0)) < 0.02 * dt  # 0.3 h_L / c_L
+    while t < 0.1 - 1e-12:
+        dt = min(dt, 0.1 - t)
+        s = oracle.step(s, dt, p)
+        t += dt
+        nstep += 1
+        dt = s["dt_next"]
+    de = (e0 - oracle.reduce(s)[0]) / e0
+    assert abs(de) < 1e-4, de
+    x = s["x"]
+    r, u, pr = sod_exact_periodic(x, 0.1, c["gamma"])
+    fan = (x > -0.11) & (x < -0.04)
+    post = (x > 0.10) & (x < 0.15)
+    far = (np.abs(x) > 0.2) & (np.abs(x) < 0.3)
+    assert np.abs(s["rho"][fan] - r[fan]).mean() < 0.02
+    assert np.abs(s["vx"][fan] - u[fan]).mean() < 0.05
+    assert np.abs(s["rho"][post] - r[post]).mean() < 0.02
+    assert np.abs(s["P"][post] - pr[post]).mean() < 0.02
+    assert np.abs(s["vx"][post] - u[post]).mean() < 0.08
+    assert np.abs(s["P"][far] - pr[far]).max() < 0.02
