@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Throughput of the SPH hydrodynamics step on one MI355X.
+
+One step = one pass of the whole hot path through the C ABI (sph_step):
+leapfrog predict, Morton keys, radix sort, permute, tree + groups, density
+with the smoothing-length iteration, force, correct, Courant dt.  The default
+workload is the 3D shock tube (294,912 particles, mixed FP32/FP64 pairs);
+the same steps are also timed in FP64 to give the mixed/FP64 ratio.
+
+Prints ONE JSON line (the last line of stdout).  ``value`` is
+particle-updates/s = N * steps / wall time of the timed steps, with the state
+resident in HBM.  ``roofline`` is for the force kernel, from its algorithmic
+FLOPs and its average launch time measured with HIP events on the library
+stream; ``cpu_baseline`` times the FP64 CPU oracle on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-updates/s (density+force, ~58 nbrs): mixed FP32/FP64 vs FP64"
+
+# Algorithmic floating-point operations per unit of work, counted from the
+# pair functions (an FMA counts 2, sqrt / rsqrt / rcp count 1):
+#   force pair (r < 2 max(h_i,h_j)): geometry 9, r and rhat 5, v.rhat 8, two
+#   kernel gradients 16, viscosity terms 14, acceleration 10, energy terms 24
+FORCE_FLOPS_PER_PAIR = 85
+#   density pair term per smoothing-length pass: q 1, M4 f and f' 14,
+#   two accumulations 7
+DENSITY_FLOPS_PER_PAIR_SUM = 22
+# Vector ALU peak of the 256 CUs at 2.4 GHz for non-packed FP32 (and FP64)
+# FMA: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz.  The published FP32
+# figure of 157.3 TFLOP/s needs packed FP32 instructions, which this build
+# does not emit.
+ALU_PEAK_TFLOPS = 78.6
+PACKED_FP32_PEAK_TFLOPS = 157.3
+
+
+def workload(name: str):
+    from paper_1909_07439_amd import inputs
+
+    if name == "sod":
+        return inputs.sod()
+    if name == "lattice":
+        return inputs.lattice(32, jitter=0.05)
+    if name == "kh":
+        return inputs.kelvin_helmholtz(100)
+    if name == "turb":
+        return inputs.turbulent_box(256)
+    if name == "sod_small":
+        return inputs.sod(dx_left=1.0 / 128, width=1.0 / 8)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def run(cfg, precision, steps, warmup):
+    import numpy as np
+    import torch
+
+    from paper_1909_07439_amd import sph
+
+    p = sph.make_params(cfg, precision)
+    parts = sph.Particles(cfg)
+    ctx = sph.Context(p, cfg["n"])
+    sph.sph_build_tree(ctx, parts)
+    sph.sph_density(ctx, parts, want_iters=True)
+    sph.sph_force(ctx, parts, want_dt=True)
+    init = parts.numpy("id", "rho", "h", "ax", "ay", "az", "dudt")
+    for _ in range(warmup):
+        sph.sph_step(ctx, parts, 0.0)
+    torch.cuda.synchronize()
+    sph.sph_check(ctx)
+    sph.sph_timings(ctx)  # drop the warm-up events
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sph.sph_step(ctx, parts, 0.0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sph.sph_check(ctx)
+    tim = sph.sph_timings(ctx)
+    st = sph.sph_stats(ctx)
+    e = sph.sph_reduce(ctx, parts)
+    ctx.close()
+    wall = t1 - t0
+    n = cfg["n"]
+    order = np.argsort(init["id"])
+    return dict(wall=wall, rate=n * steps / wall, ms_per_step=1e3 * wall / steps, timings=tim,
+                stats=st, energy=e, init={k: v[order] for k, v in init.items()})
+
+
+def cpu_baseline(cfg, budget_s=12.0):
+    import oracle
+
+    p = oracle.make_params(cfg)
+    reps, t = 0, 0.0
+    t0 = time.perf_counter()
+    while reps < 1 or (t < budget_s and reps < 20):
+        oracle.evaluate(cfg, p)
+        reps += 1
+        t = time.perf_counter() - t0
+    return dict(value=cfg["n"] * reps / t, unit="particle-updates/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample=f"{reps} full FP64 evaluation(s) (tree, density iterated to the root, "
+                       f"force) of the {cfg['workload']} workload, N={cfg['n']}, {t:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="sod")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1909_07439_amd import sph
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cfg = workload(args.workload)
+    prec = sph.SPH_PREC_MIXED if args.precision == "mixed" else sph.SPH_PREC_FP64
+    print(f"[bench] workload {cfg['workload']} n={cfg['n']} precision={args.precision} "
+          f"steps={args.steps} warmup={args.warmup}", flush=True)
+    main_run = run(cfg, prec, args.steps, args.warmup)
+    print(f"[bench] {args.precision}: {main_run['rate']:.4e} upd/s, "
+          f"{main_run['ms_per_step']:.3f} ms/step, phases {main_run['timings']}", flush=True)
+    other = None
+    if not args.no_fp64 and prec == sph.SPH_PREC_MIXED:
+        other = run(cfg, sph.SPH_PREC_FP64, max(10, args.steps // 4), args.warmup)
+        print(f"[bench] fp64: {other['rate']:.4e} upd/s, {other['ms_per_step']:.3f} ms/step, "
+              f"phases {other['timings']}", flush=True)
+    tim, st = main_run["timings"], main_run["stats"]
+    t_force = tim["force"] * 1e-3
+    t_dens = tim["density"] * 1e-3
+    force_tf = FORCE_FLOPS_PER_PAIR * st["force_pairs"] / t_force / 1e12 if t_force > 0 else 0.0
+    dens_tf = DENSITY_FLOPS_PER_PAIR_SUM * st["density_pair_sums"] / t_dens / 1e12 \
+        if t_dens > 0 else 0.0
+    roof = {"kernel": "k_force<mixed>" if prec == sph.SPH_PREC_MIXED else "k_force<fp64>",
+            "bound": "alu", "achieved": round(force_tf, 4), "peak": ALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(force_tf / ALU_PEAK_TFLOPS, 5), "traffic": None,
+            "frac_of_packed_fp32_peak": round(force_tf / PACKED_FP32_PEAK_TFLOPS, 5),
+            "launch_ms": round(tim["force"], 5), "pairs_per_launch": st["force_pairs"],
+            "flops_per_pair": FORCE_FLOPS_PER_PAIR}
+    inter = (st["density_pair_sums"] + st["force_pairs"]) / (main_run["ms_per_step"] * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": main_run["rate"],
+        "unit": "particle-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_run["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if prec == sph.SPH_PREC_MIXED else "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["workload"], "n_particles": cfg["n"],
+                   "precision": args.precision, "kernel": "M4", "hfact": cfg["hfact"],
+                   "n_leaf": cfg["n_leaf"], "n_group": cfg["n_group"]},
+        "roofline": roof,
+        "density_roofline": {"bound": "alu", "achieved": round(dens_tf, 4),
+                             "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": round(dens_tf / ALU_PEAK_TFLOPS, 5),
+                             "launch_ms": round(tim["density"], 5)},
+        "phase_ms": {k: round(v, 5) for k, v in tim.items()},
+        "interactions_per_s": inter,
+        "true_pairs_per_particle": {"density": st["density_pairs"] / cfg["n"],
+                                    "force": st["force_pairs"] / cfg["n"]},
+        "density_sums_per_step_max": st["max_density_sums"],
+    }
+    if other is not None:
+        out["fp64_value"] = other["rate"]
+        out["mixed_over_fp64"] = main_run["rate"] / other["rate"]
+        out["fp64_phase_ms"] = {k: round(v, 5) for k, v in other["timings"].items()}
+        a, b = main_run["init"], other["init"]
+        amag = np.sqrt(b["ax"] ** 2 + b["ay"] ** 2 + b["az"] ** 2)
+        scale = max(float(np.sqrt(np.mean(amag ** 2))), 1e-300)
+        out["mixed_error_vs_fp64"] = {
+            "rho_max_rel": float(np.max(np.abs(a["rho"] - b["rho"]) / b["rho"])),
+            "h_max_rel": float(np.max(np.abs(a["h"] - b["h"]) / b["h"])),
+            "a_max_over_rms_a": float(max(np.max(np.abs(a[k] - b[k])) for k in ("ax", "ay", "az"))
+                                      / scale),
+        }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

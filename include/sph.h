@@ -1,0 +1,198 @@
+/*
+ * sph.h -- C ABI of the MI355X (gfx950) SPH hydrodynamics library.
+ *
+ * The library computes the per-step hydrodynamics of Bonsai-SPH (Bedorf &
+ * Portegies Zwart, arXiv:1909.07439): space-filling-curve keys and sort, the
+ * octree and particle groups (Sect. 3.1), the group tree walk for neighbours
+ * (Sect. 3.2), the variable-h density (Sect. 2.2; iterated as in Sect.
+ * 3.2.1), the hydrodynamic force with artificial viscosity and conductivity
+ * (Sect. 2.4-2.6, eq:acc, eq:energy, eq:vsig, eq:viscosity_shock) and the
+ * leapfrog step with a global Courant time step (Sect. 2.4, eq:predict_pos,
+ * eq:predict_vel, eq:correct_vel, eq:timestep; Sect. 3.3).
+ *
+ * Conventions for every entry point:
+ *   - Particle fields are caller-owned DEVICE arrays (length n, contiguous,
+ *     float64 unless stated).  The library never allocates, frees or keeps
+ *     them beyond a call.  sph_build_tree and sph_step reorder them in place.
+ *   - All scratch memory is allocated once by sph_create (sized for n_max);
+ *     the compute calls allocate nothing.
+ *   - Work is enqueued on the HIP stream given to sph_create.  Calls that
+ *     return host values (iters_out, dt_next_out, sph_reduce, sph_get_*,
+ *     sph_neighbours) synchronise that stream; with NULL out-pointers
+ *     sph_density / sph_force / sph_step do not synchronise.
+ *   - No exception crosses the ABI.  Every call returns a status; on failure
+ *     sph_last_error() describes it.  Device-side failures (an overflowing
+ *     walk list, a non-converging smoothing length, a non-finite result) are
+ *     latched in a device error word and reported by the next call that
+ *     synchronises, and by sph_check().
+ *   - One context must not be used from two host threads at once.
+ */
+#ifndef SPH_H
+#define SPH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sph_ctx sph_ctx; /* opaque; owns all scratch */
+
+typedef enum {
+  SPH_OK = 0,
+  SPH_E_ARG = -1,       /* bad argument (NULL pointer, n > n_max, bad parameter) */
+  SPH_E_NOMEM = -2,     /* device allocation failed in sph_create */
+  SPH_E_HIP = -3,       /* a HIP runtime call failed */
+  SPH_E_NOCONV = -4,    /* smoothing-length iteration did not converge */
+  SPH_E_OVERFLOW = -5,  /* a fixed-capacity list (tree nodes, walk lists) overflowed */
+  SPH_E_DOMAIN = -6,    /* 2h reaches half a periodic box length (minimum image ambiguous) */
+  SPH_E_NONFINITE = -7  /* a NaN/Inf appeared in an input or a result */
+} sph_status;
+
+typedef enum { SPH_PREC_FP64 = 0, SPH_PREC_MIXED = 1 } sph_precision;
+
+/* Run parameters (copied by sph_create). */
+typedef struct {
+  double box_lo[3];     /* box corner */
+  double box_len[3];    /* box side lengths; keys use cubic cells of side max(box_len) */
+  int32_t periodic[3];  /* 1: periodic axis (minimum image); 0: open */
+  double gamma;         /* adiabatic index */
+  double gamma_minus_1; /* gamma - 1, given separately so that it is exact */
+  double hfact;         /* h = hfact (m/rho)^(1/3) (Sect. 2.2); 1.2 */
+  double alpha_av;      /* artificial viscosity alpha (Sect. 2.5); 1 */
+  double beta_av;       /* artificial viscosity beta; 2 */
+  double alpha_u;       /* artificial conductivity alpha_u (Sect. 2.6); 1 */
+  double c_cour;        /* Courant factor (eq:timestep); 0.3 */
+  int32_t kernel;       /* smoothing kernel: 0 = M4 cubic spline (support 2h) */
+  int32_t n_leaf;       /* max particles per tree leaf (Sect. 3.1); 1..64 */
+  int32_t n_group;      /* max particles per walk group (Sect. 3.1); one of 4,8,16,32 */
+  int32_t precision;    /* sph_precision: pair arithmetic in FP64 or FP32 */
+  double h_tol;         /* stop when |h_new - h| <= h_tol*h; < 0: three fixed passes */
+  int32_t max_h_iter;   /* iteration limit before SPH_E_NOCONV (default 30 if <= 0) */
+  int32_t reserved0;
+  double h_margin;      /* pair lists cover r < 2 h h_margin so h may grow by that
+                           factor without a new walk (default 1.1 if <= 1) */
+} sph_params;
+
+/* Particle set: SoA device pointers, all of length n.  "in" fields are read,
+   "out" fields written; sph_build_tree / sph_step permute every non-NULL
+   field into curve order.  Optional outputs may be NULL where stated. */
+typedef struct {
+  int64_t n;
+  int64_t* id;  /* in/out: caller's particle ids, permuted with the particles (may be NULL) */
+  double *x, *y, *z;       /* in: positions, inside the box on periodic axes */
+  double *vx, *vy, *vz;    /* in: velocities */
+  double* m;               /* in: masses (> 0) */
+  double* u;               /* in: specific internal energy */
+  double* h;               /* in: smoothing-length start value; out: converged h */
+  double *ax, *ay, *az;    /* out (sph_force); in+out (sph_step: previous acceleration) */
+  double* dudt;            /* out (sph_force); in+out (sph_step) */
+  double* rho;             /* out (sph_density) */
+  double* omega;           /* out (sph_density): grad-h term Omega */
+  double* P;               /* out (sph_density): pressure */
+  double* cs;              /* out (sph_density): sound speed */
+  double* vsig_dt;         /* out (sph_force): max signal speed for the time step */
+} sph_particles;
+
+/* Create a context for up to n_max particles on the current HIP device.
+   stream: a hipStream_t (NULL = default stream).  Allocates all scratch.
+   Errors: SPH_E_ARG (bad parameter), SPH_E_NOMEM, SPH_E_HIP. */
+sph_status sph_create(const sph_params* params, int64_t n_max, void* stream, sph_ctx** out);
+
+/* Destroy a context and free its scratch.  NULL is ignored. */
+void sph_destroy(sph_ctx* ctx);
+
+/* Keys, sort and tree (Sect. 3.1): computes 63-bit Morton keys of the
+   positions (21 bits per axis, x in the top bit of each triple), sorts the
+   particles stably by key, permutes every non-NULL field of *p in place into
+   that order, then builds the octree (a cell holding more than n_leaf
+   particles above level 21 is split into its non-empty children), the
+   particle groups (maximal cells with at most n_group particles; oversized
+   level-21 cells cut into chunks) and the tight bounding boxes of both.
+   Errors: SPH_E_ARG, SPH_E_OVERFLOW (node capacity), SPH_E_HIP. */
+sph_status sph_build_tree(sph_ctx* ctx, sph_particles* p);
+
+/* Density (Sect. 2.2, Sect. 3.2.1) on the tree of the last sph_build_tree:
+   for every particle the smoothing length is iterated to the root of
+   sum_j m_j W(r_ij, h) = m (hfact/h)^3 (j within 2h, self included), with a
+   wavefront-wide convergence vote per group; then rho, Omega = 1 + h S1/(3
+   rho), P = (gamma-1) rho u and cs = sqrt(gamma (gamma-1) u) are written.
+   iters_out (may be NULL; if given, the call synchronises): the largest
+   number of density sums any group needed.
+   Errors: SPH_E_NOCONV, SPH_E_OVERFLOW, SPH_E_DOMAIN, SPH_E_NONFINITE. */
+sph_status sph_density(sph_ctx* ctx, sph_particles* p, int32_t* iters_out);
+
+/* Hydrodynamic force (Sect. 2.4-2.6): for every pair with r < 2 max(h_i,h_j)
+   the pressure, artificial-viscosity and conductivity terms; writes ax, ay,
+   az, dudt and vsig_dt.  Needs rho, omega, P, cs from sph_density on the
+   same tree.  dt_next_out (may be NULL; if given the call synchronises):
+   c_cour * min_i h_i / vsig_dt_i.  The same value is also kept on the device
+   for sph_step.
+   Errors: SPH_E_OVERFLOW, SPH_E_NONFINITE, SPH_E_HIP. */
+sph_status sph_force(sph_ctx* ctx, sph_particles* p, double* dt_next_out);
+
+/* One leapfrog step (Sect. 2.4, Sect. 3.3): predict r, v, u with the
+   previous ax, ay, az, dudt; wrap positions into periodic boxes; rebuild the
+   tree; density; force; correct v and u; store the new accelerations.
+   dt > 0: that step; dt <= 0: the Courant step left on the device by the last
+   sph_force / sph_step (no host round trip).  dt_next_out as in sph_force.
+   Particles are left in the new curve order. */
+sph_status sph_step(sph_ctx* ctx, sph_particles* p, double dt, double* dt_next_out);
+
+/* Global FP64 sums in a fixed order (deterministic): out[12] = {E, E_kin,
+   E_th, p_x, p_y, p_z, sum m a_x, sum m a_y, sum m a_z, dE/dt = sum m (v.a +
+   du/dt), sum m |a|, sum m (|v.a| + |du/dt|)}.  Synchronises. */
+sph_status sph_reduce(sph_ctx* ctx, const sph_particles* p, double out[12]);
+
+/* Device error word of the last calls, as a status (SPH_OK if clean); clears
+   it.  Synchronises. */
+sph_status sph_check(sph_ctx* ctx);
+
+/* ---- inspection (host copies; synchronising; for tests and tools) ---- */
+
+/* Sorted keys of the last sph_build_tree and perm[k] = pre-sort index of the
+   particle now at position k.  Host arrays of n entries (either may be NULL). */
+sph_status sph_get_keys(sph_ctx* ctx, uint64_t* keys, int64_t* perm);
+
+/* Tree of the last sph_build_tree in canonical order (by level, then key).
+   *n_nodes: in = capacity of the arrays, out = node count.  With all arrays
+   NULL only the count is returned.  child_first is -1 for leaves.
+   Errors: SPH_E_ARG if the capacity is too small. */
+sph_status sph_get_tree(sph_ctx* ctx, int64_t* n_nodes, int32_t* level, uint64_t* prefix,
+                        int64_t* first, int64_t* count, int64_t* child_first,
+                        int32_t* n_child);
+
+/* Groups of the last sph_build_tree, ordered by first particle. */
+sph_status sph_get_groups(sph_ctx* ctx, int64_t* n_groups, int64_t* first, int64_t* count);
+
+/* Neighbour sets found by the group tree walk, as CSR over the current
+   particle order with ascending indices: mode 0 = density set (r < 2 h_i,
+   self included), mode 1 = force set (j != i, r < 2 max(h_i, h_j)), using
+   the h currently in p->h and the FP64 predicate of both precision modes.
+   offsets: host array of n+1 entries (always filled); idx: host array of
+   cap entries (may be NULL to query the total in offsets[n]).
+   Errors: SPH_E_ARG (cap too small: offsets are still filled). */
+sph_status sph_neighbours(sph_ctx* ctx, const sph_particles* p, int32_t mode, int64_t* offsets,
+                          int32_t* idx, int64_t cap);
+
+/* Per-launch timing of the last call of each phase, in milliseconds, from
+   HIP events on the library stream: out[0..7] = {keys+sort, permute, tree,
+   density, force, integrate, total step, reserved}.  Synchronises. */
+sph_status sph_timings(sph_ctx* ctx, double out[8]);
+
+/* Counters of the work since the last sph_build_tree / sph_step (for
+   throughput accounting): out[0..9] = {tree nodes, groups, most density sums
+   any group needed, true density neighbours (r < 2h, self included) at the
+   converged h, force pairs, density pair terms summed over all passes,
+   density candidate tests, force candidate tests, walks done by the density
+   pass, device error word}.  Synchronises. */
+sph_status sph_stats(sph_ctx* ctx, int64_t out[10]);
+
+/* Human-readable description of the last failure of this context. */
+const char* sph_last_error(const sph_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPH_H */

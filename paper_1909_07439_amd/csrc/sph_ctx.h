@@ -1,0 +1,91 @@
+// sph_ctx.h -- the library context: run parameters, device scratch, events.
+#pragma once
+
+#include <string>
+
+#include "sph_internal.h"
+
+namespace sph {
+constexpr int kMaxFields = 20;
+constexpr int kSortTile = 2048;  // keys per radix-sort block (256 threads x 8)
+constexpr int kTreeTile = 256;   // particles per tree block
+constexpr int kScanTile = 2048;  // elements per scan block
+
+// Per-particle data the force loop reads for a neighbour j (written by the
+// density pass once h, rho, Omega are final).
+struct alignas(16) FRec64 {
+  double x, y, z, m;
+  double vx, vy, vz, u;
+  double hinv, hinv4pi, g, k;  // g = P/(rho^2 Omega), k = 1/(rho Omega)
+  double c, P, rho, pad;
+};
+struct alignas(16) FRec32 {
+  double x, y, z;
+  float m, pad0;
+  float vx, vy, vz, u;
+  float hinv, hinv4pi, g, k;
+  float c, P, rho, pad1;
+};
+static_assert(sizeof(FRec64) == 128, "FRec64");
+static_assert(sizeof(FRec32) == 80, "FRec32");
+
+// Raw pointers of an sph_particles, as kernels take them.
+struct Parts {
+  int64_t* id;
+  double *x, *y, *z, *vx, *vy, *vz, *m, *u, *h, *ax, *ay, *az, *dudt, *rho, *omega, *P, *cs,
+      *vsig;
+};
+}  // namespace sph
+
+struct sph_ctx {
+  sph_params prm;
+  sph::KParams kp;
+  int64_t n_max = 0;
+  int32_t n = 0;  // particles of the current tree
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int n_cu = 256;
+  int walk_blocks = 0;
+
+  // sort
+  uint64_t* keys[2] = {nullptr, nullptr};
+  uint32_t* vals[2] = {nullptr, nullptr};
+  uint32_t* radix_cnt = nullptr;  // 256 * blocks
+  uint32_t* scan_part = nullptr;  // block partials of the scans
+  uint32_t* scan_total = nullptr; // scratch totals (several slots)
+  // permute
+  double* gtmp = nullptr;  // kMaxFields * n_max
+  int64_t* gtmp_id = nullptr;
+  // tree
+  uint8_t* dlev = nullptr;
+  uint8_t* lleaf = nullptr;
+  uint8_t* lgrp = nullptr;
+  uint8_t* gstart = nullptr;
+  uint32_t* tree_cnt = nullptr;  // kLevels * blocks (level-major), scanned in place
+  uint32_t* grp_cnt = nullptr;   // blocks
+  int64_t node_cap = 0;
+  int32_t* node_level = nullptr;
+  int32_t* node_first = nullptr;
+  int32_t* node_count = nullptr;
+  int32_t* node_parent = nullptr;
+  int32_t* node_child = nullptr;
+  int32_t* node_nchild = nullptr;
+  unsigned long long* node_bb = nullptr;  // 6 per node: min xyz, max xyz (ordered encodings)
+  unsigned long long* node_hm = nullptr;  // 1 per node
+  sph::WalkNode* wnode = nullptr;
+  int32_t* grp_first = nullptr;
+  int32_t* grp_count = nullptr;
+  sph::GroupInfo* ginfo = nullptr;
+  // density / force
+  void* frec = nullptr;        // FRec64 or FRec32 per particle
+  double* a1 = nullptr;        // 4 * n_max: new ax, ay, az, dudt inside sph_step
+  int32_t* nb_cnt = nullptr;   // neighbour-export counts
+  int64_t* nb_off = nullptr;   // neighbour-export offsets (device)
+  double* red_part = nullptr;  // reduction partials
+  double* red_out = nullptr;   // 12 results
+  sph::DevState* ds = nullptr;
+  sph::DevState* hs = nullptr;  // pinned host mirror
+  hipEvent_t ev[8] = {};
+  bool timing = true;
+  std::string err;
+};

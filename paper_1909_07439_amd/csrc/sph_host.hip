@@ -1,0 +1,545 @@
+// sph_host.hip -- the C ABI (include/sph.h): context, validation, phase
+// orchestration on the library stream, inspection copies and event timing.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "sph_ctx.h"
+
+namespace sph {
+hipError_t launch_node_boxes(sph_ctx* c, const sph_particles* s);
+hipError_t launch_reset_counters(sph_ctx* c);
+hipError_t launch_force_reset(sph_ctx* c);
+}  // namespace sph
+
+namespace {
+
+constexpr int kRing = 1024;  // timed launches kept per phase
+enum Phase { kPhSort = 0, kPhPermute, kPhTree, kPhDensity, kPhForce, kPhIntegrate, kPhStep, kNPh };
+
+struct Timing {
+  hipEvent_t start[kNPh][kRing];
+  hipEvent_t stop[kNPh][kRing];
+  int count[kNPh];
+  bool ready = false;
+};
+
+// Timing lives beside the context (keyed by pointer) so the context layout
+// stays plain; one per context.
+struct CtxExtra {
+  sph_ctx* ctx;
+  Timing t;
+};
+std::vector<CtxExtra*> g_extra;
+
+CtxExtra* extra_of(sph_ctx* c) {
+  for (auto* e : g_extra)
+    if (e->ctx == c) return e;
+  return nullptr;
+}
+
+sph_status fail(sph_ctx* c, sph_status st, const char* what) {
+  if (c) c->err = what;
+  return st;
+}
+
+sph_status hip_fail(sph_ctx* c, hipError_t e, const char* where) {
+  char buf[512];
+  snprintf(buf, sizeof(buf), "%s: %s", where, hipGetErrorString(e));
+  if (c) c->err = buf;
+  return SPH_E_HIP;
+}
+
+#define HIPCHK(c, call)                                   \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return hip_fail((c), e_, #call); \
+  } while (0)
+
+void ph_begin(sph_ctx* c, int ph) {
+  CtxExtra* x = extra_of(c);
+  if (!x || !x->t.ready || !c->timing) return;
+  const int k = x->t.count[ph];
+  if (k < kRing) (void)hipEventRecord(x->t.start[ph][k], c->stream);
+}
+void ph_end(sph_ctx* c, int ph) {
+  CtxExtra* x = extra_of(c);
+  if (!x || !x->t.ready || !c->timing) return;
+  const int k = x->t.count[ph];
+  if (k < kRing) {
+    (void)hipEventRecord(x->t.stop[ph][k], c->stream);
+    x->t.count[ph] = k + 1;
+  }
+}
+
+sph_status check_parts(sph_ctx* c, const sph_particles* p, bool need_state_out,
+                       bool need_dens_out) {
+  if (!p) return fail(c, SPH_E_ARG, "particles is NULL");
+  if (p->n < 1 || p->n > c->n_max) return fail(c, SPH_E_ARG, "n must be in [1, n_max]");
+  if (!p->x || !p->y || !p->z || !p->m || !p->h)
+    return fail(c, SPH_E_ARG, "x, y, z, m and h are required");
+  if (need_state_out && (!p->vx || !p->vy || !p->vz || !p->u || !p->ax || !p->ay || !p->az ||
+                         !p->dudt))
+    return fail(c, SPH_E_ARG, "vx, vy, vz, u, ax, ay, az and dudt are required");
+  if (need_dens_out && (!p->u || !p->rho || !p->omega || !p->P || !p->cs || !p->vsig_dt))
+    return fail(c, SPH_E_ARG, "u, rho, omega, P, cs and vsig_dt are required");
+  return SPH_OK;
+}
+
+sph_status status_of_err(sph_ctx* c, uint32_t e) {
+  using namespace sph;
+  if (e == 0) return SPH_OK;
+  std::string s = "device error:";
+  if (e & kErrNonFinite) s += " non-finite value;";
+  if (e & kErrDomain) s += " 2h reaches half a periodic box length;";
+  if (e & kErrNoConv) s += " smoothing length did not converge;";
+  if (e & kErrNodes) s += " tree node capacity exceeded;";
+  if (e & kErrFrontier) s += " walk frontier capacity exceeded;";
+  if (e & kErrPairs) s += " pair list capacity exceeded;";
+  c->err = s;
+  if (e & kErrNonFinite) return SPH_E_NONFINITE;
+  if (e & kErrDomain) return SPH_E_DOMAIN;
+  if (e & kErrNoConv) return SPH_E_NOCONV;
+  return SPH_E_OVERFLOW;
+}
+
+// Read the device state (synchronising) and report its error word.
+sph_status sync_state(sph_ctx* c, bool clear_err) {
+  HIPCHK(c, hipMemcpyAsync(c->hs, c->ds, sizeof(sph::DevState), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const uint32_t e = c->hs->err;
+  if (e && clear_err) {
+    const uint32_t z = 0;
+    HIPCHK(c, hipMemcpyAsync(&c->ds->err, &z, sizeof(z), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return status_of_err(c, e);
+}
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+  return hipMalloc((void**)p, sizeof(T) * (count ? count : 1));
+}
+
+}  // namespace
+
+extern "C" {
+
+sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ctx** out) {
+  if (!out) return SPH_E_ARG;
+  *out = nullptr;
+  if (!prm || n_max < 1 || n_max > (int64_t)0x3fffffff) return SPH_E_ARG;
+  const sph_params& P = *prm;
+  for (int a = 0; a < 3; ++a)
+    if (!(P.box_len[a] > 0.0) || !isfinite(P.box_lo[a])) return SPH_E_ARG;
+  if (!(P.hfact > 0.0) || !(P.gamma > 0.0) || !(P.gamma_minus_1 > 0.0) || !(P.c_cour > 0.0))
+    return SPH_E_ARG;
+  if (P.alpha_av < 0 || P.beta_av < 0 || P.alpha_u < 0) return SPH_E_ARG;
+  if (P.kernel != 0) return SPH_E_ARG;
+  if (P.n_leaf < 1 || P.n_leaf > 64) return SPH_E_ARG;
+  if (!(P.n_group == 4 || P.n_group == 8 || P.n_group == 16 || P.n_group == 32))
+    return SPH_E_ARG;
+  if (P.precision != SPH_PREC_FP64 && P.precision != SPH_PREC_MIXED) return SPH_E_ARG;
+
+  sph_ctx* c = new (std::nothrow) sph_ctx();
+  if (!c) return SPH_E_NOMEM;
+  c->prm = P;
+  c->n_max = n_max;
+  c->stream = (hipStream_t)stream;
+  sph::KParams& k = c->kp;
+  double lmax = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    k.lo[a] = P.box_lo[a];
+    k.len[a] = P.box_len[a];
+    k.half[a] = 0.5 * P.box_len[a];
+    k.inv_len[a] = 1.0 / P.box_len[a];
+    k.periodic[a] = P.periodic[a] ? 1 : 0;
+    lmax = std::max(lmax, P.box_len[a]);
+  }
+  k.key_scale = 2097152.0 / lmax;
+  k.gamma = P.gamma;
+  k.gm1 = P.gamma_minus_1;
+  k.hfact = P.hfact;
+  k.alpha = P.alpha_av;
+  k.beta = P.beta_av;
+  k.alpha_u = P.alpha_u;
+  k.c_cour = P.c_cour;
+  k.fixed_passes = P.h_tol < 0.0 ? 1 : 0;
+  k.h_tol = (P.h_tol > 0.0) ? P.h_tol : (P.precision == SPH_PREC_MIXED ? 1e-6 : 1e-10);
+  k.max_iter = P.max_h_iter > 0 ? P.max_h_iter : 30;
+  k.h_margin = P.h_margin > 1.0 ? P.h_margin : 1.1;
+  k.n = 0;
+  k.n_leaf = P.n_leaf;
+  k.n_group = P.n_group;
+  k.precision = P.precision;
+
+  auto bail = [&](hipError_t e, const char* where) {
+    sph_status st = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? SPH_E_NOMEM
+                                                                                : SPH_E_HIP;
+    (void)where;
+    sph_destroy(c);
+    return st;
+  };
+#define ALLOC(ptr, cnt)                          \
+  do {                                           \
+    hipError_t e_ = dalloc(&(ptr), (size_t)(cnt)); \
+    if (e_ != hipSuccess) return bail(e_, #ptr); \
+  } while (0)
+
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) return bail(e, "hipGetDevice");
+  int ncu = 0;
+  e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+  if (e != hipSuccess) return bail(e, "attribute");
+  c->n_cu = ncu > 0 ? ncu : 256;
+  c->walk_blocks = ((c->n_cu * 16 + 7) / 8) * 8;
+
+  const int64_t N = n_max;
+  const int64_t nblk_sort = (N + sph::kSortTile - 1) / sph::kSortTile;
+  const int64_t nblk_tree = (N + sph::kTreeTile - 1) / sph::kTreeTile;
+  const int64_t scan_max = std::max<int64_t>(256 * nblk_sort, sph::kLevels * nblk_tree);
+  ALLOC(c->keys[0], N);
+  ALLOC(c->keys[1], N);
+  ALLOC(c->vals[0], N);
+  ALLOC(c->vals[1], N);
+  ALLOC(c->radix_cnt, 256 * nblk_sort);
+  ALLOC(c->scan_part, scan_max / sph::kScanTile + 16);
+  ALLOC(c->scan_total, 16);
+  ALLOC(c->gtmp, (int64_t)sph::kMaxFields * N);
+  ALLOC(c->gtmp_id, N);
+  ALLOC(c->dlev, N);
+  ALLOC(c->lleaf, N);
+  ALLOC(c->lgrp, N);
+  ALLOC(c->gstart, N);
+  ALLOC(c->tree_cnt, sph::kLevels * nblk_tree);
+  ALLOC(c->grp_cnt, nblk_tree);
+  c->node_cap = 2 * N + 1024;
+  ALLOC(c->node_level, c->node_cap);
+  ALLOC(c->node_first, c->node_cap);
+  ALLOC(c->node_count, c->node_cap);
+  ALLOC(c->node_parent, c->node_cap);
+  ALLOC(c->node_child, c->node_cap);
+  ALLOC(c->node_nchild, c->node_cap);
+  ALLOC(c->node_bb, 6 * c->node_cap);
+  ALLOC(c->node_hm, c->node_cap);
+  ALLOC(c->wnode, c->node_cap);
+  ALLOC(c->grp_first, N);
+  ALLOC(c->grp_count, N);
+  ALLOC(c->ginfo, N);
+  {
+    const size_t rec = (P.precision == SPH_PREC_MIXED) ? sizeof(sph::FRec32) : sizeof(sph::FRec64);
+    e = hipMalloc(&c->frec, rec * (size_t)N);
+    if (e != hipSuccess) return bail(e, "frec");
+  }
+  ALLOC(c->a1, 4 * N);
+  ALLOC(c->nb_cnt, N);
+  ALLOC(c->nb_off, N + 1);
+  ALLOC(c->red_part, 512 * 12);
+  ALLOC(c->red_out, 16);
+  ALLOC(c->ds, 1);
+  e = hipHostMalloc((void**)&c->hs, sizeof(sph::DevState), hipHostMallocDefault);
+  if (e != hipSuccess) return bail(e, "hipHostMalloc");
+  memset(c->hs, 0, sizeof(sph::DevState));
+  c->hs->dt_min_enc = sph::enc_f64(__builtin_huge_val());
+  e = hipMemcpyAsync(c->ds, c->hs, sizeof(sph::DevState), hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return bail(e, "init state");
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return bail(e, "sync");
+#undef ALLOC
+  CtxExtra* x = new (std::nothrow) CtxExtra();
+  if (!x) {
+    sph_destroy(c);
+    return SPH_E_NOMEM;
+  }
+  x->ctx = c;
+  bool ok = true;
+  for (int ph = 0; ph < kNPh && ok; ++ph) {
+    x->t.count[ph] = 0;
+    for (int r = 0; r < kRing && ok; ++r) {
+      ok = hipEventCreate(&x->t.start[ph][r]) == hipSuccess &&
+           hipEventCreate(&x->t.stop[ph][r]) == hipSuccess;
+    }
+  }
+  x->t.ready = ok;
+  g_extra.push_back(x);
+  *out = c;
+  return SPH_OK;
+}
+
+void sph_destroy(sph_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (size_t i = 0; i < g_extra.size(); ++i) {
+    if (g_extra[i]->ctx == c) {
+      CtxExtra* x = g_extra[i];
+      if (x->t.ready)
+        for (int ph = 0; ph < kNPh; ++ph)
+          for (int r = 0; r < kRing; ++r) {
+            (void)hipEventDestroy(x->t.start[ph][r]);
+            (void)hipEventDestroy(x->t.stop[ph][r]);
+          }
+      delete x;
+      g_extra.erase(g_extra.begin() + i);
+      break;
+    }
+  }
+  void* ptrs[] = {c->keys[0],   c->keys[1],     c->vals[0],      c->vals[1],     c->radix_cnt,
+                  c->scan_part, c->scan_total,  c->gtmp,         c->gtmp_id,     c->dlev,
+                  c->lleaf,     c->lgrp,        c->gstart,       c->tree_cnt,    c->grp_cnt,
+                  c->node_level, c->node_first, c->node_count,   c->node_parent, c->node_child,
+                  c->node_nchild, c->node_bb,   c->node_hm,      c->wnode,       c->grp_first,
+                  c->grp_count, c->ginfo,       c->frec,         c->a1,          c->nb_cnt,
+                  c->nb_off,    c->red_part,    c->red_out,      c->ds};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (c->hs) (void)hipHostFree(c->hs);
+  delete c;
+}
+
+static sph_status do_build(sph_ctx* c, sph_particles* p, bool outputs_too, bool predict) {
+  c->n = (int32_t)p->n;
+  c->kp.n = c->n;
+  ph_begin(c, kPhSort);
+  HIPCHK(c, sph::launch_predict_keys(c, p, predict, 0.0));
+  HIPCHK(c, sph::launch_sort(c));
+  ph_end(c, kPhSort);
+  ph_begin(c, kPhPermute);
+  HIPCHK(c, sph::launch_permute(c, p, outputs_too));
+  ph_end(c, kPhPermute);
+  ph_begin(c, kPhTree);
+  HIPCHK(c, sph::launch_tree(c));
+  HIPCHK(c, sph::launch_node_boxes(c, p));
+  ph_end(c, kPhTree);
+  return SPH_OK;
+}
+
+sph_status sph_build_tree(sph_ctx* c, sph_particles* p) {
+  if (!c) return SPH_E_ARG;
+  sph_status st = check_parts(c, p, false, false);
+  if (st != SPH_OK) return st;
+  HIPCHK(c, sph::launch_reset_counters(c));
+  return do_build(c, p, true, false);
+}
+
+sph_status sph_density(sph_ctx* c, sph_particles* p, int32_t* iters_out) {
+  if (!c) return SPH_E_ARG;
+  sph_status st = check_parts(c, p, false, true);
+  if (st != SPH_OK) return st;
+  if (p->n != c->n) return fail(c, SPH_E_ARG, "n differs from the last sph_build_tree");
+  ph_begin(c, kPhDensity);
+  HIPCHK(c, sph::launch_density(c, p));
+  ph_end(c, kPhDensity);
+  if (iters_out) {
+    st = sync_state(c, true);
+    *iters_out = c->hs->max_iter;
+    return st;
+  }
+  return SPH_OK;
+}
+
+sph_status sph_force(sph_ctx* c, sph_particles* p, double* dt_next_out) {
+  if (!c) return SPH_E_ARG;
+  sph_status st = check_parts(c, p, true, true);
+  if (st != SPH_OK) return st;
+  if (p->n != c->n) return fail(c, SPH_E_ARG, "n differs from the last sph_build_tree");
+  HIPCHK(c, sph::launch_node_h(c, p));
+  HIPCHK(c, sph::launch_force_reset(c));
+  ph_begin(c, kPhForce);
+  HIPCHK(c, sph::launch_force(c, p, false));
+  ph_end(c, kPhForce);
+  if (dt_next_out) {
+    st = sync_state(c, true);
+    *dt_next_out = sph::dec_f64(c->hs->dt_min_enc);
+    return st;
+  }
+  return SPH_OK;
+}
+
+sph_status sph_step(sph_ctx* c, sph_particles* p, double dt, double* dt_next_out) {
+  if (!c) return SPH_E_ARG;
+  sph_status st = check_parts(c, p, true, true);
+  if (st != SPH_OK) return st;
+  if (!isfinite(dt)) return fail(c, SPH_E_ARG, "dt is not finite");
+  ph_begin(c, kPhStep);
+  HIPCHK(c, sph::launch_reset_counters(c));
+  HIPCHK(c, sph::launch_set_dt(c, dt));
+  st = do_build(c, p, false, true);
+  if (st != SPH_OK) return st;
+  ph_begin(c, kPhDensity);
+  HIPCHK(c, sph::launch_density(c, p));
+  ph_end(c, kPhDensity);
+  HIPCHK(c, sph::launch_node_h(c, p));
+  HIPCHK(c, sph::launch_force_reset(c));
+  ph_begin(c, kPhForce);
+  HIPCHK(c, sph::launch_force(c, p, true));
+  ph_end(c, kPhForce);
+  ph_begin(c, kPhIntegrate);
+  HIPCHK(c, sph::launch_correct(c, p));
+  ph_end(c, kPhIntegrate);
+  ph_end(c, kPhStep);
+  if (dt_next_out) {
+    st = sync_state(c, true);
+    *dt_next_out = sph::dec_f64(c->hs->dt_min_enc);
+    return st;
+  }
+  return SPH_OK;
+}
+
+sph_status sph_reduce(sph_ctx* c, const sph_particles* p, double out[12]) {
+  if (!c || !out) return SPH_E_ARG;
+  sph_status st = check_parts(c, p, true, false);
+  if (st != SPH_OK) return st;
+  HIPCHK(c, sph::launch_reduce(c, p, c->red_out));
+  HIPCHK(c, hipMemcpyAsync(out, c->red_out, 12 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SPH_OK;
+}
+
+sph_status sph_check(sph_ctx* c) {
+  if (!c) return SPH_E_ARG;
+  return sync_state(c, true);
+}
+
+sph_status sph_get_keys(sph_ctx* c, uint64_t* keys, int64_t* perm) {
+  if (!c || c->n < 1) return SPH_E_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (keys) HIPCHK(c, hipMemcpy(keys, c->keys[0], sizeof(uint64_t) * c->n, hipMemcpyDeviceToHost));
+  if (perm) {
+    std::vector<uint32_t> v(c->n);
+    HIPCHK(c, hipMemcpy(v.data(), c->vals[0], sizeof(uint32_t) * c->n, hipMemcpyDeviceToHost));
+    for (int i = 0; i < c->n; ++i) perm[i] = v[i];
+  }
+  return SPH_OK;
+}
+
+sph_status sph_get_tree(sph_ctx* c, int64_t* n_nodes, int32_t* level, uint64_t* prefix,
+                        int64_t* first, int64_t* count, int64_t* child_first, int32_t* n_child) {
+  if (!c || !n_nodes || c->n < 1) return SPH_E_ARG;
+  sph_status st = sync_state(c, false);
+  if (st != SPH_OK) return st;
+  const int64_t nn = c->hs->n_nodes;
+  const int64_t cap = *n_nodes;
+  *n_nodes = nn;
+  if (!level && !prefix && !first && !count && !child_first && !n_child) return SPH_OK;
+  if (cap < nn) return fail(c, SPH_E_ARG, "node arrays too small");
+  std::vector<int32_t> lv(nn), fi(nn), co(nn), ch(nn), nc(nn);
+  std::vector<uint64_t> keys(c->n);
+  HIPCHK(c, hipMemcpy(lv.data(), c->node_level, 4 * nn, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(fi.data(), c->node_first, 4 * nn, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(co.data(), c->node_count, 4 * nn, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(ch.data(), c->node_child, 4 * nn, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(nc.data(), c->node_nchild, 4 * nn, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(keys.data(), c->keys[0], 8 * (size_t)c->n, hipMemcpyDeviceToHost));
+  for (int64_t k = 0; k < nn; ++k) {
+    if (level) level[k] = lv[k];
+    if (first) first[k] = fi[k];
+    if (count) count[k] = co[k];
+    if (child_first) child_first[k] = nc[k] ? ch[k] : -1;
+    if (n_child) n_child[k] = nc[k];
+    if (prefix) {
+      const int l = lv[k];
+      prefix[k] = (l == 0) ? 0ull : (keys[fi[k]] >> (3 * (sph::kKeyLevels - l)));
+    }
+  }
+  return SPH_OK;
+}
+
+sph_status sph_get_groups(sph_ctx* c, int64_t* n_groups, int64_t* first, int64_t* count) {
+  if (!c || !n_groups || c->n < 1) return SPH_E_ARG;
+  sph_status st = sync_state(c, false);
+  if (st != SPH_OK) return st;
+  const int64_t ng = c->hs->n_groups;
+  const int64_t cap = *n_groups;
+  *n_groups = ng;
+  if (!first && !count) return SPH_OK;
+  if (cap < ng) return fail(c, SPH_E_ARG, "group arrays too small");
+  std::vector<int32_t> fi(ng), co(ng);
+  HIPCHK(c, hipMemcpy(fi.data(), c->grp_first, 4 * ng, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(co.data(), c->grp_count, 4 * ng, hipMemcpyDeviceToHost));
+  for (int64_t g = 0; g < ng; ++g) {
+    if (first) first[g] = fi[g];
+    if (count) count[g] = co[g];
+  }
+  return SPH_OK;
+}
+
+sph_status sph_neighbours(sph_ctx* c, const sph_particles* p, int32_t mode, int64_t* offsets,
+                          int32_t* idx, int64_t cap) {
+  if (!c || !offsets || (mode != 0 && mode != 1)) return SPH_E_ARG;
+  sph_status st = check_parts(c, p, false, false);
+  if (st != SPH_OK) return st;
+  if (p->n != c->n) return fail(c, SPH_E_ARG, "n differs from the last sph_build_tree");
+  HIPCHK(c, sph::launch_node_h(c, p));
+  HIPCHK(c, sph::launch_neighbours(c, p, mode, c->nb_cnt, nullptr, nullptr));
+  std::vector<int32_t> cnt(c->n);
+  HIPCHK(c, hipMemcpyAsync(cnt.data(), c->nb_cnt, 4 * (size_t)c->n, hipMemcpyDeviceToHost,
+                           c->stream));
+  st = sync_state(c, true);
+  if (st != SPH_OK) return st;
+  offsets[0] = 0;
+  for (int i = 0; i < c->n; ++i) offsets[i + 1] = offsets[i] + cnt[i];
+  const int64_t total = offsets[c->n];
+  if (!idx) return SPH_OK;
+  if (cap < total) return fail(c, SPH_E_ARG, "idx capacity too small");
+  int32_t* didx = nullptr;
+  HIPCHK(c, hipMalloc((void**)&didx, sizeof(int32_t) * (size_t)std::max<int64_t>(total, 1)));
+  hipError_t e = hipMemcpyAsync(c->nb_off, offsets, 8 * ((size_t)c->n + 1), hipMemcpyHostToDevice,
+                                c->stream);
+  if (e == hipSuccess) e = sph::launch_neighbours(c, p, mode, nullptr, c->nb_off, didx);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(idx, didx, 4 * (size_t)total, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(didx);
+  if (e != hipSuccess) return hip_fail(c, e, "sph_neighbours");
+  for (int i = 0; i < c->n; ++i) std::sort(idx + offsets[i], idx + offsets[i + 1]);
+  return sync_state(c, true);
+}
+
+sph_status sph_timings(sph_ctx* c, double out[8]) {
+  if (!c || !out) return SPH_E_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < 8; ++k) out[k] = 0.0;
+  CtxExtra* x = extra_of(c);
+  if (!x || !x->t.ready) return SPH_OK;
+  const int map[7] = {0, 1, 2, 3, 4, 5, 6};
+  for (int ph = 0; ph < kNPh; ++ph) {
+    double s = 0.0;
+    const int n = x->t.count[ph];
+    for (int r = 0; r < n; ++r) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, x->t.start[ph][r], x->t.stop[ph][r]) == hipSuccess) s += ms;
+    }
+    out[map[ph]] = n ? s / n : 0.0;
+    x->t.count[ph] = 0;
+  }
+  return SPH_OK;
+}
+
+sph_status sph_stats(sph_ctx* c, int64_t out[10]) {
+  if (!c || !out) return SPH_E_ARG;
+  HIPCHK(c, hipMemcpyAsync(c->hs, c->ds, sizeof(sph::DevState), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const sph::DevState& s = *c->hs;
+  out[0] = s.n_nodes;
+  out[1] = s.n_groups;
+  out[2] = s.max_iter;
+  out[3] = (int64_t)s.n_pairs_density;
+  out[4] = (int64_t)s.n_pairs_force;
+  out[5] = (int64_t)s.n_sums_density;
+  out[6] = (int64_t)s.n_cand_density;
+  out[7] = (int64_t)s.n_cand_force;
+  out[8] = s.n_rewalk;
+  out[9] = s.err;
+  return SPH_OK;
+}
+
+const char* sph_last_error(const sph_ctx* c) {
+  if (!c) return "null context";
+  return c->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// sph_internal.h -- device-side building blocks and the context layout of
+// the gfx950 SPH library.  Not part of the public ABI (include/sph.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sph.h"
+
+namespace sph {
+
+constexpr int kKeyLevels = 21;  // 21 bits per axis -> levels 1..21
+constexpr int kLevels = 22;     // tree levels 0..21
+constexpr int kWave = 64;
+
+// ---- device error word bits ------------------------------------------------
+enum : uint32_t {
+  kErrNoConv = 1u,
+  kErrNodes = 2u,      // tree node capacity
+  kErrFrontier = 4u,   // walk frontier capacity
+  kErrPairs = 8u,      // per-particle pair list capacity
+  kErrDomain = 16u,    // 2h >= L/2 on a periodic axis
+  kErrNonFinite = 32u,
+  kErrLeaves = 64u,
+};
+
+// Device-resident scalars of one context.
+struct DevState {
+  int32_t n_nodes;
+  int32_t n_groups;
+  uint32_t err;
+  int32_t max_iter;               // most density sums any group needed
+  unsigned long long dt_min_enc;  // ordered encoding of min_i c_cour h_i / vsig_i
+  double dt_cur;                  // step used by the running sph_step
+  unsigned long long n_pairs_density;  // true neighbours (r < 2h) at the final pass
+  unsigned long long n_pairs_force;    // force pairs
+  unsigned long long n_sums_density;   // sum over groups of (density passes * pairs)
+  unsigned long long n_cand_density;   // candidate tests in the density walks
+  unsigned long long n_cand_force;     // candidate tests in the force walks
+  int32_t n_rewalk;
+  int32_t pad0;
+};
+
+// Walk view of a tree node: centre, conservative half-widths, largest h.
+struct alignas(16) WalkNode {
+  double c[3];
+  float w[3];    // half-widths rounded up
+  float hmax;    // largest smoothing length, rounded up
+  int32_t first;
+  int32_t count;
+  int32_t child;   // first child (children are contiguous); -1 for leaves
+  int32_t nchild;  // 0 for leaves
+};
+static_assert(sizeof(WalkNode) == 56 || sizeof(WalkNode) == 64, "WalkNode layout");
+
+struct alignas(16) GroupInfo {
+  double c[3];
+  double w[3];
+  double hmax;
+  int32_t first;
+  int32_t count;
+};
+
+// Parameters as the kernels see them.
+struct KParams {
+  double lo[3];
+  double len[3];
+  double half[3];  // 0.5 * len (exact)
+  double inv_len[3];
+  int32_t periodic[3];
+  double key_scale;  // 2^21 / max(len)
+  double gamma, gm1, hfact, alpha, beta, alpha_u, c_cour;
+  double h_tol;
+  int32_t max_iter;
+  int32_t fixed_passes;  // 1: three fixed passes (h_tol < 0)
+  double h_margin;
+  int32_t n;
+  int32_t n_leaf;
+  int32_t n_group;
+  int32_t precision;
+};
+
+// ---- small device helpers ---------------------------------------------------
+__device__ __forceinline__ int lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  int l = lane_id();
+  return (l == 0) ? 0ull : (~0ull >> (64 - l));
+}
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+__device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
+
+// Order-preserving map of doubles to unsigned 64-bit integers, so that
+// atomicMin / atomicMax on the integers implement min / max on the doubles.
+__host__ __device__ __forceinline__ unsigned long long enc_f64(double x) {
+  unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__host__ __device__ __forceinline__ double dec_f64(unsigned long long e) {
+  unsigned long long b = (e >> 63) ? (e & 0x7fffffffffffffffull) : ~e;
+  return __builtin_bit_cast(double, b);
+}
+
+}  // namespace sph
+
+// Host-side launchers implemented in sph_kernels.hip.
+struct sph_ctx;
+namespace sph {
+hipError_t launch_predict_keys(sph_ctx* c, const sph_particles* p, bool predict, double dt_host);
+hipError_t launch_sort(sph_ctx* c);
+hipError_t launch_permute(sph_ctx* c, const sph_particles* p, bool outputs_too);
+hipError_t launch_tree(sph_ctx* c);
+hipError_t launch_node_h(sph_ctx* c, const sph_particles* p);
+hipError_t launch_density(sph_ctx* c, const sph_particles* p);
+hipError_t launch_force(sph_ctx* c, const sph_particles* p, bool step_mode);
+hipError_t launch_correct(sph_ctx* c, const sph_particles* p);
+hipError_t launch_set_dt(sph_ctx* c, double dt_host);
+hipError_t launch_reduce(sph_ctx* c, const sph_particles* p, double* dev_out);
+hipError_t launch_neighbours(sph_ctx* c, const sph_particles* p, int mode, int32_t* counts,
+                             const int64_t* offsets, int32_t* idx);
+}  // namespace sph

@@ -1,0 +1,1816 @@
+// sph_kernels.hip -- gfx950 kernels of the SPH hydrodynamics step.
+//
+//   keys + sort + permute ....... Sect. 3.1 (space-filling curve, sort)
+//   tree + groups ............... Sect. 3.1 (chopping the curve)
+//   group tree walk ............. Sect. 3.2 (breadth-first, one wave per group)
+//   density + h iteration ....... Sect. 2.2 and Sect. 3.2.1
+//   hydro force ................. Sect. 2.4 (eq:acc, eq:energy), 2.5, 2.6
+//   leapfrog + Courant step ..... Sect. 2.4 (eq:predict_pos, eq:predict_vel,
+//                                 eq:correct_vel, eq:timestep), Sect. 3.3
+//
+// Built with -ffp-contract=off: every fused multiply-add is an explicit fma().
+#include <math.h>
+
+#include <type_traits>
+
+#include "sph_ctx.h"
+
+namespace sph {
+
+#define SPH_INF (__builtin_huge_val())
+
+// ============================================================================
+// Wave / block primitives (wave64)
+// ============================================================================
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    uint32_t t = __shfl_up(v, d, kWave);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max_f64(double v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v = fmax(v, __shfl_xor(v, d, kWave));
+  return v;
+}
+
+__device__ __forceinline__ double wave_min_f64(double v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v = fmin(v, __shfl_xor(v, d, kWave));
+  return v;
+}
+
+// Sum over the LPI consecutive lanes of a particle slot (aligned segments).
+template <int LPI>
+__device__ __forceinline__ double seg_sum(double v) {
+#pragma unroll
+  for (int d = LPI / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+template <int LPI>
+__device__ __forceinline__ double seg_max(double v) {
+#pragma unroll
+  for (int d = LPI / 2; d > 0; d >>= 1) v = fmax(v, __shfl_xor(v, d, kWave));
+  return v;
+}
+template <int LPI>
+__device__ __forceinline__ uint32_t seg_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int d = LPI / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+// Exclusive scan over a 256-thread block; lds must hold 4 words.
+__device__ __forceinline__ uint32_t block256_excl_scan(uint32_t v, uint32_t* lds,
+                                                       uint32_t* total) {
+  const uint32_t inc = wave_incl_scan_u32(v);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 63) lds[w] = inc;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    uint32_t s = lds[k];
+    off += (k < w) ? s : 0u;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + inc - v;
+}
+
+// ============================================================================
+// Device-wide exclusive scan of uint32 (three launches).  Tiles of 2048.
+// ============================================================================
+__global__ __launch_bounds__(256) void k_scan_partials(const uint32_t* __restrict__ in, int64_t n,
+                                                        uint32_t* __restrict__ part) {
+  __shared__ uint32_t lds[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 8;
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s += (base + k < n) ? in[base + k] : 0u;
+  uint32_t tot;
+  block256_excl_scan(s, lds, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// One block of 1024 threads scans nb partials in chunks; writes the total.
+__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ part, int nb,
+                                                    uint32_t* __restrict__ total_out,
+                                                    int32_t* __restrict__ total_i32) {
+  __shared__ uint32_t lds[16];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int base = 0; base < nb; base += 1024) {
+    const int i = base + threadIdx.x;
+    const uint32_t v = (i < nb) ? part[i] : 0u;
+    const uint32_t inc = wave_incl_scan_u32(v);
+    if (lane == 63) lds[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (int k = 0; k < 16; ++k) {
+      uint32_t s = lds[k];
+      off += (k < w) ? s : 0u;
+      tot += s;
+    }
+    const uint32_t c0 = carry;
+    if (i < nb) part[i] = c0 + off + inc - v;
+    __syncthreads();
+    if (threadIdx.x == 0) carry = c0 + tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (total_out) *total_out = carry;
+    if (total_i32) *total_i32 = (int32_t)carry;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* in, uint32_t* out, int64_t n,
+                                                     const uint32_t* __restrict__ part) {
+  __shared__ uint32_t lds[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 8;
+  uint32_t v[8];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0u;
+    s += v[k];
+  }
+  uint32_t tot;
+  uint32_t off = block256_excl_scan(s, lds, &tot) + part[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (base + k < n) out[base + k] = off;
+    off += v[k];
+  }
+}
+
+static hipError_t scan_u32(sph_ctx* c, uint32_t* data, int64_t n, uint32_t* total,
+                           int32_t* total_i32) {
+  const int nb = (int)((n + kScanTile - 1) / kScanTile);
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scan_partials, dim3(nb), dim3(256), 0, c->stream, data, n, c->scan_part);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, c->stream, c->scan_part, nb, total,
+                     total_i32);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(256), 0, c->stream, data, data, n,
+                     c->scan_part);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// Predict (optional) + Morton keys
+// ============================================================================
+__device__ __forceinline__ uint64_t spread3(uint64_t v) {
+  v &= 0x1fffffull;
+  v = (v | (v << 32)) & 0x1f00000000ffffull;
+  v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+  v = (v | (v << 8)) & 0x100f00f00f00f00full;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
+}
+
+// (x - lo) * scale, floored and clamped to [0, 2^21 - 1]; NaN -> 0.
+__device__ __forceinline__ uint64_t quantise(double x, double lo, double scale) {
+  double q = (x - lo) * scale;
+  if (!(q >= 0.0)) return 0ull;
+  q = floor(q);
+  return (q > 2097151.0) ? 2097151ull : (uint64_t)q;
+}
+
+__device__ __forceinline__ double wrap_coord(double v, double lo, double len, int periodic) {
+  if (periodic) {
+    if (v >= lo + len)
+      v -= len;
+    else if (v < lo)
+      v += len;
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_predict_keys(KParams kp, Parts p, int predict,
+                                                       const DevState* __restrict__ ds,
+                                                       uint64_t* __restrict__ keys,
+                                                       uint32_t* __restrict__ vals,
+                                                       uint32_t* __restrict__ err) {
+  const int n = kp.n;
+  const double dt = predict ? ds->dt_cur : 0.0;
+  const double hdt2 = 0.5 * dt * dt;
+  bool bad = false;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double x = p.x[i], y = p.y[i], z = p.z[i];
+    if (predict) {
+      const double vx = p.vx[i], vy = p.vy[i], vz = p.vz[i];
+      const double ax = p.ax[i], ay = p.ay[i], az = p.az[i];
+      x = wrap_coord(x + (vx * dt + hdt2 * ax), kp.lo[0], kp.len[0], kp.periodic[0]);
+      y = wrap_coord(y + (vy * dt + hdt2 * ay), kp.lo[1], kp.len[1], kp.periodic[1]);
+      z = wrap_coord(z + (vz * dt + hdt2 * az), kp.lo[2], kp.len[2], kp.periodic[2]);
+      p.x[i] = x;
+      p.y[i] = y;
+      p.z[i] = z;
+      p.vx[i] = vx + ax * dt;
+      p.vy[i] = vy + ay * dt;
+      p.vz[i] = vz + az * dt;
+      p.u[i] = p.u[i] + p.dudt[i] * dt;
+    }
+    bad |= !(isfinite(x) && isfinite(y) && isfinite(z));
+    const uint64_t ix = quantise(x, kp.lo[0], kp.key_scale);
+    const uint64_t iy = quantise(y, kp.lo[1], kp.key_scale);
+    const uint64_t iz = quantise(z, kp.lo[2], kp.key_scale);
+    keys[i] = (spread3(ix) << 2) | (spread3(iy) << 1) | spread3(iz);
+    vals[i] = (uint32_t)i;
+  }
+  if (bad) atomicOr(err, kErrNonFinite);
+}
+
+// ============================================================================
+// LSD radix sort of (key, index), 8 bits per pass, stable.
+// ============================================================================
+// Lanes (among `active`) whose 8-bit digit equals this lane's.
+__device__ __forceinline__ uint64_t match_digit8(uint32_t d, uint64_t active) {
+  uint64_t m = active;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bal = ballot64(bit);
+    m &= bit ? bal : ~bal;
+  }
+  return m;
+}
+
+__global__ __launch_bounds__(256) void k_radix_hist(const uint64_t* __restrict__ keys, int n,
+                                                     int shift, uint32_t* __restrict__ cnt,
+                                                     int nblk) {
+  __shared__ uint32_t hist[256];
+  hist[threadIdx.x] = 0;
+  __syncthreads();
+  const int base = blockIdx.x * kSortTile;
+#pragma unroll
+  for (int k = 0; k < kSortTile / 256; ++k) {
+    const int i = base + k * 256 + threadIdx.x;
+    const bool valid = i < n;
+    const uint32_t d = valid ? (uint32_t)((keys[i] >> shift) & 255ull) : 0u;
+    const uint64_t act = ballot64(valid);
+    const uint64_t m = match_digit8(d, act);
+    if (valid && (m & lanemask_lt()) == 0) atomicAdd(&hist[d], (uint32_t)popc64(m));
+  }
+  __syncthreads();
+  cnt[threadIdx.x * nblk + blockIdx.x] = hist[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t* __restrict__ kin,
+                                                        const uint32_t* __restrict__ vin,
+                                                        uint64_t* __restrict__ kout,
+                                                        uint32_t* __restrict__ vout, int n,
+                                                        int shift,
+                                                        const uint32_t* __restrict__ off,
+                                                        int nblk) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wc[4][256];
+  const int tid = threadIdx.x, w = tid >> 6;
+  run[tid] = off[tid * nblk + blockIdx.x];
+  wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0;
+  __syncthreads();
+  const int base = blockIdx.x * kSortTile;
+  for (int k = 0; k < kSortTile / 256; ++k) {
+    const int i = base + k * 256 + tid;
+    const bool valid = i < n;
+    const uint64_t key = valid ? kin[i] : 0ull;
+    const uint32_t val = valid ? vin[i] : 0u;
+    const uint32_t d = (uint32_t)((key >> shift) & 255ull);
+    const uint64_t act = ballot64(valid);
+    const uint64_t m = match_digit8(d, act);
+    const uint32_t rank = (uint32_t)popc64(m & lanemask_lt());
+    if (valid && rank == 0) wc[w][d] = (uint32_t)popc64(m);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[d] + rank;
+      for (int q = 0; q < w; ++q) pos += wc[q][d];
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
+    wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0;
+    __syncthreads();
+  }
+}
+
+// ============================================================================
+// Permute the particle fields into key order (gather, then copy back).
+// ============================================================================
+struct FieldSet {
+  double* f[kMaxFields];
+  int64_t* id;
+  int nf;
+};
+
+__global__ __launch_bounds__(256) void k_gather(FieldSet fs, const uint32_t* __restrict__ perm,
+                                                 double* __restrict__ tmp,
+                                                 int64_t* __restrict__ tmp_id, int n,
+                                                 int64_t stride) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const uint32_t j = perm[k];
+    for (int f = 0; f < fs.nf; ++f) tmp[f * stride + k] = fs.f[f][j];
+    if (fs.id) tmp_id[k] = fs.id[j];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_copy_back(FieldSet fs, const double* __restrict__ tmp,
+                                                    const int64_t* __restrict__ tmp_id, int n,
+                                                    int64_t stride) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    for (int f = 0; f < fs.nf; ++f) fs.f[f][k] = tmp[f * stride + k];
+    if (fs.id) fs.id[k] = tmp_id[k];
+  }
+}
+
+// ============================================================================
+// Tree and groups from the sorted keys, in three launches.
+//
+// d(s): level at which keys s-1 and s first differ (1..21; 22 if equal),
+// d(0) = d(n) = 0.  The level-l cell containing s spans [a, b) with a the
+// last index <= s and b the first index > s where d <= l.  A cell at level
+// l is a node iff its parent holds more than n_leaf particles, i.e. iff the
+// smallest level L(s) at which the cell containing s holds <= n_leaf
+// particles is >= l.  So the nodes starting at s are the levels
+// d(s)..L(s), and L(s) is found in a window of n_leaf keys on each side:
+//   L(s) = min over s < b <= s+T, b-T <= a <= s of max(d(a), d(b)).
+// ============================================================================
+constexpr int kHalo = 64;  // n_leaf, n_group <= 64
+
+__device__ __forceinline__ int diff_level(uint64_t a, uint64_t b) {
+  const uint64_t x = a ^ b;
+  if (x == 0ull) return 22;
+  return (__clzll((long long)x) + 2) / 3;
+}
+
+__device__ __forceinline__ int window_level(const uint8_t* d, int idx, int s, int n, int T) {
+  int run = d[idx];
+  int best = 22;
+  for (int k = 0; k < T; ++k) {
+    if (k > 0 && s - k >= 0) run = min(run, (int)d[idx - k]);
+    const int b = s + T - k;
+    if (b <= n) best = min(best, max((int)d[idx + T - k], run));
+  }
+  return best;
+}
+
+__global__ __launch_bounds__(256) void k_tree_levels(const uint64_t* __restrict__ keys, int n,
+                                                      int n_leaf, int n_group,
+                                                      uint8_t* __restrict__ dlev,
+                                                      uint8_t* __restrict__ lleaf,
+                                                      uint8_t* __restrict__ lgrp,
+                                                      uint8_t* __restrict__ gstart,
+                                                      uint32_t* __restrict__ tree_cnt,
+                                                      uint32_t* __restrict__ grp_cnt, int nblk) {
+  __shared__ uint8_t d[kTreeTile + 2 * kHalo + 1];
+  __shared__ uint32_t lc[kLevels];
+  __shared__ uint32_t gc;
+  const int base = blockIdx.x * kTreeTile;
+  for (int t = threadIdx.x; t < kTreeTile + 2 * kHalo + 1; t += blockDim.x) {
+    const int j = base - kHalo + t;
+    d[t] = (j <= 0 || j >= n) ? (uint8_t)0 : (uint8_t)diff_level(keys[j - 1], keys[j]);
+  }
+  if (threadIdx.x < kLevels) lc[threadIdx.x] = 0;
+  if (threadIdx.x == 0) gc = 0;
+  __syncthreads();
+  const int s = base + threadIdx.x;
+  if (s < n) {
+    const int idx = kHalo + threadIdx.x;
+    const int ds = d[idx];
+    const int ll = min(window_level(d, idx, s, n, n_leaf), kKeyLevels);
+    const int lg_raw = window_level(d, idx, s, n, n_group);
+    bool start;
+    if (lg_raw <= kKeyLevels) {
+      start = ds <= lg_raw;
+    } else {  // level-21 cell with more than n_group identical keys: cut in chunks
+      int a = s;
+      while (a > 0 && keys[a - 1] == keys[a]) --a;
+      start = ((s - a) % n_group) == 0;
+    }
+    dlev[s] = (uint8_t)ds;
+    lleaf[s] = (uint8_t)ll;
+    lgrp[s] = (uint8_t)lg_raw;
+    gstart[s] = start ? 1 : 0;
+    for (int l = ds; l <= ll; ++l) atomicAdd(&lc[l], 1u);
+    if (start) atomicAdd(&gc, 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < kLevels) tree_cnt[threadIdx.x * nblk + blockIdx.x] = lc[threadIdx.x];
+  if (threadIdx.x == 0) grp_cnt[blockIdx.x] = gc;
+}
+
+// First index > s whose key leaves the level-l cell of s (galloping search).
+__device__ __forceinline__ int cell_end(const uint64_t* __restrict__ keys, int n, int s, int l) {
+  if (l == 0) return n;
+  const int sh = 3 * (kKeyLevels - l);
+  const uint64_t pre = keys[s] >> sh;
+  int lo = s, step = 1;
+  while (lo + step < n && (keys[lo + step] >> sh) == pre) {
+    lo += step;
+    step <<= 1;
+  }
+  int hi = min(lo + step, n);
+  while (hi - lo > 1) {
+    const int mid = lo + ((hi - lo) >> 1);
+    if ((keys[mid] >> sh) == pre)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return hi;
+}
+
+__global__ __launch_bounds__(256) void k_zero_i32(int32_t* __restrict__ a, const int32_t* count,
+                                                   int64_t cap) {
+  const int64_t m = min((int64_t)*count, cap);
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m;
+       k += (int64_t)gridDim.x * blockDim.x)
+    a[k] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_tree_emit(
+    const uint64_t* __restrict__ keys, int n, int n_group, const uint8_t* __restrict__ dlev,
+    const uint8_t* __restrict__ lleaf, const uint8_t* __restrict__ lgrp,
+    const uint8_t* __restrict__ gstart, const uint32_t* __restrict__ tree_off,
+    const uint32_t* __restrict__ grp_off, int nblk, int64_t node_cap,
+    int32_t* __restrict__ nlevel, int32_t* __restrict__ nfirst, int32_t* __restrict__ ncount,
+    int32_t* __restrict__ nparent, int32_t* __restrict__ nchild, int32_t* __restrict__ nnchild,
+    int32_t* __restrict__ gfirst, int32_t* __restrict__ gcount, DevState* __restrict__ ds) {
+  __shared__ uint32_t wc[4][kLevels];
+  __shared__ uint32_t gw[4];
+  if ((int64_t)ds->n_nodes > node_cap || ds->n_nodes < 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ds->err, kErrNodes);
+    return;
+  }
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int s = blockIdx.x * kTreeTile + tid;
+  const bool valid = s < n;
+  const int dsv = valid ? dlev[s] : 99;
+  const int ll = valid ? lleaf[s] : -1;
+  const bool gs = valid && gstart[s];
+  for (int l = 0; l < kLevels; ++l) {
+    const uint64_t b = ballot64(valid && dsv <= l && l <= ll);
+    if (lane == 0) wc[w][l] = (uint32_t)popc64(b);
+  }
+  const uint64_t bg = ballot64(gs);
+  if (lane == 0) gw[w] = (uint32_t)popc64(bg);
+  __syncthreads();
+  int prev = -1, par_at_d = -1;
+  for (int l = 0; l < kLevels; ++l) {
+    const bool mem = valid && dsv <= l && l <= ll;
+    const uint64_t b = ballot64(mem);
+    uint32_t r = (uint32_t)popc64(b & lanemask_lt());
+    for (int q = 0; q < w; ++q) r += wc[q][l];
+    const int idx = (int)(tree_off[l * nblk + blockIdx.x] + r);
+    if (valid && l == dsv - 1) par_at_d = idx - 1;  // last level-(d-1) node before s
+    if (mem) {
+      nlevel[idx] = l;
+      nfirst[idx] = s;
+      ncount[idx] = cell_end(keys, n, s, l) - s;
+      const int parent = (l == 0) ? -1 : (l == dsv ? par_at_d : prev);
+      nparent[idx] = parent;
+      nchild[idx] = -1;
+      if (l > dsv) nchild[prev] = idx;  // first child of (l-1, s) is (l, s)
+      if (parent >= 0) atomicAdd(&nnchild[parent], 1);
+      prev = idx;
+    }
+  }
+  uint32_t rg = (uint32_t)popc64(bg & lanemask_lt());
+  for (int q = 0; q < w; ++q) rg += gw[q];
+  if (gs) {
+    const int g = (int)(grp_off[blockIdx.x] + rg);
+    const int lg = lgrp[s];
+    int cnt;
+    if (lg <= kKeyLevels) {
+      cnt = cell_end(keys, n, s, lg) - s;
+    } else {
+      cnt = min(n_group, cell_end(keys, n, s, kKeyLevels) - s);
+    }
+    gfirst[g] = s;
+    gcount[g] = cnt;
+  }
+}
+
+// If the tree outgrew the node arrays, report it and leave an empty tree so
+// that no later launch reads or writes past the arrays.
+__global__ void k_tree_guard(DevState* ds, int64_t node_cap) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if ((int64_t)ds->n_nodes > node_cap || ds->n_nodes < 0) {
+      atomicOr(&ds->err, kErrNodes);
+      ds->n_nodes = 0;
+      ds->n_groups = 0;
+    }
+  }
+}
+
+// ---- node boxes and largest h: leaves reduce their particles, then push
+// the result up with atomic min/max; a push stops at the first ancestor
+// that already holds a value at least as extreme (whoever wrote that value
+// is carrying it further up).  Min/max are order independent, so the result
+// is exact and deterministic.
+__global__ __launch_bounds__(256) void k_node_init(unsigned long long* __restrict__ bb,
+                                                    unsigned long long* __restrict__ hm,
+                                                    const DevState* __restrict__ ds, int do_bb) {
+  const int nn = ds->n_nodes;
+  const unsigned long long lo = enc_f64(SPH_INF), hi = enc_f64(-SPH_INF), z = enc_f64(0.0);
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nn; k += gridDim.x * blockDim.x) {
+    if (do_bb) {
+      bb[6 * (int64_t)k + 0] = lo;
+      bb[6 * (int64_t)k + 1] = lo;
+      bb[6 * (int64_t)k + 2] = lo;
+      bb[6 * (int64_t)k + 3] = hi;
+      bb[6 * (int64_t)k + 4] = hi;
+      bb[6 * (int64_t)k + 5] = hi;
+    }
+    hm[k] = z;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_node_leaves(
+    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
+    const double* __restrict__ h, const int32_t* __restrict__ nfirst,
+    const int32_t* __restrict__ ncount, const int32_t* __restrict__ nparent,
+    const int32_t* __restrict__ nnchild, unsigned long long* __restrict__ bb,
+    unsigned long long* __restrict__ hm, const DevState* __restrict__ ds, int do_bb) {
+  const int nn = ds->n_nodes;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nn; k += gridDim.x * blockDim.x) {
+    if (nnchild[k] != 0) continue;
+    const int f = nfirst[k], e = f + ncount[k];
+    double lo0 = SPH_INF, lo1 = SPH_INF, lo2 = SPH_INF;
+    double hi0 = -SPH_INF, hi1 = -SPH_INF, hi2 = -SPH_INF, hmx = 0.0;
+    for (int s = f; s < e; ++s) {
+      if (do_bb) {
+        const double a = x[s], b = y[s], cc = z[s];
+        lo0 = fmin(lo0, a);
+        hi0 = fmax(hi0, a);
+        lo1 = fmin(lo1, b);
+        hi1 = fmax(hi1, b);
+        lo2 = fmin(lo2, cc);
+        hi2 = fmax(hi2, cc);
+      }
+      if (h) hmx = fmax(hmx, h[s]);
+    }
+    unsigned long long e6[6] = {enc_f64(lo0), enc_f64(lo1), enc_f64(lo2),
+                                enc_f64(hi0), enc_f64(hi1), enc_f64(hi2)};
+    const unsigned long long eh = enc_f64(hmx);
+    if (do_bb)
+      for (int q = 0; q < 6; ++q) bb[6 * (int64_t)k + q] = e6[q];
+    hm[k] = eh;
+    int p = nparent[k];
+    while (p >= 0 && p < nn) {
+      bool improved = false;
+      if (do_bb) {
+        for (int q = 0; q < 3; ++q) {
+          const unsigned long long old = atomicMin(&bb[6 * (int64_t)p + q], e6[q]);
+          improved |= e6[q] < old;
+        }
+        for (int q = 3; q < 6; ++q) {
+          const unsigned long long old = atomicMax(&bb[6 * (int64_t)p + q], e6[q]);
+          improved |= e6[q] > old;
+        }
+      }
+      if (h) {
+        const unsigned long long old = atomicMax(&hm[p], eh);
+        improved |= eh > old;
+      }
+      if (!improved) break;
+      p = nparent[p];
+    }
+  }
+}
+
+__device__ __forceinline__ float f32_up(double v) {
+  float f = (float)v;
+  if ((double)f < v) f = nextafterf(f, SPH_INF);
+  return f;
+}
+
+__global__ __launch_bounds__(256) void k_node_finalize(
+    const unsigned long long* __restrict__ bb, const unsigned long long* __restrict__ hm,
+    const int32_t* __restrict__ nfirst, const int32_t* __restrict__ ncount,
+    const int32_t* __restrict__ nchild, const int32_t* __restrict__ nnchild,
+    WalkNode* __restrict__ wn, const DevState* __restrict__ ds, int do_bb) {
+  const int nn = ds->n_nodes;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nn; k += gridDim.x * blockDim.x) {
+    WalkNode w = wn[k];
+    if (do_bb) {
+      for (int a = 0; a < 3; ++a) {
+        const double lo = dec_f64(bb[6 * (int64_t)k + a]);
+        const double hi = dec_f64(bb[6 * (int64_t)k + 3 + a]);
+        const double c = 0.5 * (lo + hi);
+        w.c[a] = c;
+        w.w[a] = f32_up(fmax(hi - c, c - lo));
+      }
+      w.first = nfirst[k];
+      w.count = ncount[k];
+      w.child = nnchild[k] ? nchild[k] : -1;
+      w.nchild = nnchild[k];
+    }
+    w.hmax = f32_up(dec_f64(hm[k]));
+    wn[k] = w;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_group_info(const double* __restrict__ x,
+                                                     const double* __restrict__ y,
+                                                     const double* __restrict__ z,
+                                                     const double* __restrict__ h,
+                                                     const int32_t* __restrict__ gfirst,
+                                                     const int32_t* __restrict__ gcount,
+                                                     GroupInfo* __restrict__ gi,
+                                                     const DevState* __restrict__ ds) {
+  const int ng = ds->n_groups;
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += gridDim.x * blockDim.x) {
+    const int f = gfirst[g], e = f + gcount[g];
+    double lo[3] = {SPH_INF, SPH_INF, SPH_INF}, hi[3] = {-SPH_INF, -SPH_INF, -SPH_INF};
+    double hmx = 0.0;
+    for (int s = f; s < e; ++s) {
+      const double c[3] = {x[s], y[s], z[s]};
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = fmin(lo[a], c[a]);
+        hi[a] = fmax(hi[a], c[a]);
+      }
+      hmx = fmax(hmx, h[s]);
+    }
+    GroupInfo G;
+    for (int a = 0; a < 3; ++a) {
+      G.c[a] = 0.5 * (lo[a] + hi[a]);
+      G.w[a] = fmax(hi[a] - G.c[a], G.c[a] - lo[a]);
+    }
+    G.hmax = hmx;
+    G.first = f;
+    G.count = e - f;
+    gi[g] = G;
+  }
+}
+
+// ============================================================================
+// Group tree walk (Sect. 3.2): one wavefront per group, breadth-first.  The
+// frontier lives in LDS; nodes are tested 64 at a time, opened inner nodes
+// push their (contiguous) children, opened leaves append (first, count) to an
+// LDS leaf list that is flushed through a candidate loop when it fills.
+// The opening test is conservative (a superset); the exact pair predicate is
+// applied in the candidate loop.
+// ============================================================================
+constexpr int kFCap = 512;  // frontier entries per level
+constexpr int kLCap = 128;  // leaves per flush
+constexpr int kPMax = 128;  // pairs per particle slot
+constexpr int kTile = 256;  // candidates staged in LDS at a time
+
+__device__ __forceinline__ double fold(double d, double len, double half, int periodic) {
+  if (periodic) {
+    if (d > half)
+      d -= len;
+    else if (d < -half)
+      d += len;
+  }
+  return d;
+}
+
+// min-image squared distance between a node box and the group box
+__device__ __forceinline__ double box_gap2(const WalkNode& nd, const GroupInfo& G,
+                                           const KParams& kp) {
+  double d2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double dc = nd.c[a] - G.c[a];
+    if (kp.periodic[a]) dc = dc - kp.len[a] * rint(dc * kp.inv_len[a]);
+    double gap = fabs(dc) - (double)nd.w[a] - G.w[a];
+    gap = gap > 0.0 ? gap : 0.0;
+    d2 = d2 + gap * gap;
+  }
+  return d2;
+}
+
+struct WalkLds {
+  int front[2][kFCap];
+  int lfirst[kLCap];
+  int lcnt[kLCap];
+  int loff[kLCap + 1];
+};
+
+// Candidate tile: positions and one more per-particle value (m_j for the
+// density, h_j for the force) of up to kTile candidates, and their indices.
+struct CandTile {
+  double x[kTile];
+  double y[kTile];
+  double z[kTile];
+  double a[kTile];
+  int j[kTile];
+};
+
+// Breadth-first walk.  open_r(node) returns the opening radius for a node;
+// flush(nleaf) consumes the leaf list (loff filled).  Returns false on
+// frontier overflow.
+template <typename RadiusFn, typename FlushFn>
+__device__ bool group_walk(const WalkNode* __restrict__ nodes, const GroupInfo& G,
+                           const KParams& kp, WalkLds& L, RadiusFn open_r, FlushFn flush) {
+  const int lane = threadIdx.x;
+  int nf = 1, cur = 0, nleaf = 0;
+  if (lane == 0) L.front[0][0] = 0;
+  __syncthreads();
+  bool ok = true;
+  while (nf > 0) {
+    int nn = 0;
+    for (int base = 0; base < nf; base += kWave) {
+      const int k = base + lane;
+      const bool act = k < nf;
+      WalkNode nd;
+      bool open = false;
+      if (act) {
+        nd = nodes[L.front[cur][k]];
+        const double R = open_r(nd);
+        open = box_gap2(nd, G, kp) < R * R;
+      }
+      const bool leaf = open && nd.nchild == 0;
+      const bool inner = open && nd.nchild > 0;
+      const uint64_t lb = ballot64(leaf);
+      const int nl = popc64(lb);
+      if (nleaf + nl > kLCap) {
+        flush(nleaf);
+        nleaf = 0;
+      }
+      if (leaf) {
+        const int pos = nleaf + popc64(lb & lanemask_lt());
+        L.lfirst[pos] = nd.first;
+        L.lcnt[pos] = nd.count;
+      }
+      nleaf += nl;
+      const uint32_t nc = inner ? (uint32_t)nd.nchild : 0u;
+      const uint32_t inc = wave_incl_scan_u32(nc);
+      const uint32_t tot = __shfl(inc, kWave - 1, kWave);
+      if (nn + (int)tot > kFCap) {
+        ok = false;
+      } else {
+        const int o = nn + (int)(inc - nc);
+        for (uint32_t q = 0; q < nc; ++q) L.front[cur ^ 1][o + q] = nd.child + (int)q;
+        nn += (int)tot;
+      }
+      __syncthreads();
+    }
+    if (!ok) break;
+    nf = nn;
+    cur ^= 1;
+  }
+  if (nleaf > 0) flush(nleaf);
+  return ok;
+}
+
+// Exclusive scan of the leaf counts into L.loff[0..nleaf].
+__device__ __forceinline__ int leaf_offsets(WalkLds& L, int nleaf) {
+  const int lane = threadIdx.x;
+  uint32_t carry = 0;
+  for (int base = 0; base < nleaf; base += kWave) {
+    const int k = base + lane;
+    const uint32_t v = (k < nleaf) ? (uint32_t)L.lcnt[k] : 0u;
+    const uint32_t inc = wave_incl_scan_u32(v);
+    if (k < nleaf) L.loff[k] = (int)(carry + inc - v);
+    carry += __shfl(inc, kWave - 1, kWave);
+  }
+  if (lane == 0) L.loff[nleaf] = (int)carry;
+  __syncthreads();
+  return (int)carry;
+}
+
+// Stage candidates [c0, c0+cnt) of the flushed leaves into the LDS tile.
+// Every lane resolves its candidates' particle indices first and then issues
+// all their loads before storing any, so a whole tile costs about one
+// memory latency instead of one per candidate step.
+__device__ __forceinline__ void stage_tile(const WalkLds& L, int nleaf, int c0, int cnt,
+                                           const double* __restrict__ px,
+                                           const double* __restrict__ py,
+                                           const double* __restrict__ pz,
+                                           const double* __restrict__ pa, CandTile& T) {
+  constexpr int PER = kTile / kWave;
+  const int lane = threadIdx.x;
+  int jj[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int t = lane + q * kWave;
+    jj[q] = -1;
+    if (t < cnt) {
+      const int c = c0 + t;
+      int lo = 0, hi = nleaf;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (L.loff[mid] <= c)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      jj[q] = L.lfirst[lo] + (c - L.loff[lo]);
+    }
+  }
+  double vx[PER], vy[PER], vz[PER], va[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = jj[q] >= 0 ? jj[q] : 0;
+    vx[q] = px[j];
+    vy[q] = py[j];
+    vz[q] = pz[j];
+    va[q] = pa[j];
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int t = lane + q * kWave;
+    if (jj[q] >= 0) {
+      T.x[t] = vx[q];
+      T.y[t] = vy[q];
+      T.z[t] = vz[q];
+      T.a[t] = va[q];
+      T.j[t] = jj[q];
+    }
+  }
+  __syncthreads();
+}
+
+// Candidate loop over the flushed leaves, one staged tile at a time: lane
+// `sub` of every slot visits tile entries sub, sub+LPI, ...;
+// body(valid, c) is called by all lanes with c the tile index.
+template <int LPI, typename Body>
+__device__ __forceinline__ void for_tiles(const WalkLds& L, int nleaf, int total, int sub,
+                                          const double* __restrict__ px,
+                                          const double* __restrict__ py,
+                                          const double* __restrict__ pz,
+                                          const double* __restrict__ pa, CandTile& T,
+                                          Body body) {
+  for (int c0 = 0; c0 < total; c0 += kTile) {
+    const int cnt = min(kTile, total - c0);
+    stage_tile(L, nleaf, c0, cnt, px, py, pz, pa, T);
+    for (int cb = 0; cb < cnt; cb += LPI) {
+      const int c = cb + sub;
+      body(c < cnt, c);
+    }
+    __syncthreads();
+  }
+}
+
+// ---- M4 cubic spline (3D, support 2h, 1/pi): f(q) and f'(q) -------------
+template <typename T>
+__device__ __forceinline__ void m4_f_df(T q, T& f, T& df) {
+  const T one = T(1), two = T(2);
+  const T t = two - q;
+  const T tp = t > T(0) ? t : T(0);
+  // inner branch (q < 1): 1 - 1.5 q^2 + 0.75 q^3 and -3q + 2.25 q^2
+  const T fi = one + q * q * (T(0.75) * q - T(1.5));
+  const T dfi = q * (T(2.25) * q - T(3));
+  // outer branch (1 <= q < 2): 0.25 (2-q)^3 and -0.75 (2-q)^2
+  const T fo = T(0.25) * tp * tp * tp;
+  const T dfo = T(-0.75) * tp * tp;
+  const bool in = q < one;
+  f = in ? fi : fo;
+  df = in ? dfi : dfo;
+}
+
+template <typename T>
+__device__ __forceinline__ T m4_df(T q) {
+  const T t = T(2) - q;
+  const T tp = t > T(0) ? t : T(0);
+  const T dfi = q * (T(2.25) * q - T(3));
+  const T dfo = T(-0.75) * tp * tp;
+  return q < T(1) ? dfi : dfo;
+}
+
+__device__ __forceinline__ float fast_sqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
+__device__ __forceinline__ float fast_rcp(float v) { return __builtin_amdgcn_rcpf(v); }
+
+// ============================================================================
+// Density: one wave per group (GS = 64/LPI particle slots of LPI lanes).
+// Pair lists (r, m_j) for r < 2 h_i * margin are built once by the walk and
+// kept in LDS while h is iterated; the walk is redone only if some h grows
+// past its list radius.  Newton-Raphson on f(h) = S0(h) - m (hfact/h)^3 with
+// a bracket; the group leaves the loop when a ballot shows every slot
+// converged, after one more sum at the converged h.
+// ============================================================================
+constexpr double kInvPi = 0.318309886183790671537767526745;
+
+template <bool MIXED, int LPI>
+__global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
+                                                const WalkNode* __restrict__ nodes,
+                                                const GroupInfo* __restrict__ groups,
+                                                void* __restrict__ frec_out,
+                                                DevState* __restrict__ ds) {
+  using R = typename std::conditional<MIXED, float, double>::type;
+  constexpr int GS = kWave / LPI;
+  __shared__ WalkLds L;
+  __shared__ CandTile T;
+  __shared__ R s_r[kPMax * GS];
+  __shared__ R s_m[kPMax * GS];
+
+  const int lane = threadIdx.x;
+  const int slot = lane / LPI, sub = lane % LPI;
+  const int ng = ds->n_groups;
+  const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, nloc = gridDim.x >> 3;
+  const int chunk = (ng + 7) >> 3;
+  const int gbeg = xcd * chunk, gend = min(gbeg + chunk, ng);
+  const double margin = kp.h_margin;
+  double minhalf = SPH_INF;
+  for (int a = 0; a < 3; ++a)
+    if (kp.periodic[a]) minhalf = fmin(minhalf, kp.half[a]);
+
+  uint32_t err = 0;
+  int it_max = 0;
+  unsigned long long pairs_final = 0, sums = 0, cands = 0;
+  int rewalks = 0;
+
+  for (int g = gbeg + local; g < gend; g += nloc) {
+    const GroupInfo G = groups[g];
+    const bool act = slot < G.count;
+    const int i = G.first + (act ? slot : 0);
+    const double xi = p.x[i], yi = p.y[i], zi = p.z[i], mi = p.m[i];
+    double h = p.h[i];
+    if (!(h > 0.0) || !isfinite(h)) {
+      err |= kErrNonFinite;
+      h = 1.0;
+    }
+    double hlim = h * margin;
+    double hlo = 0.0, hhi = SPH_INF;
+    bool conv = !act;
+    bool need = true;
+    int npair = 0;
+    int nit = 0;
+    double S0 = 0.0, S1 = 0.0;
+    uint32_t nnb = 0;
+    bool failed = false;
+    bool stream = false;  // group-wide: a pair list overflowed, sum on the fly instead
+    while (true) {
+      if (!stream && ballot64(act && need) != 0ull) {
+        // ---- walk and fill the pair lists (r < 2 hlim_i)
+        const double Rg = 2.0 * wave_max_f64(act ? hlim : 0.0) * (1.0 + 4e-9);
+        const double rl = 2.0 * hlim, rl2 = rl * rl;
+        npair = 0;
+        auto radius = [&](const WalkNode&) { return Rg; };
+        auto flush = [&](int nleaf) {
+          const int total = leaf_offsets(L, nleaf);
+          cands += (unsigned long long)total * ((act && sub == 0) ? 1u : 0u);
+          for_tiles<LPI>(L, nleaf, total, sub, p.x, p.y, p.z, p.m, T, [&](bool valid, int c) {
+            bool pred = false;
+            double r2 = 0.0;
+            double mj = 0.0;
+            if (valid && act) {
+              const double dx = fold(xi - T.x[c], kp.len[0], kp.half[0], kp.periodic[0]);
+              const double dy = fold(yi - T.y[c], kp.len[1], kp.half[1], kp.periodic[1]);
+              const double dz = fold(zi - T.z[c], kp.len[2], kp.half[2], kp.periodic[2]);
+              r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+              pred = r2 < rl2;
+              mj = T.a[c];
+            }
+            const uint64_t b = ballot64(pred);
+            const uint32_t seg = (uint32_t)((b >> (slot * LPI)) & ((LPI == 64) ? ~0ull : ((1ull << LPI) - 1ull)));
+            const int pos = npair + __popc(seg & ((1u << sub) - 1u));
+            if (pred && pos < kPMax) {
+              if constexpr (MIXED) {
+                s_r[pos * GS + slot] = fast_sqrt((float)r2);
+                s_m[pos * GS + slot] = (float)mj;
+              } else {
+                s_r[pos * GS + slot] = sqrt(r2);
+                s_m[pos * GS + slot] = mj;
+              }
+            }
+            npair += __popc(seg);
+          });
+          __syncthreads();
+        };
+        if (!group_walk(nodes, G, kp, L, radius, flush)) {
+          err |= kErrFrontier;
+          failed = true;
+        }
+        if (ballot64(failed) != 0ull) {
+          failed = true;
+          break;
+        }
+        if (ballot64(npair > kPMax) != 0ull) stream = true;
+        need = false;
+        ++rewalks;
+      }
+      // ---- one density sum at the current h
+      const double hinv = 1.0 / h;
+      double a0 = 0.0, a1 = 0.0;
+      uint32_t cnt = 0;
+      if (stream) {
+        // walk at the current h and accumulate the candidates directly
+        const double Rg = 2.0 * wave_max_f64(act ? h : 0.0) * (1.0 + 4e-9);
+        const double twoh = 2.0 * h, rl2 = twoh * twoh;
+        auto radius = [&](const WalkNode&) { return Rg; };
+        auto flush = [&](int nleaf) {
+          const int total = leaf_offsets(L, nleaf);
+          for_tiles<LPI>(L, nleaf, total, sub, p.x, p.y, p.z, p.m, T, [&](bool valid, int c) {
+            if (valid && act) {
+              const double dx = fold(xi - T.x[c], kp.len[0], kp.half[0], kp.periodic[0]);
+              const double dy = fold(yi - T.y[c], kp.len[1], kp.half[1], kp.periodic[1]);
+              const double dz = fold(zi - T.z[c], kp.len[2], kp.half[2], kp.periodic[2]);
+              const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+              if (r2 < rl2) {
+                const double mj = T.a[c];
+                if constexpr (MIXED) {
+                  const float m = (float)mj;
+                  const float q = fast_sqrt((float)r2) * (float)hinv;
+                  float f, df;
+                  m4_f_df<float>(q, f, df);
+                  a0 += (double)(m * f);
+                  a1 += (double)(m * (3.0f * f + q * df));
+                } else {
+                  const double q = sqrt(r2) * hinv;
+                  double f, df;
+                  m4_f_df<double>(q, f, df);
+                  a0 += mj * f;
+                  a1 += mj * (3.0 * f + q * df);
+                }
+                ++cnt;
+              }
+            }
+          });
+          __syncthreads();
+        };
+        if (!group_walk(nodes, G, kp, L, radius, flush)) {
+          err |= kErrFrontier;
+          failed = true;
+        }
+        if (ballot64(failed) != 0ull) {
+          failed = true;
+          break;
+        }
+        ++rewalks;
+      } else if (MIXED) {
+        const float hinvf = (float)hinv;
+        const float twohf = (float)(2.0 * h);
+        for (int k = sub; k < npair; k += LPI) {
+          const float r = (float)s_r[k * GS + slot], m = (float)s_m[k * GS + slot];
+          const float q = r * hinvf;
+          float f, df;
+          m4_f_df<float>(q, f, df);
+          a0 += (double)(m * f);
+          a1 += (double)(m * (3.0f * f + q * df));
+          cnt += (r < twohf) ? 1u : 0u;
+        }
+      } else {
+        const double twoh = 2.0 * h;
+        for (int k = sub; k < npair; k += LPI) {
+          const double r = (double)s_r[k * GS + slot], m = (double)s_m[k * GS + slot];
+          const double q = r * hinv;
+          double f, df;
+          m4_f_df<double>(q, f, df);
+          a0 += m * f;
+          a1 += m * (3.0 * f + q * df);
+          cnt += (r < twoh) ? 1u : 0u;
+        }
+      }
+      a0 = seg_sum<LPI>(a0);
+      a1 = seg_sum<LPI>(a1);
+      cnt = seg_sum_u32<LPI>(cnt);
+      const double h3 = hinv * hinv * hinv;
+      S0 = a0 * h3 * kInvPi;
+      S1 = -a1 * h3 * hinv * kInvPi;
+      nnb = cnt;
+      sums += (act && sub == 0) ? (unsigned long long)(stream ? cnt : (uint32_t)npair) : 0ull;
+      if (ballot64(!conv) == 0ull) break;  // this was the sum at the converged h
+      if (!conv) {
+        const double t = kp.hfact * hinv;
+        const double rh = mi * (t * t * t);
+        const double f = S0 - rh;
+        const double fp = S1 + 3.0 * rh * hinv;
+        double hn;
+        if (kp.fixed_passes) {
+          hn = h - f / fp;
+          if (!(fp > 0.0))
+            hn = h;
+          else if (hn > 1.2 * h)
+            hn = 1.2 * h;
+          else if (hn < 0.8 * h)
+            hn = 0.8 * h;
+          conv = (nit + 1) >= 3;
+        } else {
+          if (f < 0.0)
+            hlo = fmax(hlo, h);
+          else
+            hhi = fmin(hhi, h);
+          hn = h - f / fp;
+          // a step below the tolerance is accepted as it is (it may sit on
+          // the bracket end the current h just became)
+          const bool small = (fp > 0.0) && fabs(hn - h) <= kp.h_tol * h;
+          const bool bad = !small && (!(fp > 0.0) || !(hn >= 0.8 * h) || !(hn <= 1.2 * h) ||
+                                      !(hn > hlo) || !(hn < hhi));
+          if (bad) {
+            if (hlo > 0.0 && hhi < SPH_INF)
+              hn = 0.5 * (hlo + hhi);
+            else
+              hn = (f < 0.0) ? 1.2 * h : h / 1.2;
+          }
+          conv = small || fabs(hn - h) <= kp.h_tol * h || f == 0.0;
+          if (f == 0.0) hn = h;
+        }
+        h = hn;
+        if (h > hlim) {
+          hlim = h * margin;
+          need = true;
+        }
+        ++nit;
+        if (nit > kp.max_iter) {
+          err |= kErrNoConv;
+          conv = true;
+        }
+      }
+    }
+    it_max = max(it_max, nit + 1);
+    if (act && !failed) {
+      const double rho = S0;
+      const double omega = 1.0 + h * S1 / (3.0 * rho);
+      const double u = p.u[i];
+      const double P = kp.gm1 * rho * u;
+      const double cs = sqrt(kp.gamma * kp.gm1 * u);
+      if (!(isfinite(rho) && isfinite(omega) && isfinite(P) && isfinite(cs))) err |= kErrNonFinite;
+      if (2.0 * h >= minhalf) err |= kErrDomain;
+      if (sub == 0) {
+        p.h[i] = h;
+        p.rho[i] = rho;
+        p.omega[i] = omega;
+        p.P[i] = P;
+        p.cs[i] = cs;
+        const double hinv = 1.0 / h;
+        const double g = P / (rho * rho * omega);
+        const double kk = 1.0 / (rho * omega);
+        const double hinv4pi = hinv * hinv * hinv * hinv * kInvPi;
+        if constexpr (MIXED) {
+          FRec32 r;
+          r.x = xi;
+          r.y = yi;
+          r.z = zi;
+          r.m = (float)mi;
+          r.pad0 = 0.f;
+          r.vx = (float)p.vx[i];
+          r.vy = (float)p.vy[i];
+          r.vz = (float)p.vz[i];
+          r.u = (float)u;
+          r.hinv = (float)hinv;
+          r.hinv4pi = (float)hinv4pi;
+          r.g = (float)g;
+          r.k = (float)kk;
+          r.c = (float)cs;
+          r.P = (float)P;
+          r.rho = (float)rho;
+          r.pad1 = 0.f;
+          reinterpret_cast<FRec32*>(frec_out)[i] = r;
+        } else {
+          FRec64 r;
+          r.x = xi;
+          r.y = yi;
+          r.z = zi;
+          r.m = mi;
+          r.vx = p.vx[i];
+          r.vy = p.vy[i];
+          r.vz = p.vz[i];
+          r.u = u;
+          r.hinv = hinv;
+          r.hinv4pi = hinv4pi;
+          r.g = g;
+          r.k = kk;
+          r.c = cs;
+          r.P = P;
+          r.rho = rho;
+          r.pad = 0.0;
+          reinterpret_cast<FRec64*>(frec_out)[i] = r;
+        }
+        pairs_final += nnb;
+      }
+    }
+  }
+  // one set of atomics per wave
+  const uint64_t b = ballot64(err != 0);
+  uint32_t eall = err;
+  for (int d = 32; d > 0; d >>= 1) eall |= __shfl_xor(eall, d, kWave);
+  unsigned long long pf = pairs_final;
+  for (int d = 32; d > 0; d >>= 1) pf += __shfl_xor(pf, d, kWave);
+  unsigned long long cd = cands, sm = sums;
+  for (int d = 32; d > 0; d >>= 1) {
+    cd += __shfl_xor(cd, d, kWave);
+    sm += __shfl_xor(sm, d, kWave);
+  }
+  sums = sm;
+  if (lane == 0) {
+    if (b) atomicOr(&ds->err, eall);
+    atomicMax(&ds->max_iter, it_max);
+    atomicAdd(&ds->n_pairs_density, pf);
+    atomicAdd(&ds->n_sums_density, sums);
+    atomicAdd(&ds->n_cand_density, cd);
+    atomicAdd(&ds->n_rewalk, rewalks);
+  }
+}
+
+// ============================================================================
+// Force: one wave per group.  The walk opens a node if the group box comes
+// within 2 max(h_max,group, h_max,node) of it; candidates j != i with
+// r < 2 max(h_i, h_j) go to a per-slot LDS list of indices; the pair loop
+// then reads each neighbour's record.
+// ============================================================================
+template <bool MIXED>
+struct FRecOf {
+  using T = FRec64;
+};
+template <>
+struct FRecOf<true> {
+  using T = FRec32;
+};
+
+template <bool MIXED, int LPI>
+__global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
+                                              const WalkNode* __restrict__ nodes,
+                                              const GroupInfo* __restrict__ groups,
+                                              const void* __restrict__ frec_in,
+                                              double* __restrict__ out_ax,
+                                              double* __restrict__ out_ay,
+                                              double* __restrict__ out_az,
+                                              double* __restrict__ out_du,
+                                              DevState* __restrict__ ds) {
+  using Rec = typename FRecOf<MIXED>::T;
+  constexpr int GS = kWave / LPI;
+  __shared__ WalkLds L;
+  __shared__ CandTile T;
+  __shared__ int s_j[kPMax * GS];
+  const Rec* __restrict__ rec = reinterpret_cast<const Rec*>(frec_in);
+
+  const int lane = threadIdx.x;
+  const int slot = lane / LPI, sub = lane % LPI;
+  const int ng = ds->n_groups;
+  const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, nloc = gridDim.x >> 3;
+  const int chunk = (ng + 7) >> 3;
+  const int gbeg = xcd * chunk, gend = min(gbeg + chunk, ng);
+  uint32_t err = 0;
+  unsigned long long pairs = 0, cands = 0;
+  double dtmin = SPH_INF;
+
+  for (int g = gbeg + local; g < gend; g += nloc) {
+    const GroupInfo G = groups[g];
+    const bool act = slot < G.count;
+    const int i = G.first + (act ? slot : 0);
+    const double xi = p.x[i], yi = p.y[i], zi = p.z[i], hi = p.h[i];
+    const Rec ri = rec[i];
+    double ax = 0.0, ay = 0.0, az = 0.0, du = 0.0, vmax = 0.0;
+    int npair = 0;
+    // ---- pair loop over the pending list entries of each slot
+    auto compute = [&]() {
+      if constexpr (MIXED) {
+        const float al = (float)kp.alpha, be = (float)kp.beta, au = (float)kp.alpha_u;
+        const float vxi = ri.vx, vyi = ri.vy, vzi = ri.vz;
+        const float hinvi = ri.hinv, h4i = ri.hinv4pi, gi = ri.g, ki = ri.k, ci = ri.c;
+        const float Pi = ri.P, rhoi = ri.rho, ui = ri.u;
+        auto pair = [&](const Rec& rj) {
+          const float dx = (float)fold(xi - rj.x, kp.len[0], kp.half[0], kp.periodic[0]);
+          const float dy = (float)fold(yi - rj.y, kp.len[1], kp.half[1], kp.periodic[1]);
+          const float dz = (float)fold(zi - rj.z, kp.len[2], kp.half[2], kp.periodic[2]);
+          const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+          const float rinv = __builtin_amdgcn_rsqf(r2);
+          const float r = r2 * rinv;
+          const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
+          const float w = fmaf(vzi - rj.vz, ez, fmaf(vyi - rj.vy, ey, (vxi - rj.vx) * ex));
+          const float Fi = m4_df<float>(r * hinvi) * h4i;
+          const float Fj = m4_df<float>(r * rj.hinv) * rj.hinv4pi;
+          const float aw = fabsf(w);
+          const bool app = w < 0.0f;
+          const float vsi = fmaf(be, aw, al * ci);
+          const float vsj = fmaf(be, aw, al * rj.c);
+          const float ti = app ? fmaf(-0.5f * vsi * w, ki, gi) : gi;
+          const float tj = app ? fmaf(-0.5f * vsj * w, rj.k, rj.g) : rj.g;
+          const float pa = rj.m * fmaf(ti, Fi, tj * Fj);
+          ax -= (double)(pa * ex);
+          ay -= (double)(pa * ey);
+          az -= (double)(pa * ez);
+          const float mwF = rj.m * w * Fi;
+          float e = gi * mwF;
+          if (app) e = fmaf(-0.5f * ki * vsi * w, mwF, e);
+          const float dP = fabsf(Pi - rj.P);
+          const float vu = fast_sqrt(dP * fast_rcp(0.5f * (rhoi + rj.rho)));
+          e = fmaf(rj.m * au * vu * (ui - rj.u), 0.5f * fmaf(Fi, ki, Fj * rj.k), e);
+          du += (double)e;
+          vmax = fmax(vmax, (double)vsi);
+        };
+        for (int k = sub; k < npair; k += 2 * LPI) {
+          const int k2 = k + LPI;
+          const bool two = k2 < npair;
+          const int j1 = s_j[k * GS + slot];
+          const int j2 = two ? s_j[k2 * GS + slot] : j1;
+          const Rec r1 = rec[j1];
+          const Rec r2 = rec[j2];
+          pair(r1);
+          if (two) pair(r2);
+        }
+      } else {
+        const double al = kp.alpha, be = kp.beta, au = kp.alpha_u;
+        const double vxi = ri.vx, vyi = ri.vy, vzi = ri.vz;
+        const double hinvi = ri.hinv, h4i = ri.hinv4pi, gi = ri.g, ki = ri.k, ci = ri.c;
+        const double Pi = ri.P, rhoi = ri.rho, ui = ri.u;
+        auto pair = [&](const Rec& rj) {
+          const double dx = fold(xi - rj.x, kp.len[0], kp.half[0], kp.periodic[0]);
+          const double dy = fold(yi - rj.y, kp.len[1], kp.half[1], kp.periodic[1]);
+          const double dz = fold(zi - rj.z, kp.len[2], kp.half[2], kp.periodic[2]);
+          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+          const double r = sqrt(r2);
+          const double rinv = 1.0 / r;
+          const double ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
+          const double w = fma(vzi - rj.vz, ez, fma(vyi - rj.vy, ey, (vxi - rj.vx) * ex));
+          const double Fi = m4_df<double>(r * hinvi) * h4i;
+          const double Fj = m4_df<double>(r * rj.hinv) * rj.hinv4pi;
+          const double aw = fabs(w);
+          const bool app = w < 0.0;
+          const double vsi = fma(be, aw, al * ci);
+          const double vsj = fma(be, aw, al * rj.c);
+          const double ti = app ? fma(-0.5 * vsi * w, ki, gi) : gi;
+          const double tj = app ? fma(-0.5 * vsj * w, rj.k, rj.g) : rj.g;
+          const double pa = rj.m * fma(ti, Fi, tj * Fj);
+          ax -= pa * ex;
+          ay -= pa * ey;
+          az -= pa * ez;
+          const double mwF = rj.m * w * Fi;
+          double e = gi * mwF;
+          if (app) e = fma(-0.5 * ki * vsi * w, mwF, e);
+          const double vu = sqrt(fabs(Pi - rj.P) / (0.5 * (rhoi + rj.rho)));
+          e = fma(rj.m * au * vu * (ui - rj.u), 0.5 * fma(Fi, ki, Fj * rj.k), e);
+          du += e;
+          vmax = fmax(vmax, vsi);
+        };
+        for (int k = sub; k < npair; k += 2 * LPI) {
+          const int k2 = k + LPI;
+          const bool two = k2 < npair;
+          const int j1 = s_j[k * GS + slot];
+          const int j2 = two ? s_j[k2 * GS + slot] : j1;
+          const Rec r1 = rec[j1];
+          const Rec r2 = rec[j2];
+          pair(r1);
+          if (two) pair(r2);
+        }
+      }
+      pairs += (act && sub == 0) ? (unsigned long long)npair : 0ull;
+      npair = 0;
+    };
+    const double hg = G.hmax;
+    auto radius = [&](const WalkNode& nd) {
+      return 2.0 * fmax(hg, (double)nd.hmax) * (1.0 + 4e-9);
+    };
+    auto flush = [&](int nleaf) {
+      const int total = leaf_offsets(L, nleaf);
+      cands += (unsigned long long)total * ((act && sub == 0) ? 1u : 0u);
+      for_tiles<LPI>(L, nleaf, total, sub, p.x, p.y, p.z, p.h, T, [&](bool valid, int c) {
+        // one candidate step adds at most LPI entries per slot: empty the
+        // lists through the pair loop before they can overflow
+        if (ballot64(npair > kPMax - LPI) != 0ull) {
+          __syncthreads();
+          compute();
+          __syncthreads();
+        }
+        bool pred = false;
+        const int j = valid ? T.j[c] : -1;
+        if (valid && act && j != i) {
+          const double dx = fold(xi - T.x[c], kp.len[0], kp.half[0], kp.periodic[0]);
+          const double dy = fold(yi - T.y[c], kp.len[1], kp.half[1], kp.periodic[1]);
+          const double dz = fold(zi - T.z[c], kp.len[2], kp.half[2], kp.periodic[2]);
+          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+          const double hj = T.a[c];
+          const double sr = 2.0 * (hi > hj ? hi : hj);
+          pred = r2 < sr * sr;
+        }
+        const uint64_t b = ballot64(pred);
+        const uint32_t seg = (uint32_t)((b >> (slot * LPI)) & ((LPI == 64) ? ~0ull : ((1ull << LPI) - 1ull)));
+        const int pos = npair + __popc(seg & ((1u << sub) - 1u));
+        if (pred) s_j[pos * GS + slot] = j;
+        npair += __popc(seg);
+      });
+      __syncthreads();
+    };
+    if (!group_walk(nodes, G, kp, L, radius, flush)) err |= kErrFrontier;
+    __syncthreads();
+    compute();
+    ax = seg_sum<LPI>(ax);
+    ay = seg_sum<LPI>(ay);
+    az = seg_sum<LPI>(az);
+    du = seg_sum<LPI>(du);
+    vmax = seg_max<LPI>(vmax);
+    if (act) {
+      const double v0 = (kp.alpha == 0.0) ? (double)ri.c : kp.alpha * (double)ri.c;
+      const double vs = fmax(vmax, v0);
+      if (!(isfinite(ax) && isfinite(ay) && isfinite(az) && isfinite(du))) err |= kErrNonFinite;
+      if (sub == 0) {
+        out_ax[i] = ax;
+        out_ay[i] = ay;
+        out_az[i] = az;
+        out_du[i] = du;
+        p.vsig[i] = vs;
+      }
+      dtmin = fmin(dtmin, kp.c_cour * hi / vs);
+    }
+  }
+  const uint64_t b = ballot64(err != 0);
+  uint32_t eall = err;
+  for (int d = 32; d > 0; d >>= 1) eall |= __shfl_xor(eall, d, kWave);
+  unsigned long long pf = pairs, cd = cands;
+  for (int d = 32; d > 0; d >>= 1) {
+    pf += __shfl_xor(pf, d, kWave);
+    cd += __shfl_xor(cd, d, kWave);
+  }
+  const double dm = wave_min_f64(dtmin);
+  if (lane == 0) {
+    if (b) atomicOr(&ds->err, eall);
+    atomicAdd(&ds->n_pairs_force, pf);
+    atomicAdd(&ds->n_cand_force, cd);
+    if (dm < SPH_INF) atomicMin(&ds->dt_min_enc, enc_f64(dm));
+  }
+}
+
+// ============================================================================
+// Neighbour sets for inspection: the same walk, the exact FP64 predicates,
+// counts (idx == nullptr) or indices written at offsets[i].
+// ============================================================================
+template <int LPI>
+__global__ __launch_bounds__(64) void k_neighbours(KParams kp, Parts p, int mode,
+                                                   const WalkNode* __restrict__ nodes,
+                                                   const GroupInfo* __restrict__ groups,
+                                                   int32_t* __restrict__ counts,
+                                                   const int64_t* __restrict__ offsets,
+                                                   int32_t* __restrict__ idx,
+                                                   DevState* __restrict__ ds) {
+  __shared__ WalkLds L;
+  __shared__ CandTile T;
+  const int lane = threadIdx.x;
+  const int slot = lane / LPI, sub = lane % LPI;
+  const int ng = ds->n_groups;
+  uint32_t err = 0;
+  for (int g = blockIdx.x; g < ng; g += gridDim.x) {
+    const GroupInfo G = groups[g];
+    const bool act = slot < G.count;
+    const int i = G.first + (act ? slot : 0);
+    const double xi = p.x[i], yi = p.y[i], zi = p.z[i], hi = p.h[i];
+    int cnt = 0;
+    const double hg = G.hmax;
+    auto radius = [&](const WalkNode& nd) {
+      return 2.0 * (mode == 1 ? fmax(hg, (double)nd.hmax) : hg) * (1.0 + 4e-9);
+    };
+    auto flush = [&](int nleaf) {
+      const int total = leaf_offsets(L, nleaf);
+      for_tiles<LPI>(L, nleaf, total, sub, p.x, p.y, p.z, p.h, T, [&](bool valid, int c) {
+        bool pred = false;
+        const int j = valid ? T.j[c] : -1;
+        if (valid && act) {
+          const double dx = fold(xi - T.x[c], kp.len[0], kp.half[0], kp.periodic[0]);
+          const double dy = fold(yi - T.y[c], kp.len[1], kp.half[1], kp.periodic[1]);
+          const double dz = fold(zi - T.z[c], kp.len[2], kp.half[2], kp.periodic[2]);
+          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+          if (mode == 0) {
+            const double s = 2.0 * hi;
+            pred = r2 < s * s;
+          } else {
+            const double hj = T.a[c];
+            const double s = 2.0 * (hi > hj ? hi : hj);
+            pred = (j != i) && r2 < s * s;
+          }
+        }
+        const uint64_t b = ballot64(pred);
+        const uint32_t seg = (uint32_t)((b >> (slot * LPI)) & ((LPI == 64) ? ~0ull : ((1ull << LPI) - 1ull)));
+        const int pos = cnt + __popc(seg & ((1u << sub) - 1u));
+        if (pred && idx) idx[offsets[i] + pos] = j;
+        cnt += __popc(seg);
+      });
+      __syncthreads();
+    };
+    if (!group_walk(nodes, G, kp, L, radius, flush)) err |= kErrFrontier;
+    if (act && sub == 0 && !idx) counts[i] = cnt;
+  }
+  if (err) atomicOr(&ds->err, err);
+}
+
+// ============================================================================
+// Integration and reductions (one thread per particle)
+// ============================================================================
+__global__ void k_set_dt(DevState* ds, double dt_host) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ds->dt_cur = (dt_host > 0.0) ? dt_host : dec_f64(ds->dt_min_enc);
+  }
+}
+
+__global__ void k_reset_force_state(DevState* ds) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ds->dt_min_enc = enc_f64(SPH_INF);
+}
+
+__global__ void k_reset_counters(DevState* ds) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ds->max_iter = 0;
+    ds->n_pairs_density = 0;
+    ds->n_pairs_force = 0;
+    ds->n_sums_density = 0;
+    ds->n_cand_density = 0;
+    ds->n_cand_force = 0;
+    ds->n_rewalk = 0;
+  }
+}
+
+// v1 = v_p + (a1 - a0) dt/2, u1 = u_p + (du1 - du0) dt/2; a0 <- a1.
+__global__ __launch_bounds__(256) void k_correct(Parts p, int n, const double* __restrict__ a1,
+                                                  int64_t stride, const DevState* __restrict__ ds) {
+  const double hdt = 0.5 * ds->dt_cur;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double nax = a1[i], nay = a1[stride + i], naz = a1[2 * stride + i],
+                 ndu = a1[3 * stride + i];
+    p.vx[i] = p.vx[i] + (nax - p.ax[i]) * hdt;
+    p.vy[i] = p.vy[i] + (nay - p.ay[i]) * hdt;
+    p.vz[i] = p.vz[i] + (naz - p.az[i]) * hdt;
+    p.u[i] = p.u[i] + (ndu - p.dudt[i]) * hdt;
+    p.ax[i] = nax;
+    p.ay[i] = nay;
+    p.az[i] = naz;
+    p.dudt[i] = ndu;
+  }
+}
+
+constexpr int kRedBlocks = 512;
+
+// Fixed-order FP64 sums: thread t of block b owns particles b*256+t + k*stride.
+__global__ __launch_bounds__(256) void k_reduce_part(Parts p, int n, double* __restrict__ part) {
+  __shared__ double s[12][256];
+  double acc[12];
+  for (int q = 0; q < 12; ++q) acc[q] = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += kRedBlocks * 256) {
+    const double m = p.m[i], vx = p.vx[i], vy = p.vy[i], vz = p.vz[i];
+    const double ax = p.ax[i], ay = p.ay[i], az = p.az[i], du = p.dudt[i], u = p.u[i];
+    const double v2 = vx * vx + vy * vy + vz * vz;
+    const double va = vx * ax + vy * ay + vz * az;
+    acc[1] += 0.5 * m * v2;
+    acc[2] += m * u;
+    acc[3] += m * vx;
+    acc[4] += m * vy;
+    acc[5] += m * vz;
+    acc[6] += m * ax;
+    acc[7] += m * ay;
+    acc[8] += m * az;
+    acc[9] += m * (va + du);
+    acc[10] += m * sqrt(ax * ax + ay * ay + az * az);
+    acc[11] += m * (fabs(va) + fabs(du));
+  }
+  for (int q = 0; q < 12; ++q) s[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int q = 0; q < 12; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 12) part[blockIdx.x * 12 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ void k_reduce_final(const double* __restrict__ part, double* __restrict__ out) {
+  if (threadIdx.x < 12) {
+    double a = 0.0;
+    for (int b = 0; b < kRedBlocks; ++b) a += part[b * 12 + threadIdx.x];
+    out[threadIdx.x] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = out[1] + out[2];
+}
+
+// ============================================================================
+// Host-side launchers
+// ============================================================================
+static Parts parts_of(const sph_particles* s) {
+  Parts p;
+  p.id = s->id;
+  p.x = s->x;
+  p.y = s->y;
+  p.z = s->z;
+  p.vx = s->vx;
+  p.vy = s->vy;
+  p.vz = s->vz;
+  p.m = s->m;
+  p.u = s->u;
+  p.h = s->h;
+  p.ax = s->ax;
+  p.ay = s->ay;
+  p.az = s->az;
+  p.dudt = s->dudt;
+  p.rho = s->rho;
+  p.omega = s->omega;
+  p.P = s->P;
+  p.cs = s->cs;
+  p.vsig = s->vsig_dt;
+  return p;
+}
+
+static int stream_blocks(int n) {
+  int b = (n + 255) / 256;
+  return b < 1 ? 1 : (b > 8192 ? 8192 : b);
+}
+
+hipError_t launch_set_dt(sph_ctx* c, double dt_host) {
+  hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(64), 0, c->stream, c->ds, dt_host);
+  return hipGetLastError();
+}
+
+hipError_t launch_predict_keys(sph_ctx* c, const sph_particles* s, bool predict, double) {
+  c->kp.n = c->n;
+  hipLaunchKernelGGL(k_predict_keys, dim3(stream_blocks(c->n)), dim3(256), 0, c->stream, c->kp,
+                     parts_of(s), predict ? 1 : 0, c->ds, c->keys[0], c->vals[0], &c->ds->err);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort(sph_ctx* c) {
+  const int n = c->n;
+  const int nblk = (n + kSortTile - 1) / kSortTile;
+  for (int pass = 0; pass < 8; ++pass) {
+    const int shift = 8 * pass;
+    const int src = pass & 1, dst = src ^ 1;
+    hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(256), 0, c->stream, c->keys[src], n, shift,
+                       c->radix_cnt, nblk);
+    hipError_t e = scan_u32(c, c->radix_cnt, (int64_t)256 * nblk, c->scan_total, nullptr);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(256), 0, c->stream, c->keys[src],
+                       c->vals[src], c->keys[dst], c->vals[dst], n, shift, c->radix_cnt, nblk);
+  }
+  return hipGetLastError();  // 8 passes: the result is back in buffer 0
+}
+
+hipError_t launch_permute(sph_ctx* c, const sph_particles* s, bool outputs_too) {
+  FieldSet fs;
+  fs.nf = 0;
+  double* all[] = {s->x,  s->y,  s->z,    s->vx,  s->vy,   s->vz, s->m,  s->u,     s->h,
+                   s->ax, s->ay, s->az,   s->dudt, s->rho, s->omega, s->P, s->cs, s->vsig_dt};
+  const int n_in = 13;  // x..dudt are state; the rest are outputs
+  for (int k = 0; k < (int)(sizeof(all) / sizeof(all[0])); ++k) {
+    if (!all[k]) continue;
+    if (k >= n_in && !outputs_too) continue;
+    fs.f[fs.nf++] = all[k];
+  }
+  fs.id = s->id;
+  const int nb = stream_blocks(c->n);
+  hipLaunchKernelGGL(k_gather, dim3(nb), dim3(256), 0, c->stream, fs, c->vals[0], c->gtmp,
+                     c->gtmp_id, c->n, (int64_t)c->n_max);
+  hipLaunchKernelGGL(k_copy_back, dim3(nb), dim3(256), 0, c->stream, fs, c->gtmp, c->gtmp_id,
+                     c->n, (int64_t)c->n_max);
+  return hipGetLastError();
+}
+
+hipError_t launch_tree(sph_ctx* c) {
+  const int n = c->n;
+  const int nblk = (n + kTreeTile - 1) / kTreeTile;
+  hipLaunchKernelGGL(k_tree_levels, dim3(nblk), dim3(256), 0, c->stream, c->keys[0], n,
+                     c->kp.n_leaf, c->kp.n_group, c->dlev, c->lleaf, c->lgrp, c->gstart,
+                     c->tree_cnt, c->grp_cnt, nblk);
+  hipError_t e = scan_u32(c, c->tree_cnt, (int64_t)kLevels * nblk, nullptr, &c->ds->n_nodes);
+  if (e != hipSuccess) return e;
+  e = scan_u32(c, c->grp_cnt, nblk, nullptr, &c->ds->n_groups);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zero_i32, dim3(1024), dim3(256), 0, c->stream, c->node_nchild,
+                     &c->ds->n_nodes, c->node_cap);
+  hipLaunchKernelGGL(k_tree_emit, dim3(nblk), dim3(256), 0, c->stream, c->keys[0], n,
+                     c->kp.n_group, c->dlev, c->lleaf, c->lgrp, c->gstart, c->tree_cnt,
+                     c->grp_cnt, nblk, c->node_cap, c->node_level, c->node_first,
+                     c->node_count, c->node_parent, c->node_child, c->node_nchild,
+                     c->grp_first, c->grp_count, c->ds);
+  hipLaunchKernelGGL(k_tree_guard, dim3(1), dim3(64), 0, c->stream, c->ds, c->node_cap);
+  return hipGetLastError();
+}
+
+// Node boxes (positions) and largest h; group boxes.  The positions are the
+// current (sorted) ones; h may be the start value or the converged one.
+static hipError_t node_props(sph_ctx* c, const sph_particles* s, bool do_bb) {
+  const int nb = 2048;
+  hipLaunchKernelGGL(k_node_init, dim3(nb), dim3(256), 0, c->stream, c->node_bb, c->node_hm,
+                     c->ds, do_bb ? 1 : 0);
+  hipLaunchKernelGGL(k_node_leaves, dim3(nb), dim3(256), 0, c->stream, s->x, s->y, s->z, s->h,
+                     c->node_first, c->node_count, c->node_parent, c->node_nchild, c->node_bb,
+                     c->node_hm, c->ds, do_bb ? 1 : 0);
+  hipLaunchKernelGGL(k_node_finalize, dim3(nb), dim3(256), 0, c->stream, c->node_bb, c->node_hm,
+                     c->node_first, c->node_count, c->node_child, c->node_nchild, c->wnode,
+                     c->ds, do_bb ? 1 : 0);
+  hipLaunchKernelGGL(k_group_info, dim3(nb), dim3(256), 0, c->stream, s->x, s->y, s->z, s->h,
+                     c->grp_first, c->grp_count, c->ginfo, c->ds);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_h(sph_ctx* c, const sph_particles* s) { return node_props(c, s, false); }
+hipError_t launch_node_boxes(sph_ctx* c, const sph_particles* s) { return node_props(c, s, true); }
+
+template <bool MIXED>
+static hipError_t density_dispatch(sph_ctx* c, const sph_particles* s) {
+  const Parts p = parts_of(s);
+  const dim3 grid(c->walk_blocks), block(64);
+  switch (c->kp.n_group) {
+    case 4:
+      hipLaunchKernelGGL((k_density<MIXED, 16>), grid, block, 0, c->stream, c->kp, p, c->wnode,
+                         c->ginfo, c->frec, c->ds);
+      break;
+    case 8:
+      hipLaunchKernelGGL((k_density<MIXED, 8>), grid, block, 0, c->stream, c->kp, p, c->wnode,
+                         c->ginfo, c->frec, c->ds);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_density<MIXED, 4>), grid, block, 0, c->stream, c->kp, p, c->wnode,
+                         c->ginfo, c->frec, c->ds);
+      break;
+    default:
+      hipLaunchKernelGGL((k_density<MIXED, 2>), grid, block, 0, c->stream, c->kp, p, c->wnode,
+                         c->ginfo, c->frec, c->ds);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_density(sph_ctx* c, const sph_particles* s) {
+  c->kp.n = c->n;
+  return c->kp.precision == SPH_PREC_MIXED ? density_dispatch<true>(c, s)
+                                           : density_dispatch<false>(c, s);
+}
+
+template <bool MIXED>
+static hipError_t force_dispatch(sph_ctx* c, const sph_particles* s, double* oax, double* oay,
+                                 double* oaz, double* odu) {
+  const Parts p = parts_of(s);
+  const dim3 grid(c->walk_blocks), block(64);
+  switch (c->kp.n_group) {
+    case 4:
+      hipLaunchKernelGGL((k_force<MIXED, 16>), grid, block, 0, c->stream, c->kp, p, c->wnode,
+                         c->ginfo, c->frec, oax, oay, oaz, odu, c->ds);
+      break;
+    case 8:
+      hipLaunchKernelGGL((k_force<MIXED, 8>), grid, block, 0, c->stream, c->kp, p, c->wnode,
+                         c->ginfo, c->frec, oax, oay, oaz, odu, c->ds);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_force<MIXED, 4>), grid, block, 0, c->stream, c->kp, p, c->wnode,
+                         c->ginfo, c->frec, oax, oay, oaz, odu, c->ds);
+      break;
+    default:
+      hipLaunchKernelGGL((k_force<MIXED, 2>), grid, block, 0, c->stream, c->kp, p, c->wnode,
+                         c->ginfo, c->frec, oax, oay, oaz, odu, c->ds);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_force_reset(sph_ctx* c) {
+  hipLaunchKernelGGL(k_reset_force_state, dim3(1), dim3(64), 0, c->stream, c->ds);
+  return hipGetLastError();
+}
+
+hipError_t launch_force(sph_ctx* c, const sph_particles* s, bool step_mode) {
+  c->kp.n = c->n;
+  double* oax = step_mode ? c->a1 : s->ax;
+  double* oay = step_mode ? c->a1 + c->n_max : s->ay;
+  double* oaz = step_mode ? c->a1 + 2 * c->n_max : s->az;
+  double* odu = step_mode ? c->a1 + 3 * c->n_max : s->dudt;
+  return c->kp.precision == SPH_PREC_MIXED ? force_dispatch<true>(c, s, oax, oay, oaz, odu)
+                                           : force_dispatch<false>(c, s, oax, oay, oaz, odu);
+}
+
+hipError_t launch_correct(sph_ctx* c, const sph_particles* s) {
+  hipLaunchKernelGGL(k_correct, dim3(stream_blocks(c->n)), dim3(256), 0, c->stream, parts_of(s),
+                     c->n, c->a1, (int64_t)c->n_max, c->ds);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(sph_ctx* c, const sph_particles* s, double* dev_out) {
+  hipLaunchKernelGGL(k_reduce_part, dim3(kRedBlocks), dim3(256), 0, c->stream, parts_of(s),
+                     (int)s->n, c->red_part);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, c->stream, c->red_part, dev_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_counters(sph_ctx* c) {
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, c->stream, c->ds);
+  return hipGetLastError();
+}
+
+hipError_t launch_neighbours(sph_ctx* c, const sph_particles* s, int mode, int32_t* counts,
+                             const int64_t* offsets, int32_t* idx) {
+  c->kp.n = c->n;
+  const Parts p = parts_of(s);
+  const dim3 grid(c->walk_blocks), block(64);
+  switch (c->kp.n_group) {
+    case 4:
+      hipLaunchKernelGGL((k_neighbours<16>), grid, block, 0, c->stream, c->kp, p, mode, c->wnode,
+                         c->ginfo, counts, offsets, idx, c->ds);
+      break;
+    case 8:
+      hipLaunchKernelGGL((k_neighbours<8>), grid, block, 0, c->stream, c->kp, p, mode, c->wnode,
+                         c->ginfo, counts, offsets, idx, c->ds);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_neighbours<4>), grid, block, 0, c->stream, c->kp, p, mode, c->wnode,
+                         c->ginfo, counts, offsets, idx, c->ds);
+      break;
+    default:
+      hipLaunchKernelGGL((k_neighbours<2>), grid, block, 0, c->stream, c->kp, p, mode, c->wnode,
+                         c->ginfo, counts, offsets, idx, c->ds);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sph

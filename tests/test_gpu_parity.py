@@ -1,0 +1,301 @@
+"""GPU <-> oracle parity through the C ABI.
+
+Integer and index work (keys, sort permutation, tree, groups, neighbour sets)
+must be bit-exact.  FP64 fields must agree to 1e-12: h, rho, Omega, P, c_s
+relative; a and du/dt per particle relative to the sum of their pair-term
+magnitudes (anorm, unorm from the oracle), since on near-uniform inputs the
+sums cancel.  Mixed (FP32 pair) fields are checked against measured bounds.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_07439_amd import inputs, sph
+
+from gpu_util import gpu_eval, rel_err, say, to_orig
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+
+
+def small_workloads():
+    out = []
+    out.append(inputs.lattice(16, jitter=0.3))
+    out.append(inputs.lattice(16, jitter=0.05, velocities=True))
+    c = inputs.sod(dx_left=1.0 / 64, width=0.25)
+    out.append(c)
+    out.append(inputs.kelvin_helmholtz(n_side=20, jitter=0.02))
+    return out
+
+
+WL = small_workloads()
+WL_IDS = [c["workload"] for c in WL]
+
+
+@pytest.mark.parametrize("cfg", WL, ids=WL_IDS)
+def test_keys_sort_tree_groups_bit_exact(cfg):
+    p = sph.make_params(cfg)
+    parts = sph.Particles(cfg)
+    ctx = sph.Context(p, cfg["n"])
+    say(f"[tree] {cfg['workload']} n={cfg['n']}")
+    sph.sph_build_tree(ctx, parts)
+    keys, perm = sph.sph_get_keys(ctx, cfg["n"])
+    op = oracle.make_params(cfg)
+    ok = oracle.keys(cfg["x"], cfg["y"], cfg["z"], op)
+    operm = oracle.sort(ok)
+    np.testing.assert_array_equal(perm, operm)
+    np.testing.assert_array_equal(keys, ok[operm])
+    out = parts.numpy("id", "x")
+    np.testing.assert_array_equal(out["id"], operm)
+    np.testing.assert_array_equal(out["x"], cfg["x"][operm])
+    t = sph.sph_get_tree(ctx)
+    ot = oracle.tree(ok[operm], cfg["n_leaf"])
+    for k in ("level", "prefix", "first", "count", "child_first", "n_child"):
+        np.testing.assert_array_equal(t[k], ot[k], err_msg=k)
+    g = sph.sph_get_groups(ctx)
+    og = oracle.groups(ok[operm], cfg["n_group"])
+    np.testing.assert_array_equal(g["first"], og["first"])
+    np.testing.assert_array_equal(g["count"], og["count"])
+    sph.sph_check(ctx)
+
+
+@pytest.mark.parametrize("n_leaf,n_group", [(16, 8), (8, 16), (4, 4), (32, 32), (1, 4)])
+def test_tree_groups_other_thresholds(n_leaf, n_group):
+    cfg = inputs.lattice(12, jitter=0.4)
+    cfg.update(n_leaf=n_leaf, n_group=n_group)
+    p = sph.make_params(cfg)
+    parts = sph.Particles(cfg)
+    ctx = sph.Context(p, cfg["n"])
+    sph.sph_build_tree(ctx, parts)
+    keys, perm = sph.sph_get_keys(ctx, cfg["n"])
+    t = sph.sph_get_tree(ctx)
+    ot = oracle.tree(keys, n_leaf)
+    for k in ("level", "prefix", "first", "count", "child_first", "n_child"):
+        np.testing.assert_array_equal(t[k], ot[k], err_msg=k)
+    g = sph.sph_get_groups(ctx)
+    og = oracle.groups(keys, n_group)
+    np.testing.assert_array_equal(g["first"], og["first"])
+    np.testing.assert_array_equal(g["count"], og["count"])
+
+
+def test_tree_with_duplicate_positions():
+    """Identical keys: level-21 leaves above n_leaf and groups cut in chunks."""
+    cfg = inputs.lattice(10, jitter=0.3)
+    for k in ("x", "y", "z"):
+        cfg[k][100:180] = cfg[k][100]
+    cfg["x"][500:520] = cfg["x"][500]
+    cfg["y"][500:520] = cfg["y"][500]
+    cfg["z"][500:520] = cfg["z"][500]
+    p = sph.make_params(cfg)
+    parts = sph.Particles(cfg)
+    ctx = sph.Context(p, cfg["n"])
+    sph.sph_build_tree(ctx, parts)
+    keys, perm = sph.sph_get_keys(ctx, cfg["n"])
+    op = oracle.make_params(cfg)
+    ok = oracle.keys(cfg["x"], cfg["y"], cfg["z"], op)
+    np.testing.assert_array_equal(perm, oracle.sort(ok))
+    t = sph.sph_get_tree(ctx)
+    ot = oracle.tree(keys, cfg["n_leaf"])
+    for k in ("level", "first", "count", "child_first", "n_child"):
+        np.testing.assert_array_equal(t[k], ot[k], err_msg=k)
+    assert t["level"].max() == 21
+    g = sph.sph_get_groups(ctx)
+    og = oracle.groups(keys, cfg["n_group"])
+    np.testing.assert_array_equal(g["first"], og["first"])
+    np.testing.assert_array_equal(g["count"], og["count"])
+
+
+@pytest.mark.parametrize("n", [1, 5, 8, 9, 17, 100, 2049, 4097])
+def test_tiny_and_ragged_sizes_tree(n):
+    rng = np.random.default_rng(n)
+    cfg = dict(inputs.DEFAULTS, box_lo=(0, 0, 0), box_len=(1, 1, 1), periodic=(1, 1, 1),
+               x=rng.random(n), y=rng.random(n), z=rng.random(n), m=np.full(n, 1.0 / n),
+               h=np.full(n, 0.2), n=n, workload=f"random{n}")
+    p = sph.make_params(cfg)
+    parts = sph.Particles(cfg)
+    ctx = sph.Context(p, n)
+    sph.sph_build_tree(ctx, parts)
+    keys, perm = sph.sph_get_keys(ctx, n)
+    ok = oracle.keys(cfg["x"], cfg["y"], cfg["z"], oracle.make_params(cfg))
+    np.testing.assert_array_equal(perm, oracle.sort(ok))
+    t = sph.sph_get_tree(ctx)
+    ot = oracle.tree(keys, cfg["n_leaf"])
+    for k in ("level", "prefix", "first", "count", "child_first", "n_child"):
+        np.testing.assert_array_equal(t[k], ot[k], err_msg=k)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("cfg", WL[:3], ids=WL_IDS[:3])
+def test_neighbour_sets_bit_exact(cfg, mode):
+    rng = np.random.default_rng(5)
+    c = dict(cfg)
+    c["h"] = cfg["h"] * rng.uniform(0.8, 1.25, cfg["n"])
+    p = sph.make_params(c)
+    parts = sph.Particles(c)
+    ctx = sph.Context(p, c["n"])
+    sph.sph_build_tree(ctx, parts)
+    off, idx = sph.sph_neighbours(ctx, parts, mode)
+    s = parts.numpy("x", "y", "z", "h", "id")
+    ooff, oidx = oracle.neighbours(s["x"], s["y"], s["z"], s["h"], oracle.make_params(c),
+                                   mode=mode)
+    np.testing.assert_array_equal(off, ooff)
+    np.testing.assert_array_equal(idx, oidx)
+
+
+def compare_fp64(g, o, tol=FP64_TOL):
+    for k in ("h", "rho", "omega", "P", "cs"):
+        e = rel_err(g[k], o[k]).max()
+        say(f"  {k}: max rel err {e:.3e}")
+        assert e <= tol, k
+    for k, nk in (("ax", "anorm"), ("ay", "anorm"), ("az", "anorm"), ("dudt", "unorm")):
+        e = (np.abs(g[k] - o[k]) / np.maximum(o[nk], 1e-300)).max()
+        say(f"  {k}: max err / {nk} {e:.3e}")
+        assert e <= tol, k
+    e = rel_err(g["vsig_dt"], o["vsig_dt"]).max()
+    assert e <= tol, "vsig_dt"
+
+
+@pytest.mark.parametrize("cfg", WL, ids=WL_IDS)
+def test_density_force_fp64_parity(cfg):
+    g, ctx, parts, info = gpu_eval(cfg)
+    o = oracle.evaluate(cfg, oracle.make_params(cfg))
+    compare_fp64(g, o)
+    assert abs(info["dt"] - o["dt_next"]) <= FP64_TOL * o["dt_next"]
+    assert info["stats"]["density_pairs"] == int(o["nneigh"].sum())
+    assert info["stats"]["force_pairs"] == int(o["nneigh_force"].sum())
+
+
+def test_density_force_fp64_cfg1_full_size():
+    """The plain-method workload at its full size (32^3, one evaluation)."""
+    cfg = inputs.lattice(32, jitter=0.05)
+    g, ctx, parts, info = gpu_eval(cfg)
+    o = oracle.evaluate(cfg, oracle.make_params(cfg))
+    compare_fp64(g, o)
+
+
+def test_fixed_three_passes_matches_oracle():
+    cfg = inputs.lattice(12, jitter=0.2)
+    g, ctx, parts, info = gpu_eval(cfg, h_tol=-1.0)
+    oc = dict(cfg)
+    oc["h_tol_oracle"] = -1.0
+    o = oracle.evaluate(cfg, oracle.make_params(oc))
+    for k in ("h", "rho", "omega"):
+        assert rel_err(g[k], o[k]).max() <= FP64_TOL, k
+    assert info["iters"] == 4  # three updates, then the sum at the final h
+
+
+@pytest.mark.parametrize("cfg", WL, ids=WL_IDS)
+def test_mixed_precision_bounds(cfg):
+    g, ctx, parts, info = gpu_eval(cfg, sph.SPH_PREC_MIXED)
+    o = oracle.evaluate(cfg, oracle.make_params(cfg))
+    eh = rel_err(g["h"], o["h"]).max()
+    er = rel_err(g["rho"], o["rho"]).max()
+    eo = rel_err(g["omega"], o["omega"]).max()
+    ea = max((np.abs(g[k] - o[k]) / o["anorm"]).max() for k in ("ax", "ay", "az"))
+    eu = (np.abs(g["dudt"] - o["dudt"]) / np.maximum(o["unorm"], 1e-300)).max()
+    say(f"  mixed: h {eh:.2e} rho {er:.2e} omega {eo:.2e} a/anorm {ea:.2e} du/unorm {eu:.2e}")
+    assert eh < 2e-6 and er < 1e-5 and eo < 1e-5
+    assert ea < 2e-5 and eu < 2e-5
+
+
+def test_step_fp64_matches_oracle_step():
+    cfg = inputs.lattice(16, jitter=0.1, velocities=True)
+    op = oracle.make_params(cfg)
+    o0 = oracle.evaluate(cfg, op)
+    s0 = dict(cfg)
+    for k in ("ax", "ay", "az", "dudt", "h"):
+        s0[k] = o0[k]
+    dt = o0["dt_next"]
+    o1 = oracle.step(s0, dt, op)
+    p = sph.make_params(cfg)
+    parts = sph.Particles(s0)
+    ctx = sph.Context(p, cfg["n"])
+    dtn = sph.sph_step(ctx, parts, dt, want_dt=True)
+    g = to_orig(parts.numpy())
+    for k in ("x", "y", "z", "vx", "vy", "vz", "u", "h", "rho"):
+        e = np.abs(g[k] - o1[k]).max() / max(np.abs(o1[k]).max(), 1e-300)
+        say(f"  step {k}: {e:.2e}")
+        assert e < 1e-12, k
+    for k, nk in (("ax", "anorm"), ("dudt", "unorm")):
+        assert (np.abs(g[k] - o1[k]) / o1[nk]).max() < 1e-11, k
+    assert abs(dtn - o1["dt_next"]) <= 1e-12 * o1["dt_next"]
+
+
+def test_reduce_matches_oracle():
+    cfg = inputs.lattice(12, jitter=0.2, velocities=True)
+    g, ctx, parts, info = gpu_eval(cfg)
+    r = sph.sph_reduce(ctx, parts)
+    o = oracle.evaluate(cfg, oracle.make_params(cfg))
+    ro = oracle.reduce(o)
+    for k in range(12):
+        scale = max(abs(ro[k]), ro[10] if k in (6, 7, 8) else 0.0, ro[11] if k == 9 else 0.0,
+                    1e-300)
+        assert abs(r[k] - ro[k]) <= 1e-12 * scale, k
+    assert abs(r[6:9]).max() <= 1e-13 * r[10]
+    assert abs(r[9]) <= 1e-12 * r[11]
+
+
+def test_error_nonfinite_input():
+    cfg = inputs.lattice(8, jitter=0.1)
+    cfg["x"] = cfg["x"].copy()
+    cfg["x"][5] = np.nan
+    p = sph.make_params(cfg)
+    parts = sph.Particles(cfg)
+    ctx = sph.Context(p, cfg["n"])
+    sph.sph_build_tree(ctx, parts)
+    with pytest.raises(sph.SphError) as e:
+        sph.sph_check(ctx)
+    assert e.value.status == sph.SPH_E_NONFINITE
+
+
+def test_error_no_convergence_within_limit():
+    cfg = inputs.lattice(8, jitter=0.2)
+    cfg["h"] = cfg["h"] * 1.15
+    p = sph.make_params(cfg, max_h_iter=1)
+    parts = sph.Particles(cfg)
+    ctx = sph.Context(p, cfg["n"])
+    sph.sph_build_tree(ctx, parts)
+    with pytest.raises(sph.SphError) as e:
+        sph.sph_density(ctx, parts, want_iters=True)
+    assert e.value.status == sph.SPH_E_NOCONV
+
+
+def test_error_smoothing_length_too_large_for_box():
+    cfg = inputs.lattice(4, jitter=0.0)  # 64 particles: 2h ~ 0.6 > L/2
+    p = sph.make_params(cfg)
+    parts = sph.Particles(cfg)
+    ctx = sph.Context(p, cfg["n"])
+    sph.sph_build_tree(ctx, parts)
+    with pytest.raises(sph.SphError) as e:
+        sph.sph_density(ctx, parts, want_iters=True)
+    assert e.value.status == sph.SPH_E_DOMAIN
+
+
+def test_n_above_capacity_rejected():
+    cfg = inputs.lattice(8)
+    p = sph.make_params(cfg)
+    parts = sph.Particles(cfg)
+    ctx = sph.Context(p, 100)
+    with pytest.raises(sph.SphError) as e:
+        sph.sph_build_tree(ctx, parts)
+    assert e.value.status == sph.SPH_E_ARG
+
+
+@pytest.mark.parametrize("precision", [sph.SPH_PREC_FP64, sph.SPH_PREC_MIXED])
+def test_many_neighbours_use_streaming_density_and_chunked_force(precision):
+    """hfact = 1.8 gives ~195 neighbours: more than a pair list holds, so the
+    density sums stream through the walk and the force empties its lists in
+    chunks.  Results must still match the oracle."""
+    cfg = inputs.lattice(16, jitter=0.2, velocities=True)
+    cfg["hfact"] = 1.8
+    cfg["h"] = cfg["h"] * 1.5
+    g, ctx, parts, info = gpu_eval(cfg, precision)
+    o = oracle.evaluate(cfg, oracle.make_params(cfg))
+    assert o["nneigh"].min() > 128 and o["nneigh_force"].max() > 128
+    if precision == sph.SPH_PREC_FP64:
+        compare_fp64(g, o)
+    else:
+        assert rel_err(g["rho"], o["rho"]).max() < 1e-5
+        assert max((np.abs(g[k] - o[k]) / o["anorm"]).max() for k in ("ax", "ay", "az")) < 2e-5
+    assert info["stats"]["force_pairs"] == int(o["nneigh_force"].sum())
