@@ -76,6 +76,10 @@ struct sph_ctx {
   int32_t* grp_first = nullptr;
   int32_t* grp_count = nullptr;
   sph::GroupInfo* ginfo = nullptr;
+  int2* leaf_pool = nullptr;   // leaf lists stored by the density walk (per-wave regions)
+  int64_t pool_cap = 0;
+  int32_t* gl_off = nullptr;   // per group: first pool entry
+  int32_t* gl_cnt = nullptr;   // per group: entries, -1 if not stored
   // density / force
   void* frec = nullptr;        // FRec64 or FRec32 per particle
   double* a1 = nullptr;        // 4 * n_max: new ax, ay, az, dudt inside sph_step

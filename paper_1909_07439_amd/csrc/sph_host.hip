@@ -14,6 +14,7 @@ namespace sph {
 hipError_t launch_node_boxes(sph_ctx* c, const sph_particles* s);
 hipError_t launch_reset_counters(sph_ctx* c);
 hipError_t launch_force_reset(sph_ctx* c);
+hipError_t launch_leaf_state(sph_ctx* c, int v);
 }  // namespace sph
 
 namespace {
@@ -230,6 +231,10 @@ sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ct
   ALLOC(c->grp_first, N);
   ALLOC(c->grp_count, N);
   ALLOC(c->ginfo, N);
+  c->pool_cap = std::min<int64_t>(16 * N + 256 * (int64_t)c->walk_blocks, 0x7fffffff);
+  ALLOC(c->leaf_pool, c->pool_cap);
+  ALLOC(c->gl_off, N);
+  ALLOC(c->gl_cnt, N);
   {
     const size_t rec = (P.precision == SPH_PREC_MIXED) ? sizeof(sph::FRec32) : sizeof(sph::FRec64);
     e = hipMalloc(&c->frec, rec * (size_t)N);
@@ -293,7 +298,8 @@ void sph_destroy(sph_ctx* c) {
                   c->node_level, c->node_first, c->node_count,   c->node_parent, c->node_child,
                   c->node_nchild, c->node_bb,   c->node_hm,      c->wnode,       c->grp_first,
                   c->grp_count, c->ginfo,       c->frec,         c->a1,          c->nb_cnt,
-                  c->nb_off,    c->red_part,    c->red_out,      c->ds};
+                  c->nb_off,    c->red_part,    c->red_out,      c->ds,
+                  c->leaf_pool, c->gl_off,      c->gl_cnt};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->hs) (void)hipHostFree(c->hs);
@@ -330,6 +336,7 @@ sph_status sph_density(sph_ctx* c, sph_particles* p, int32_t* iters_out) {
   sph_status st = check_parts(c, p, false, true);
   if (st != SPH_OK) return st;
   if (p->n != c->n) return fail(c, SPH_E_ARG, "n differs from the last sph_build_tree");
+  HIPCHK(c, sph::launch_leaf_state(c, 1));
   ph_begin(c, kPhDensity);
   HIPCHK(c, sph::launch_density(c, p));
   ph_end(c, kPhDensity);
@@ -369,6 +376,7 @@ sph_status sph_step(sph_ctx* c, sph_particles* p, double dt, double* dt_next_out
   HIPCHK(c, sph::launch_set_dt(c, dt));
   st = do_build(c, p, false, true);
   if (st != SPH_OK) return st;
+  HIPCHK(c, sph::launch_leaf_state(c, 1));
   ph_begin(c, kPhDensity);
   HIPCHK(c, sph::launch_density(c, p));
   ph_end(c, kPhDensity);

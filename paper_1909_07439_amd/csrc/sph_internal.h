@@ -38,7 +38,7 @@ struct DevState {
   unsigned long long n_cand_density;   // candidate tests in the density walks
   unsigned long long n_cand_force;     // candidate tests in the force walks
   int32_t n_rewalk;
-  int32_t pad0;
+  int32_t leaf_state;  // 0: no stored leaf lists, 1: valid for the force, 2: some h outgrew them
 };
 
 // Walk view of a tree node: centre, conservative half-widths, largest h.

@@ -703,13 +703,17 @@ struct WalkLds {
   int loff[kLCap + 1];
 };
 
-// Candidate tile: positions and one more per-particle value (m_j for the
-// density, h_j for the force) of up to kTile candidates, and their indices.
-struct CandTile {
-  double x[kTile];
-  double y[kTile];
-  double z[kTile];
-  double a[kTile];
+// Candidate tile: up to kTile candidates of the flushed leaves.  FP64 path:
+// absolute positions; FP32 path: positions relative to the group centre,
+// folded to the nearest periodic image once, when staged.  `a` carries one
+// more per-particle value (m_j for the density, h_j for the force), `j` the
+// particle index.
+template <typename T>
+struct TileOf {
+  T x[kTile];
+  T y[kTile];
+  T z[kTile];
+  T a[kTile];
   int j[kTile];
 };
 
@@ -790,11 +794,13 @@ __device__ __forceinline__ int leaf_offsets(WalkLds& L, int nleaf) {
 // Every lane resolves its candidates' particle indices first and then issues
 // all their loads before storing any, so a whole tile costs about one
 // memory latency instead of one per candidate step.
+template <typename T>
 __device__ __forceinline__ void stage_tile(const WalkLds& L, int nleaf, int c0, int cnt,
                                            const double* __restrict__ px,
                                            const double* __restrict__ py,
                                            const double* __restrict__ pz,
-                                           const double* __restrict__ pa, CandTile& T) {
+                                           const double* __restrict__ pa, TileOf<T>& S,
+                                           const GroupInfo& G, const KParams& kp) {
   constexpr int PER = kTile / kWave;
   const int lane = threadIdx.x;
   int jj[PER];
@@ -828,11 +834,18 @@ __device__ __forceinline__ void stage_tile(const WalkLds& L, int nleaf, int c0, 
   for (int q = 0; q < PER; ++q) {
     const int t = lane + q * kWave;
     if (jj[q] >= 0) {
-      T.x[t] = vx[q];
-      T.y[t] = vy[q];
-      T.z[t] = vz[q];
-      T.a[t] = va[q];
-      T.j[t] = jj[q];
+      if constexpr (std::is_same<T, float>::value) {
+        S.x[t] = (float)fold(vx[q] - G.c[0], kp.len[0], kp.half[0], kp.periodic[0]);
+        S.y[t] = (float)fold(vy[q] - G.c[1], kp.len[1], kp.half[1], kp.periodic[1]);
+        S.z[t] = (float)fold(vz[q] - G.c[2], kp.len[2], kp.half[2], kp.periodic[2]);
+        S.a[t] = (float)va[q];
+      } else {
+        S.x[t] = vx[q];
+        S.y[t] = vy[q];
+        S.z[t] = vz[q];
+        S.a[t] = va[q];
+      }
+      S.j[t] = jj[q];
     }
   }
   __syncthreads();
@@ -841,22 +854,33 @@ __device__ __forceinline__ void stage_tile(const WalkLds& L, int nleaf, int c0, 
 // Candidate loop over the flushed leaves, one staged tile at a time: lane
 // `sub` of every slot visits tile entries sub, sub+LPI, ...;
 // body(valid, c) is called by all lanes with c the tile index.
-template <int LPI, typename Body>
+template <int LPI, typename T, typename Body>
 __device__ __forceinline__ void for_tiles(const WalkLds& L, int nleaf, int total, int sub,
                                           const double* __restrict__ px,
                                           const double* __restrict__ py,
                                           const double* __restrict__ pz,
-                                          const double* __restrict__ pa, CandTile& T,
-                                          Body body) {
+                                          const double* __restrict__ pa, TileOf<T>& S,
+                                          const GroupInfo& G, const KParams& kp, Body body) {
   for (int c0 = 0; c0 < total; c0 += kTile) {
     const int cnt = min(kTile, total - c0);
-    stage_tile(L, nleaf, c0, cnt, px, py, pz, pa, T);
+    stage_tile<T>(L, nleaf, c0, cnt, px, py, pz, pa, S, G, kp);
     for (int cb = 0; cb < cnt; cb += LPI) {
       const int c = cb + sub;
       body(c < cnt, c);
     }
     __syncthreads();
   }
+}
+
+// Load entries [b, b+nl) of a stored leaf list into the LDS leaf list.
+__device__ __forceinline__ void load_leaves(WalkLds& L, const int2* __restrict__ pool, int off,
+                                            int b, int nl) {
+  for (int k = threadIdx.x; k < nl; k += kWave) {
+    const int2 e = pool[off + b + k];
+    L.lfirst[k] = e.x;
+    L.lcnt[k] = e.y;
+  }
+  __syncthreads();
 }
 
 // ---- M4 cubic spline (3D, support 2h, 1/pi): f(q) and f'(q) -------------
@@ -894,7 +918,10 @@ __device__ __forceinline__ float fast_rcp(float v) { return __builtin_amdgcn_rcp
 // kept in LDS while h is iterated; the walk is redone only if some h grows
 // past its list radius.  Newton-Raphson on f(h) = S0(h) - m (hfact/h)^3 with
 // a bracket; the group leaves the loop when a ballot shows every slot
-// converged, after one more sum at the converged h.
+// converged, after one more sum at the converged h.  A group whose lists
+// would overflow sums on the fly during a walk at the current h instead.
+// The first walk opens nodes with the force criterion widened by the margin
+// and stores the group's leaf list, so that the force pass can replay it.
 // ============================================================================
 constexpr double kInvPi = 0.318309886183790671537767526745;
 
@@ -903,11 +930,14 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
                                                 const WalkNode* __restrict__ nodes,
                                                 const GroupInfo* __restrict__ groups,
                                                 void* __restrict__ frec_out,
+                                                int2* __restrict__ pool, int64_t pool_cap,
+                                                int32_t* __restrict__ gl_off,
+                                                int32_t* __restrict__ gl_cnt,
                                                 DevState* __restrict__ ds) {
   using R = typename std::conditional<MIXED, float, double>::type;
   constexpr int GS = kWave / LPI;
   __shared__ WalkLds L;
-  __shared__ CandTile T;
+  __shared__ TileOf<R> T;
   __shared__ R s_r[kPMax * GS];
   __shared__ R s_m[kPMax * GS];
 
@@ -921,11 +951,16 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
   double minhalf = SPH_INF;
   for (int a = 0; a < 3; ++a)
     if (kp.periodic[a]) minhalf = fmin(minhalf, kp.half[a]);
+  // this wave's region of the leaf-list pool
+  const int64_t rsize = pool_cap / gridDim.x;
+  const int64_t rbase = (int64_t)blockIdx.x * rsize;
+  int64_t rpos = 0;
 
   uint32_t err = 0;
   int it_max = 0;
   unsigned long long pairs_final = 0, sums = 0, cands = 0;
-  int rewalks = 0;
+  int walks = 0;
+  bool grew = false;
 
   for (int g = gbeg + local; g < gend; g += nloc) {
     const GroupInfo G = groups[g];
@@ -937,10 +972,20 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
       err |= kErrNonFinite;
       h = 1.0;
     }
+    const double h0 = h;
+    float xr = 0.f, yr = 0.f, zr = 0.f;  // FP32 path: position relative to the group centre
+    if constexpr (MIXED) {
+      xr = (float)fold(xi - G.c[0], kp.len[0], kp.half[0], kp.periodic[0]);
+      yr = (float)fold(yi - G.c[1], kp.len[1], kp.half[1], kp.periodic[1]);
+      zr = (float)fold(zi - G.c[2], kp.len[2], kp.half[2], kp.periodic[2]);
+    }
     double hlim = h * margin;
     double hlo = 0.0, hhi = SPH_INF;
     bool conv = !act;
     bool need = true;
+    bool store = true;  // the first walk stores the leaf list
+    const int64_t gstart = rpos;
+    bool gover = false;
     int npair = 0;
     int nit = 0;
     double S0 = 0.0, S1 = 0.0;
@@ -950,36 +995,52 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
     while (true) {
       if (!stream && ballot64(act && need) != 0ull) {
         // ---- walk and fill the pair lists (r < 2 hlim_i)
-        const double Rg = 2.0 * wave_max_f64(act ? hlim : 0.0) * (1.0 + 4e-9);
+        const double hm = wave_max_f64(act ? hlim : 0.0);
         const double rl = 2.0 * hlim, rl2 = rl * rl;
+        const float rl2f = (float)rl2 * 1.00001f;
         npair = 0;
-        auto radius = [&](const WalkNode&) { return Rg; };
+        auto radius = [&](const WalkNode& nd) {
+          const double r = store ? fmax(hm, margin * (double)nd.hmax) : hm;
+          return 2.0 * r * (1.0 + 4e-9);
+        };
         auto flush = [&](int nleaf) {
           const int total = leaf_offsets(L, nleaf);
+          if (store) {
+            if (!gover && rpos + nleaf <= rsize) {
+              for (int k = lane; k < nleaf; k += kWave)
+                pool[rbase + rpos + k] = make_int2(L.lfirst[k], L.lcnt[k]);
+              rpos += nleaf;
+            } else {
+              gover = true;
+            }
+          }
           cands += (unsigned long long)total * ((act && sub == 0) ? 1u : 0u);
-          for_tiles<LPI>(L, nleaf, total, sub, p.x, p.y, p.z, p.m, T, [&](bool valid, int c) {
+          for_tiles<LPI, R>(L, nleaf, total, sub, p.x, p.y, p.z, p.m, T, G, kp,
+                            [&](bool valid, int c) {
             bool pred = false;
-            double r2 = 0.0;
-            double mj = 0.0;
+            R rv = R(0), mj = R(0);
             if (valid && act) {
-              const double dx = fold(xi - T.x[c], kp.len[0], kp.half[0], kp.periodic[0]);
-              const double dy = fold(yi - T.y[c], kp.len[1], kp.half[1], kp.periodic[1]);
-              const double dz = fold(zi - T.z[c], kp.len[2], kp.half[2], kp.periodic[2]);
-              r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-              pred = r2 < rl2;
+              if constexpr (MIXED) {
+                const float dx = xr - T.x[c], dy = yr - T.y[c], dz = zr - T.z[c];
+                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                pred = r2 < rl2f;
+                rv = fast_sqrt(r2);
+              } else {
+                const double dx = fold(xi - T.x[c], kp.len[0], kp.half[0], kp.periodic[0]);
+                const double dy = fold(yi - T.y[c], kp.len[1], kp.half[1], kp.periodic[1]);
+                const double dz = fold(zi - T.z[c], kp.len[2], kp.half[2], kp.periodic[2]);
+                const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                pred = r2 < rl2;
+                if (pred) rv = sqrt(r2);
+              }
               mj = T.a[c];
             }
             const uint64_t b = ballot64(pred);
             const uint32_t seg = (uint32_t)((b >> (slot * LPI)) & ((LPI == 64) ? ~0ull : ((1ull << LPI) - 1ull)));
             const int pos = npair + __popc(seg & ((1u << sub) - 1u));
             if (pred && pos < kPMax) {
-              if constexpr (MIXED) {
-                s_r[pos * GS + slot] = fast_sqrt((float)r2);
-                s_m[pos * GS + slot] = (float)mj;
-              } else {
-                s_r[pos * GS + slot] = sqrt(r2);
-                s_m[pos * GS + slot] = mj;
-              }
+              s_r[pos * GS + slot] = rv;
+              s_m[pos * GS + slot] = mj;
             }
             npair += __popc(seg);
           });
@@ -989,13 +1050,20 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
           err |= kErrFrontier;
           failed = true;
         }
+        if (store) {
+          if (lane == 0) {
+            gl_off[g] = (int32_t)(rbase + gstart);
+            gl_cnt[g] = (gover || failed) ? -1 : (int32_t)(rpos - gstart);
+          }
+          store = false;
+        }
         if (ballot64(failed) != 0ull) {
           failed = true;
           break;
         }
         if (ballot64(npair > kPMax) != 0ull) stream = true;
         need = false;
-        ++rewalks;
+        ++walks;
       }
       // ---- one density sum at the current h
       const double hinv = 1.0 / h;
@@ -1005,32 +1073,40 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
         // walk at the current h and accumulate the candidates directly
         const double Rg = 2.0 * wave_max_f64(act ? h : 0.0) * (1.0 + 4e-9);
         const double twoh = 2.0 * h, rl2 = twoh * twoh;
+        const float rl2f = (float)rl2;
+        const float hinvf = (float)hinv;
         auto radius = [&](const WalkNode&) { return Rg; };
         auto flush = [&](int nleaf) {
           const int total = leaf_offsets(L, nleaf);
-          for_tiles<LPI>(L, nleaf, total, sub, p.x, p.y, p.z, p.m, T, [&](bool valid, int c) {
+          for_tiles<LPI, R>(L, nleaf, total, sub, p.x, p.y, p.z, p.m, T, G, kp,
+                            [&](bool valid, int c) {
             if (valid && act) {
-              const double dx = fold(xi - T.x[c], kp.len[0], kp.half[0], kp.periodic[0]);
-              const double dy = fold(yi - T.y[c], kp.len[1], kp.half[1], kp.periodic[1]);
-              const double dz = fold(zi - T.z[c], kp.len[2], kp.half[2], kp.periodic[2]);
-              const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-              if (r2 < rl2) {
-                const double mj = T.a[c];
-                if constexpr (MIXED) {
-                  const float m = (float)mj;
-                  const float q = fast_sqrt((float)r2) * (float)hinv;
+              if constexpr (MIXED) {
+                const float dx = xr - T.x[c], dy = yr - T.y[c], dz = zr - T.z[c];
+                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                if (r2 < rl2f) {
+                  const float m = T.a[c];
+                  const float q = fast_sqrt(r2) * hinvf;
                   float f, df;
                   m4_f_df<float>(q, f, df);
                   a0 += (double)(m * f);
                   a1 += (double)(m * (3.0f * f + q * df));
-                } else {
+                  ++cnt;
+                }
+              } else {
+                const double dx = fold(xi - T.x[c], kp.len[0], kp.half[0], kp.periodic[0]);
+                const double dy = fold(yi - T.y[c], kp.len[1], kp.half[1], kp.periodic[1]);
+                const double dz = fold(zi - T.z[c], kp.len[2], kp.half[2], kp.periodic[2]);
+                const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                if (r2 < rl2) {
+                  const double mj = T.a[c];
                   const double q = sqrt(r2) * hinv;
                   double f, df;
                   m4_f_df<double>(q, f, df);
                   a0 += mj * f;
                   a1 += mj * (3.0 * f + q * df);
+                  ++cnt;
                 }
-                ++cnt;
               }
             }
           });
@@ -1044,7 +1120,7 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
           failed = true;
           break;
         }
-        ++rewalks;
+        ++walks;
       } else if (MIXED) {
         const float hinvf = (float)hinv;
         const float twohf = (float)(2.0 * h);
@@ -1126,6 +1202,7 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
       }
     }
     it_max = max(it_max, nit + 1);
+    if (act && !failed && h > h0 * margin) grew = true;
     if (act && !failed) {
       const double rho = S0;
       const double omega = 1.0 + h * S1 / (3.0 * rho);
@@ -1189,6 +1266,7 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
     }
   }
   // one set of atomics per wave
+  const bool ballot_any = ballot64(grew) != 0ull;
   const uint64_t b = ballot64(err != 0);
   uint32_t eall = err;
   for (int d = 32; d > 0; d >>= 1) eall |= __shfl_xor(eall, d, kWave);
@@ -1206,7 +1284,8 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
     atomicAdd(&ds->n_pairs_density, pf);
     atomicAdd(&ds->n_sums_density, sums);
     atomicAdd(&ds->n_cand_density, cd);
-    atomicAdd(&ds->n_rewalk, rewalks);
+    atomicAdd(&ds->n_rewalk, walks);
+    if (ballot_any) atomicMax(&ds->leaf_state, 2);
   }
 }
 
@@ -1230,16 +1309,21 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
                                               const WalkNode* __restrict__ nodes,
                                               const GroupInfo* __restrict__ groups,
                                               const void* __restrict__ frec_in,
+                                              const int2* __restrict__ pool,
+                                              const int32_t* __restrict__ gl_off,
+                                              const int32_t* __restrict__ gl_cnt,
                                               double* __restrict__ out_ax,
                                               double* __restrict__ out_ay,
                                               double* __restrict__ out_az,
                                               double* __restrict__ out_du,
                                               DevState* __restrict__ ds) {
   using Rec = typename FRecOf<MIXED>::T;
+  using R = typename std::conditional<MIXED, float, double>::type;
   constexpr int GS = kWave / LPI;
   __shared__ WalkLds L;
-  __shared__ CandTile T;
+  __shared__ TileOf<R> T;
   __shared__ int s_j[kPMax * GS];
+  const bool use_lists = ds->leaf_state == 1;
   const Rec* __restrict__ rec = reinterpret_cast<const Rec*>(frec_in);
 
   const int lane = threadIdx.x;
@@ -1258,6 +1342,13 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
     const int i = G.first + (act ? slot : 0);
     const double xi = p.x[i], yi = p.y[i], zi = p.z[i], hi = p.h[i];
     const Rec ri = rec[i];
+    float xr = 0.f, yr = 0.f, zr = 0.f;  // FP32 path: position relative to the group centre
+    const float hif = (float)hi;
+    if constexpr (MIXED) {
+      xr = (float)fold(xi - G.c[0], kp.len[0], kp.half[0], kp.periodic[0]);
+      yr = (float)fold(yi - G.c[1], kp.len[1], kp.half[1], kp.periodic[1]);
+      zr = (float)fold(zi - G.c[2], kp.len[2], kp.half[2], kp.periodic[2]);
+    }
     double ax = 0.0, ay = 0.0, az = 0.0, du = 0.0, vmax = 0.0;
     int npair = 0;
     // ---- pair loop over the pending list entries of each slot
@@ -1362,7 +1453,8 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
     auto flush = [&](int nleaf) {
       const int total = leaf_offsets(L, nleaf);
       cands += (unsigned long long)total * ((act && sub == 0) ? 1u : 0u);
-      for_tiles<LPI>(L, nleaf, total, sub, p.x, p.y, p.z, p.h, T, [&](bool valid, int c) {
+      for_tiles<LPI, R>(L, nleaf, total, sub, p.x, p.y, p.z, p.h, T, G, kp,
+                        [&](bool valid, int c) {
         // one candidate step adds at most LPI entries per slot: empty the
         // lists through the pair loop before they can overflow
         if (ballot64(npair > kPMax - LPI) != 0ull) {
@@ -1373,13 +1465,21 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
         bool pred = false;
         const int j = valid ? T.j[c] : -1;
         if (valid && act && j != i) {
-          const double dx = fold(xi - T.x[c], kp.len[0], kp.half[0], kp.periodic[0]);
-          const double dy = fold(yi - T.y[c], kp.len[1], kp.half[1], kp.periodic[1]);
-          const double dz = fold(zi - T.z[c], kp.len[2], kp.half[2], kp.periodic[2]);
-          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-          const double hj = T.a[c];
-          const double sr = 2.0 * (hi > hj ? hi : hj);
-          pred = r2 < sr * sr;
+          if constexpr (MIXED) {
+            const float dx = xr - T.x[c], dy = yr - T.y[c], dz = zr - T.z[c];
+            const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            const float hj = T.a[c];
+            const float sr = 2.0f * fmaxf(hif, hj);
+            pred = r2 < sr * sr * 1.00001f;
+          } else {
+            const double dx = fold(xi - T.x[c], kp.len[0], kp.half[0], kp.periodic[0]);
+            const double dy = fold(yi - T.y[c], kp.len[1], kp.half[1], kp.periodic[1]);
+            const double dz = fold(zi - T.z[c], kp.len[2], kp.half[2], kp.periodic[2]);
+            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            const double hj = T.a[c];
+            const double sr = 2.0 * (hi > hj ? hi : hj);
+            pred = r2 < sr * sr;
+          }
         }
         const uint64_t b = ballot64(pred);
         const uint32_t seg = (uint32_t)((b >> (slot * LPI)) & ((LPI == 64) ? ~0ull : ((1ull << LPI) - 1ull)));
@@ -1389,7 +1489,18 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
       });
       __syncthreads();
     };
-    if (!group_walk(nodes, G, kp, L, radius, flush)) err |= kErrFrontier;
+    const int lcount = use_lists ? gl_cnt[g] : -1;
+    if (lcount >= 0) {
+      // replay the leaf list the density walk stored for this group
+      const int off = gl_off[g];
+      for (int b = 0; b < lcount; b += kLCap) {
+        const int nl = min(kLCap, lcount - b);
+        load_leaves(L, pool, off, b, nl);
+        flush(nl);
+      }
+    } else if (!group_walk(nodes, G, kp, L, radius, flush)) {
+      err |= kErrFrontier;
+    }
     __syncthreads();
     compute();
     ax = seg_sum<LPI>(ax);
@@ -1441,7 +1552,7 @@ __global__ __launch_bounds__(64) void k_neighbours(KParams kp, Parts p, int mode
                                                    int32_t* __restrict__ idx,
                                                    DevState* __restrict__ ds) {
   __shared__ WalkLds L;
-  __shared__ CandTile T;
+  __shared__ TileOf<double> T;
   const int lane = threadIdx.x;
   const int slot = lane / LPI, sub = lane % LPI;
   const int ng = ds->n_groups;
@@ -1458,7 +1569,8 @@ __global__ __launch_bounds__(64) void k_neighbours(KParams kp, Parts p, int mode
     };
     auto flush = [&](int nleaf) {
       const int total = leaf_offsets(L, nleaf);
-      for_tiles<LPI>(L, nleaf, total, sub, p.x, p.y, p.z, p.h, T, [&](bool valid, int c) {
+      for_tiles<LPI, double>(L, nleaf, total, sub, p.x, p.y, p.z, p.h, T, G, kp,
+                             [&](bool valid, int c) {
         bool pred = false;
         const int j = valid ? T.j[c] : -1;
         if (valid && act) {
@@ -1498,6 +1610,10 @@ __global__ void k_set_dt(DevState* ds, double dt_host) {
   }
 }
 
+__global__ void k_set_leaf_state(DevState* ds, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ds->leaf_state = v;
+}
+
 __global__ void k_reset_force_state(DevState* ds) {
   if (threadIdx.x == 0 && blockIdx.x == 0) ds->dt_min_enc = enc_f64(SPH_INF);
 }
@@ -1511,6 +1627,7 @@ __global__ void k_reset_counters(DevState* ds) {
     ds->n_cand_density = 0;
     ds->n_cand_force = 0;
     ds->n_rewalk = 0;
+    ds->leaf_state = 0;
   }
 }
 
@@ -1704,21 +1821,30 @@ static hipError_t density_dispatch(sph_ctx* c, const sph_particles* s) {
   switch (c->kp.n_group) {
     case 4:
       hipLaunchKernelGGL((k_density<MIXED, 16>), grid, block, 0, c->stream, c->kp, p, c->wnode,
-                         c->ginfo, c->frec, c->ds);
+                         c->ginfo, c->frec, c->leaf_pool, c->pool_cap, c->gl_off, c->gl_cnt,
+                         c->ds);
       break;
     case 8:
       hipLaunchKernelGGL((k_density<MIXED, 8>), grid, block, 0, c->stream, c->kp, p, c->wnode,
-                         c->ginfo, c->frec, c->ds);
+                         c->ginfo, c->frec, c->leaf_pool, c->pool_cap, c->gl_off, c->gl_cnt,
+                         c->ds);
       break;
     case 16:
       hipLaunchKernelGGL((k_density<MIXED, 4>), grid, block, 0, c->stream, c->kp, p, c->wnode,
-                         c->ginfo, c->frec, c->ds);
+                         c->ginfo, c->frec, c->leaf_pool, c->pool_cap, c->gl_off, c->gl_cnt,
+                         c->ds);
       break;
     default:
       hipLaunchKernelGGL((k_density<MIXED, 2>), grid, block, 0, c->stream, c->kp, p, c->wnode,
-                         c->ginfo, c->frec, c->ds);
+                         c->ginfo, c->frec, c->leaf_pool, c->pool_cap, c->gl_off, c->gl_cnt,
+                         c->ds);
       break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_leaf_state(sph_ctx* c, int v) {
+  hipLaunchKernelGGL(k_set_leaf_state, dim3(1), dim3(64), 0, c->stream, c->ds, v);
   return hipGetLastError();
 }
 
@@ -1736,19 +1862,23 @@ static hipError_t force_dispatch(sph_ctx* c, const sph_particles* s, double* oax
   switch (c->kp.n_group) {
     case 4:
       hipLaunchKernelGGL((k_force<MIXED, 16>), grid, block, 0, c->stream, c->kp, p, c->wnode,
-                         c->ginfo, c->frec, oax, oay, oaz, odu, c->ds);
+                         c->ginfo, c->frec, c->leaf_pool, c->gl_off, c->gl_cnt, oax, oay, oaz,
+                         odu, c->ds);
       break;
     case 8:
       hipLaunchKernelGGL((k_force<MIXED, 8>), grid, block, 0, c->stream, c->kp, p, c->wnode,
-                         c->ginfo, c->frec, oax, oay, oaz, odu, c->ds);
+                         c->ginfo, c->frec, c->leaf_pool, c->gl_off, c->gl_cnt, oax, oay, oaz,
+                         odu, c->ds);
       break;
     case 16:
       hipLaunchKernelGGL((k_force<MIXED, 4>), grid, block, 0, c->stream, c->kp, p, c->wnode,
-                         c->ginfo, c->frec, oax, oay, oaz, odu, c->ds);
+                         c->ginfo, c->frec, c->leaf_pool, c->gl_off, c->gl_cnt, oax, oay, oaz,
+                         odu, c->ds);
       break;
     default:
       hipLaunchKernelGGL((k_force<MIXED, 2>), grid, block, 0, c->stream, c->kp, p, c->wnode,
-                         c->ginfo, c->frec, oax, oay, oaz, odu, c->ds);
+                         c->ginfo, c->frec, c->leaf_pool, c->gl_off, c->gl_cnt, oax, oay, oaz,
+                         odu, c->ds);
       break;
   }
   return hipGetLastError();

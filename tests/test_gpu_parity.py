@@ -295,7 +295,10 @@ def test_many_neighbours_use_streaming_density_and_chunked_force(precision):
     assert o["nneigh"].min() > 128 and o["nneigh_force"].max() > 128
     if precision == sph.SPH_PREC_FP64:
         compare_fp64(g, o)
+        assert info["stats"]["force_pairs"] == int(o["nneigh_force"].sum())
     else:
         assert rel_err(g["rho"], o["rho"]).max() < 1e-5
         assert max((np.abs(g[k] - o[k]) / o["anorm"]).max() for k in ("ax", "ay", "az")) < 2e-5
-    assert info["stats"]["force_pairs"] == int(o["nneigh_force"].sum())
+        # the FP32 filter admits pairs up to a relative 1e-5 beyond 2h (where F = 0)
+        assert abs(info["stats"]["force_pairs"] - int(o["nneigh_force"].sum())) \
+            <= 1e-4 * o["nneigh_force"].sum()
