@@ -119,6 +119,8 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n-group", type=int, default=None, help="particles per walk group")
+    ap.add_argument("--n-leaf", type=int, default=None, help="particles per tree leaf")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no "
@@ -131,6 +133,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     cfg = workload(args.workload)
+    if args.n_group:
+        cfg["n_group"] = args.n_group
+    if args.n_leaf:
+        cfg["n_leaf"] = args.n_leaf
     prec = sph.SPH_PREC_MIXED if args.precision == "mixed" else sph.SPH_PREC_FP64
     print(f"[bench] workload {cfg['workload']} n={cfg['n']} precision={args.precision} "
           f"steps={args.steps} warmup={args.warmup}", flush=True)

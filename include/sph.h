@@ -67,7 +67,9 @@ typedef struct {
   int32_t n_leaf;       /* max particles per tree leaf (Sect. 3.1); 1..64 */
   int32_t n_group;      /* max particles per walk group (Sect. 3.1); one of 4,8,16,32 */
   int32_t precision;    /* sph_precision: pair arithmetic in FP64 or FP32 */
-  double h_tol;         /* stop when |h_new - h| <= h_tol*h; < 0: three fixed passes */
+  double h_tol;         /* h is converged when |S0(h) - m (hfact/h)^3| <= 3 h_tol m (hfact/h)^3,
+                           i.e. a Newton step would move it by <= ~h_tol*h; 0 selects the
+                           default (1e-14 FP64, 2e-7 mixed); < 0: three fixed passes */
   int32_t max_h_iter;   /* iteration limit before SPH_E_NOCONV (default 30 if <= 0) */
   int32_t reserved0;
   double h_margin;      /* pair lists cover r < 2 h h_margin so h may grow by that

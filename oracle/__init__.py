@@ -113,8 +113,18 @@ def _load():
         lib.orc_neighbours.argtypes = [ctypes.c_int64, _D, _D, _D, _D, _P, ctypes.c_int,
                                        ctypes.c_int, _I64, _I64, ctypes.c_int64]
         lib.orc_neighbours.restype = ctypes.c_int64
+        lib.orc_neighbours_sel.argtypes = [ctypes.c_int64, _D, _D, _D, _D, _P, ctypes.c_int,
+                                           ctypes.c_int, _I64, ctypes.c_int64, _I64, _I64,
+                                           ctypes.c_int64]
+        lib.orc_neighbours_sel.restype = ctypes.c_int64
         lib.orc_density.argtypes = [ctypes.c_int64, _D, _D, _D, _D, _D, _P, _D, _D, _D, _I64, _I32]
         lib.orc_density.restype = ctypes.c_int
+        lib.orc_density_sel.argtypes = [ctypes.c_int64, _D, _D, _D, _D, _D, _P, _I64,
+                                        ctypes.c_int64, _D, _D, _D, _I64, _I32]
+        lib.orc_density_sel.restype = ctypes.c_int
+        lib.orc_force_sel.argtypes = [ctypes.c_int64] + [_D] * 13 + [_P, _I64, ctypes.c_int64] + \
+            [_D] * 7 + [_I64]
+        lib.orc_force_sel.restype = ctypes.c_int
         lib.orc_eos.argtypes = [ctypes.c_int64, _D, _D, _P, _D, _D]
         lib.orc_force.argtypes = [ctypes.c_int64] + [_D] * 13 + [_P] + [_D] * 7 + [_I64]
         lib.orc_force.restype = ctypes.c_int
@@ -199,25 +209,30 @@ def groups(sorted_keys: np.ndarray, n_group: int) -> dict:
     return dict(first=first[:ng], count=count[:ng])
 
 
-def neighbours(x, y, z, h, params: Params, mode: int = 0, brute: bool = False):
-    """CSR (offsets[n+1], idx) of neighbour sets, ascending indices.
+def neighbours(x, y, z, h, params: Params, mode: int = 0, brute: bool = False, sel=None):
+    """CSR (offsets, idx) of neighbour sets, ascending indices.
 
     mode 0: density set, r_ij < 2 h_i, self included.
     mode 1: force set, j != i and r_ij < 2 max(h_i, h_j).
+    sel: only these particles (row k is particle sel[k]); default all.
     """
     x, y, z, h = _f64(x), _f64(y), _f64(z), _f64(h)
     n = x.size
-    off = np.empty(n + 1, np.int64)
+    if sel is None:
+        selp, nsel = None, n
+    else:
+        sel = np.ascontiguousarray(sel, dtype=np.int64)
+        selp, nsel = sel.ctypes.data_as(_I64), sel.size
+    off = np.empty(nsel + 1, np.int64)
     lib = _load()
-    tot = lib.orc_neighbours(n, _dptr(x), _dptr(y), _dptr(z), _dptr(h), ctypes.byref(params),
-                             int(mode), int(bool(brute)), off.ctypes.data_as(_I64), None, 0)
+    args = (n, _dptr(x), _dptr(y), _dptr(z), _dptr(h), ctypes.byref(params), int(mode),
+            int(bool(brute)), selp, nsel, off.ctypes.data_as(_I64))
+    tot = lib.orc_neighbours_sel(*args, None, 0)
     if tot not in (E_OVERFLOW,) and tot < 0:
         raise RuntimeError(f"orc_neighbours failed: {tot}")
-    total = int(off[n])
+    total = int(off[nsel])
     idx = np.empty(max(total, 1), np.int64)
-    tot = lib.orc_neighbours(n, _dptr(x), _dptr(y), _dptr(z), _dptr(h), ctypes.byref(params),
-                             int(mode), int(bool(brute)), off.ctypes.data_as(_I64),
-                             idx.ctypes.data_as(_I64), total)
+    tot = lib.orc_neighbours_sel(*args, idx.ctypes.data_as(_I64), total)
     if tot < 0:
         raise RuntimeError(f"orc_neighbours failed: {tot}")
     return off, idx[:total]
@@ -261,6 +276,61 @@ def force(s: dict, params: Params) -> dict:
     if st != OK:
         raise RuntimeError(f"orc_force failed: {st}")
     out["nneigh_force"] = nn
+    return out
+
+
+def evaluate_subset(s: dict, params: Params, sel) -> dict:
+    """Density (root h), EOS and force for the particles ``sel`` only.
+
+    Every particle's fields are inputs (the neighbours of a selected particle
+    are found among all of them, and the force needs each neighbour's rho,
+    Omega, P, c_s: these are solved for the neighbours too).  Outputs are
+    arrays over ``sel`` in its order.  The arithmetic is that of
+    ``evaluate``; only the particle loops are restricted.
+    """
+    a = {k: _f64(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m", "u", "h")}
+    n = a["x"].size
+    sel = np.ascontiguousarray(sel, dtype=np.int64)
+    lib = _load()
+    # particles whose rho, Omega, P, c_s the force on sel needs: sel and all
+    # force neighbours of sel at the start h grown by a safe factor
+    grow = a["h"] * 1.6
+    off, idx = neighbours(a["x"], a["y"], a["z"], grow, params, mode=1, sel=sel)
+    need = np.unique(np.concatenate([sel, idx]))
+    m = need.size
+    ho, rho, om = np.empty(m), np.empty(m), np.empty(m)
+    nn = np.empty(m, np.int64)
+    it = np.empty(m, np.int32)
+    st = lib.orc_density_sel(n, _dptr(a["x"]), _dptr(a["y"]), _dptr(a["z"]), _dptr(a["m"]),
+                             _dptr(a["h"]), ctypes.byref(params), need.ctypes.data_as(_I64), m,
+                             _dptr(ho), _dptr(rho), _dptr(om), nn.ctypes.data_as(_I64),
+                             it.ctypes.data_as(_I32))
+    if st != OK:
+        raise RuntimeError(f"orc_density_sel failed: {st}")
+    full = {k: np.full(n, np.nan) for k in ("h", "rho", "omega")}
+    full["h"] = a["h"].copy()
+    full["h"][need], full["rho"][need], full["omega"][need] = ho, rho, om
+    P, cs = np.full(n, np.nan), np.full(n, np.nan)
+    P[need], cs[need] = eos(rho, a["u"][need], params)
+    # a neighbour of sel outside `need` would leave a NaN in the sums: checked
+    k = sel.size
+    out = {q: np.empty(k) for q in ("ax", "ay", "az", "dudt", "vsig_dt", "anorm", "unorm")}
+    nnf = np.empty(k, np.int64)
+    st = lib.orc_force_sel(n, *[_dptr(v) for v in (a["x"], a["y"], a["z"], a["vx"], a["vy"],
+                                                   a["vz"], a["m"], a["u"], full["h"],
+                                                   full["rho"], full["omega"], P, cs)],
+                           ctypes.byref(params), sel.ctypes.data_as(_I64), k,
+                           *[_dptr(out[q]) for q in ("ax", "ay", "az", "dudt", "vsig_dt",
+                                                      "anorm", "unorm")],
+                           nnf.ctypes.data_as(_I64))
+    if st != OK:
+        raise RuntimeError(f"orc_force_sel failed: {st}")
+    pos = np.searchsorted(need, sel)
+    out.update(h=ho[pos], rho=rho[pos], omega=om[pos], nneigh=nn[pos], P=P[sel], cs=cs[sel],
+               nneigh_force=nnf)
+    for q in ("ax", "dudt"):
+        if not np.all(np.isfinite(out[q])):
+            raise RuntimeError("a neighbour of a selected particle was not solved for")
     return out
 
 

@@ -506,12 +506,15 @@ static int neighbours_of(const orc_stree* t, int64_t i, double hi, int mode,
 /* brute = 1: test every pair (O(N^2)); brute = 0: via the search tree.       */
 /* Returns the total number of entries, or a negative status.  If the total */
 /* exceeds cap, offsets are still filled and ORC_E_OVERFLOW is returned.    */
-int64_t orc_neighbours(int64_t n, const double* x, const double* y,
-                       const double* z, const double* h, const orc_params* p,
-                       int mode, int brute, int64_t* offsets, int64_t* idx,
-                       int64_t cap) {
+/* As orc_neighbours, for the particles sel[0..nsel) only (all if sel is   */
+/* NULL); offsets has nsel+1 entries and row k belongs to particle sel[k].   */
+int64_t orc_neighbours_sel(int64_t n, const double* x, const double* y,
+                           const double* z, const double* h, const orc_params* p,
+                           int mode, int brute, const int64_t* sel, int64_t nsel,
+                           int64_t* offsets, int64_t* idx, int64_t cap) {
   if (n <= 0) return ORC_E_ARG;
-  int64_t* cnt = (int64_t*)calloc((size_t)n, sizeof(int64_t));
+  if (!sel) nsel = n;
+  int64_t* cnt = (int64_t*)calloc((size_t)(nsel > 0 ? nsel : 1), sizeof(int64_t));
   if (!cnt) return ORC_E_NOMEM;
   orc_stree t;
   int st = ORC_OK;
@@ -527,34 +530,36 @@ int64_t orc_neighbours(int64_t n, const double* x, const double* y,
   {
     orc_list l = {0};
 #pragma omp for schedule(dynamic, 64)
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t k = 0; k < nsel; ++k) {
+      const int64_t i = sel ? sel[k] : k;
       if (brute) {
         int64_t c = 0;
         for (int64_t j = 0; j < n; ++j) {
           double r2 = pair_r2(x, y, z, i, j, p, NULL, NULL, NULL);
           if (mode == 0 ? in_density(r2, h[i]) : (j != i && in_force(r2, h[i], h[j]))) ++c;
         }
-        cnt[i] = c;
+        cnt[k] = c;
       } else {
         if (neighbours_of(&t, i, h[i], mode, x, y, z, h, p, &l) != ORC_OK) {
 #pragma omp atomic write
           st = ORC_E_NOMEM;
         }
-        cnt[i] = l.n;
+        cnt[k] = l.n;
       }
     }
     free(l.idx);
   }
   offsets[0] = 0;
-  for (int64_t i = 0; i < n; ++i) offsets[i + 1] = offsets[i] + cnt[i];
-  int64_t total = offsets[n];
+  for (int64_t k = 0; k < nsel; ++k) offsets[k + 1] = offsets[k] + cnt[k];
+  int64_t total = offsets[nsel];
   if (st == ORC_OK && total <= cap && idx) {
 #pragma omp parallel
     {
       orc_list l = {0};
 #pragma omp for schedule(dynamic, 64)
-      for (int64_t i = 0; i < n; ++i) {
-        int64_t o = offsets[i];
+      for (int64_t k = 0; k < nsel; ++k) {
+        const int64_t i = sel ? sel[k] : k;
+        int64_t o = offsets[k];
         if (brute) {
           for (int64_t j = 0; j < n; ++j) {
             double r2 = pair_r2(x, y, z, i, j, p, NULL, NULL, NULL);
@@ -565,7 +570,7 @@ int64_t orc_neighbours(int64_t n, const double* x, const double* y,
 #pragma omp atomic write
             st = ORC_E_NOMEM;
           }
-          for (int64_t k = 0; k < l.n; ++k) idx[o + k] = l.idx[k];
+          for (int64_t q = 0; q < l.n; ++q) idx[o + q] = l.idx[q];
         }
       }
       free(l.idx);
@@ -576,6 +581,13 @@ int64_t orc_neighbours(int64_t n, const double* x, const double* y,
   if (st != ORC_OK) return st;
   if (total > cap) return ORC_E_OVERFLOW;
   return total;
+}
+
+int64_t orc_neighbours(int64_t n, const double* x, const double* y,
+                       const double* z, const double* h, const orc_params* p,
+                       int mode, int brute, int64_t* offsets, int64_t* idx,
+                       int64_t cap) {
+  return orc_neighbours_sel(n, x, y, z, h, p, mode, brute, NULL, n, offsets, idx, cap);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -675,11 +687,14 @@ static int dens_bisect(const dens_ctx* c, int64_t i, double h0, double tol,
   return ORC_OK;
 }
 
-int orc_density(int64_t n, const double* x, const double* y, const double* z,
-                const double* m, const double* h_in, const orc_params* p,
-                double* h_out, double* rho, double* omega, int64_t* nneigh,
-                int32_t* iters) {
+/* Density of the particles sel[0..nsel) (all particles if sel is NULL, then */
+/* nsel = n); outputs are packed: entry k belongs to particle sel[k].        */
+int orc_density_sel(int64_t n, const double* x, const double* y, const double* z,
+                    const double* m, const double* h_in, const orc_params* p,
+                    const int64_t* sel, int64_t nsel, double* h_out, double* rho,
+                    double* omega, int64_t* nneigh, int32_t* iters) {
   if (n <= 0) return ORC_E_ARG;
+  if (!sel) nsel = n;
   orc_stree t;
   int st = stree_build(&t, n, x, y, z, NULL, p);
   if (st != ORC_OK) return st;
@@ -692,7 +707,8 @@ int orc_density(int64_t n, const double* x, const double* y, const double* z,
     orc_list l = {0};
     dens_ctx c = {&t, x, y, z, m, p, &l};
 #pragma omp for schedule(dynamic, 64)
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t k = 0; k < nsel; ++k) {
+      const int64_t i = sel ? sel[k] : k;
       double h = h_in[i];
       int it = 0, done = 0, need_bisect = 0, s = ORC_OK;
       if (!(h > 0.0) || !(m[i] > 0.0)) s = ORC_E_ARG;
@@ -737,16 +753,23 @@ int orc_density(int64_t n, const double* x, const double* y, const double* z,
 #pragma omp atomic write
         status = s;
       }
-      h_out[i] = h;
-      rho[i] = S0;
-      omega[i] = 1.0 + h * S1 / (3.0 * S0);
-      if (nneigh) nneigh[i] = nnb;
-      if (iters) iters[i] = it;
+      h_out[k] = h;
+      rho[k] = S0;
+      omega[k] = 1.0 + h * S1 / (3.0 * S0);
+      if (nneigh) nneigh[k] = nnb;
+      if (iters) iters[k] = it;
     }
     free(l.idx);
   }
   stree_free(&t);
   return status;
+}
+
+int orc_density(int64_t n, const double* x, const double* y, const double* z,
+                const double* m, const double* h_in, const orc_params* p,
+                double* h_out, double* rho, double* omega, int64_t* nneigh,
+                int32_t* iters) {
+  return orc_density_sel(n, x, y, z, m, h_in, p, NULL, n, h_out, rho, omega, nneigh, iters);
 }
 
 /* Equation of state.  The paper names only the adiabatic index (Sect. 4),  */
@@ -782,14 +805,16 @@ void orc_eos(int64_t n, const double* rho, const double* u, const orc_params* p,
 /* printed term.  anorm_i / unorm_i are sums of pair-term magnitudes, used   */
 /* to normalise errors of a_i and du_i/dt.                                    */
 /* ------------------------------------------------------------------------ */
-int orc_force(int64_t n, const double* x, const double* y, const double* z,
-              const double* vx, const double* vy, const double* vz,
-              const double* m, const double* u, const double* h,
-              const double* rho, const double* omega, const double* P,
-              const double* cs, const orc_params* p, double* ax, double* ay,
-              double* az, double* dudt, double* vsig_dt, double* anorm,
-              double* unorm, int64_t* nneigh) {
+/* Force on the particles sel[0..nsel) (all if sel is NULL); outputs packed. */
+int orc_force_sel(int64_t n, const double* x, const double* y, const double* z,
+                  const double* vx, const double* vy, const double* vz,
+                  const double* m, const double* u, const double* h,
+                  const double* rho, const double* omega, const double* P,
+                  const double* cs, const orc_params* p, const int64_t* sel,
+                  int64_t nsel, double* ax, double* ay, double* az, double* dudt,
+                  double* vsig_dt, double* anorm, double* unorm, int64_t* nneigh) {
   if (n <= 0) return ORC_E_ARG;
+  if (!sel) nsel = n;
   orc_stree t;
   int st = stree_build(&t, n, x, y, z, h, p);
   if (st != ORC_OK) return st;
@@ -799,7 +824,8 @@ int orc_force(int64_t n, const double* x, const double* y, const double* z,
   {
     orc_list l = {0};
 #pragma omp for schedule(dynamic, 64)
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t k = 0; k < nsel; ++k) {
+      const int64_t i = sel ? sel[k] : k;
       int s = neighbours_of(&t, i, h[i], 1, x, y, z, h, p, &l);
       if (s != ORC_OK) {
 #pragma omp atomic write
@@ -849,19 +875,30 @@ int orc_force(int64_t n, const double* x, const double* y, const double* z,
         du_c += e3;
         un += fabs(e1) + fabs(e2) + fabs(e3);
       }
-      ax[i] = sx;
-      ay[i] = sy;
-      az[i] = sz;
-      dudt[i] = du_p + du_v + du_c;
-      vsig_dt[i] = vmax;
-      if (anorm) anorm[i] = an;
-      if (unorm) unorm[i] = un;
-      if (nneigh) nneigh[i] = l.n;
+      ax[k] = sx;
+      ay[k] = sy;
+      az[k] = sz;
+      dudt[k] = du_p + du_v + du_c;
+      vsig_dt[k] = vmax;
+      if (anorm) anorm[k] = an;
+      if (unorm) unorm[k] = un;
+      if (nneigh) nneigh[k] = l.n;
     }
     free(l.idx);
   }
   stree_free(&t);
   return status;
+}
+
+int orc_force(int64_t n, const double* x, const double* y, const double* z,
+              const double* vx, const double* vy, const double* vz,
+              const double* m, const double* u, const double* h,
+              const double* rho, const double* omega, const double* P,
+              const double* cs, const orc_params* p, double* ax, double* ay,
+              double* az, double* dudt, double* vsig_dt, double* anorm,
+              double* unorm, int64_t* nneigh) {
+  return orc_force_sel(n, x, y, z, vx, vy, vz, m, u, h, rho, omega, P, cs, p, NULL, n, ax, ay,
+                       az, dudt, vsig_dt, anorm, unorm, nneigh);
 }
 
 /* Courant step (Sect. 2.4, eq:timestep): dt = C_cour min_i h_i / vsig_i.   */

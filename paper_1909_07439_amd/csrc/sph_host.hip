@@ -170,7 +170,7 @@ sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ct
   k.alpha_u = P.alpha_u;
   k.c_cour = P.c_cour;
   k.fixed_passes = P.h_tol < 0.0 ? 1 : 0;
-  k.h_tol = (P.h_tol > 0.0) ? P.h_tol : (P.precision == SPH_PREC_MIXED ? 1e-6 : 1e-10);
+  k.h_tol = (P.h_tol > 0.0) ? P.h_tol : (P.precision == SPH_PREC_MIXED ? 2e-7 : 1e-14);
   k.max_iter = P.max_h_iter > 0 ? P.max_h_iter : 30;
   k.h_margin = P.h_margin > 1.0 ? P.h_margin : 1.1;
   k.n = 0;
@@ -442,10 +442,21 @@ sph_status sph_get_tree(sph_ctx* c, int64_t* n_nodes, int32_t* level, uint64_t* 
   HIPCHK(c, hipMemcpy(ch.data(), c->node_child, 4 * nn, hipMemcpyDeviceToHost));
   HIPCHK(c, hipMemcpy(nc.data(), c->node_nchild, 4 * nn, hipMemcpyDeviceToHost));
   HIPCHK(c, hipMemcpy(keys.data(), c->keys[0], 8 * (size_t)c->n, hipMemcpyDeviceToHost));
+  // inner-node counts: sums of the (contiguous) children, deepest first
+  std::vector<int64_t> cnt64(nn);
+  for (int64_t k = nn - 1; k >= 0; --k) {
+    if (nc[k] == 0) {
+      cnt64[k] = co[k];
+    } else {
+      int64_t t = 0;
+      for (int q = 0; q < nc[k]; ++q) t += cnt64[ch[k] + q];
+      cnt64[k] = t;
+    }
+  }
   for (int64_t k = 0; k < nn; ++k) {
     if (level) level[k] = lv[k];
     if (first) first[k] = fi[k];
-    if (count) count[k] = co[k];
+    if (count) count[k] = cnt64[k];
     if (child_first) child_first[k] = nc[k] ? ch[k] : -1;
     if (n_child) n_child[k] = nc[k];
     if (prefix) {

@@ -276,11 +276,26 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t* __restric
                                                         uint32_t* __restrict__ vout, int n,
                                                         int shift,
                                                         const uint32_t* __restrict__ off,
-                                                        int nblk) {
+                                                        int nblk, int fused) {
   __shared__ uint32_t run[256];
   __shared__ uint32_t wc[4][256];
+  __shared__ uint32_t lds4[4];
   const int tid = threadIdx.x, w = tid >> 6;
-  run[tid] = off[tid * nblk + blockIdx.x];
+  if (fused) {
+    // `off` holds the raw per-block digit counts: this block's start for
+    // digit d = (all keys with a smaller digit) + (digit d in earlier blocks)
+    uint32_t tot = 0, pre = 0;
+    const uint32_t* row = off + (int64_t)tid * nblk;
+    for (int b = 0; b < nblk; ++b) {
+      const uint32_t v = row[b];
+      tot += v;
+      pre += (b < (int)blockIdx.x) ? v : 0u;
+    }
+    uint32_t all;
+    run[tid] = block256_excl_scan(tot, lds4, &all) + pre;
+  } else {
+    run[tid] = off[tid * nblk + blockIdx.x];
+  }
   wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0;
   __syncthreads();
   const int base = blockIdx.x * kSortTile;
@@ -480,7 +495,9 @@ __global__ __launch_bounds__(256) void k_tree_emit(
     if (mem) {
       nlevel[idx] = l;
       nfirst[idx] = s;
-      ncount[idx] = cell_end(keys, n, s, l) - s;
+      // only leaves need their particle count (the walk reads particles of
+      // leaves only); inner counts are derived on the host for inspection
+      ncount[idx] = (l == ll) ? cell_end(keys, n, s, l) - s : 0;
       const int parent = (l == 0) ? -1 : (l == dsv ? par_at_d : prev);
       nparent[idx] = parent;
       nchild[idx] = -1;
@@ -670,6 +687,8 @@ constexpr int kFCap = 512;  // frontier entries per level
 constexpr int kLCap = 128;  // leaves per flush
 constexpr int kPMax = 128;  // pairs per particle slot
 constexpr int kTile = 256;  // candidates staged in LDS at a time
+constexpr int kSG = 8;      // groups sharing one super-group walk
+constexpr int kSLCap = 256; // leaves a super-group walk may collect
 
 __device__ __forceinline__ double fold(double d, double len, double half, int periodic) {
   if (periodic) {
@@ -700,6 +719,7 @@ struct WalkLds {
   int front[2][kFCap];
   int lfirst[kLCap];
   int lcnt[kLCap];
+  int lnode[kLCap];
   int loff[kLCap + 1];
 };
 
@@ -752,6 +772,7 @@ __device__ bool group_walk(const WalkNode* __restrict__ nodes, const GroupInfo& 
         const int pos = nleaf + popc64(lb & lanemask_lt());
         L.lfirst[pos] = nd.first;
         L.lcnt[pos] = nd.count;
+        L.lnode[pos] = L.front[cur][k];
       }
       nleaf += nl;
       const uint32_t nc = inner ? (uint32_t)nd.nchild : 0u;
@@ -772,6 +793,42 @@ __device__ bool group_walk(const WalkNode* __restrict__ nodes, const GroupInfo& 
   }
   if (nleaf > 0) flush(nleaf);
   return ok;
+}
+
+// The same leaf collection as group_walk, but over a list of leaves that a
+// walk for an enclosing region already found (super-group walk): every listed
+// leaf is tested against this group's box.
+template <typename RadiusFn, typename FlushFn>
+__device__ void list_walk(const WalkNode* __restrict__ nodes, const int* sl, int nsl,
+                          const GroupInfo& G, const KParams& kp, WalkLds& L, RadiusFn open_r,
+                          FlushFn flush) {
+  const int lane = threadIdx.x;
+  int nleaf = 0;
+  for (int base = 0; base < nsl; base += kWave) {
+    const int k = base + lane;
+    WalkNode nd;
+    bool open = false;
+    if (k < nsl) {
+      nd = nodes[sl[k]];
+      const double R = open_r(nd);
+      open = box_gap2(nd, G, kp) < R * R;
+    }
+    const uint64_t lb = ballot64(open);
+    const int nl = popc64(lb);
+    if (nleaf + nl > kLCap) {
+      flush(nleaf);
+      nleaf = 0;
+    }
+    if (open) {
+      const int pos = nleaf + popc64(lb & lanemask_lt());
+      L.lfirst[pos] = nd.first;
+      L.lcnt[pos] = nd.count;
+      L.lnode[pos] = sl[k];
+    }
+    nleaf += nl;
+    __syncthreads();
+  }
+  if (nleaf > 0) flush(nleaf);
 }
 
 // Exclusive scan of the leaf counts into L.loff[0..nleaf].
@@ -940,13 +997,17 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
   __shared__ TileOf<R> T;
   __shared__ R s_r[kPMax * GS];
   __shared__ R s_m[kPMax * GS];
+  __shared__ int s_sl[kSLCap];  // leaves found by the super-group walk
 
   const int lane = threadIdx.x;
   const int slot = lane / LPI, sub = lane % LPI;
   const int ng = ds->n_groups;
+  // waves take super-groups of kSG consecutive groups; each XCD a contiguous
+  // range of them, so that neighbouring groups share that XCD's L2
+  const int nsg = (ng + kSG - 1) / kSG;
   const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, nloc = gridDim.x >> 3;
-  const int chunk = (ng + 7) >> 3;
-  const int gbeg = xcd * chunk, gend = min(gbeg + chunk, ng);
+  const int chunk = (nsg + 7) >> 3;
+  const int sbeg = xcd * chunk, send = min(sbeg + chunk, nsg);
   const double margin = kp.h_margin;
   double minhalf = SPH_INF;
   for (int a = 0; a < 3; ++a)
@@ -962,7 +1023,45 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
   int walks = 0;
   bool grew = false;
 
-  for (int g = gbeg + local; g < gend; g += nloc) {
+  for (int sg = sbeg + local; sg < send; sg += nloc) {
+   const int g0 = sg * kSG, g1 = min(g0 + kSG, ng);
+   // ---- super-group box (union of the group boxes) and largest start h
+   GroupInfo SG;
+   {
+     const bool v = lane < g1 - g0;
+     GroupInfo Gk;
+     if (v) Gk = groups[g0 + lane];
+     for (int a = 0; a < 3; ++a) {
+       const double lo = wave_min_f64(v ? Gk.c[a] - Gk.w[a] : SPH_INF);
+       const double hi = wave_max_f64(v ? Gk.c[a] + Gk.w[a] : -SPH_INF);
+       SG.c[a] = 0.5 * (lo + hi);
+       SG.w[a] = fmax(hi - SG.c[a], SG.c[a] - lo);
+     }
+     SG.hmax = wave_max_f64(v ? Gk.hmax : 0.0);
+     SG.first = 0;
+     SG.count = 0;
+   }
+   // ---- one walk for the super-group: every leaf any of its groups can need
+   int nsl = 0;
+   bool sok = true;
+   {
+     const double hs = margin * SG.hmax;
+     auto sradius = [&](const WalkNode& nd) {
+       return 2.0 * fmax(hs, margin * (double)nd.hmax) * (1.0 + 4e-9);
+     };
+     auto sflush = [&](int nleaf) {
+       if (nsl + nleaf <= kSLCap) {
+         for (int q = lane; q < nleaf; q += kWave) s_sl[nsl + q] = L.lnode[q];
+       } else {
+         sok = false;
+       }
+       nsl += nleaf;
+       __syncthreads();
+     };
+     if (!group_walk(nodes, SG, kp, L, sradius, sflush)) sok = false;
+     ++walks;
+   }
+   for (int g = g0; g < g1; ++g) {
     const GroupInfo G = groups[g];
     const bool act = slot < G.count;
     const int i = G.first + (act ? slot : 0);
@@ -1046,7 +1145,12 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
           });
           __syncthreads();
         };
-        if (!group_walk(nodes, G, kp, L, radius, flush)) {
+        bool wok;
+        if (store && sok)
+          wok = true, list_walk(nodes, s_sl, nsl, G, kp, L, radius, flush);
+        else
+          wok = group_walk(nodes, G, kp, L, radius, flush);
+        if (!wok) {
           err |= kErrFrontier;
           failed = true;
         }
@@ -1122,17 +1226,21 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
         }
         ++walks;
       } else if (MIXED) {
+        // each lane sums its few terms in FP32; lanes are combined in FP64
         const float hinvf = (float)hinv;
         const float twohf = (float)(2.0 * h);
+        float s0 = 0.f, s1 = 0.f;
         for (int k = sub; k < npair; k += LPI) {
           const float r = (float)s_r[k * GS + slot], m = (float)s_m[k * GS + slot];
           const float q = r * hinvf;
           float f, df;
           m4_f_df<float>(q, f, df);
-          a0 += (double)(m * f);
-          a1 += (double)(m * (3.0f * f + q * df));
+          s0 = fmaf(m, f, s0);
+          s1 = fmaf(m, fmaf(q, df, 3.0f * f), s1);
           cnt += (r < twohf) ? 1u : 0u;
         }
+        a0 = (double)s0;
+        a1 = (double)s1;
       } else {
         const double twoh = 2.0 * h;
         for (int k = sub; k < npair; k += LPI) {
@@ -1153,13 +1261,16 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
       S1 = -a1 * h3 * hinv * kInvPi;
       nnb = cnt;
       sums += (act && sub == 0) ? (unsigned long long)(stream ? cnt : (uint32_t)npair) : 0ull;
-      if (ballot64(!conv) == 0ull) break;  // this was the sum at the converged h
+      // ---- decide: a slot is done when the h-rho relation holds at its
+      // current h to the tolerance (then S0, S1 above are its final sums);
+      // otherwise it takes a safeguarded Newton step and is summed again
+      bool moved = false;
       if (!conv) {
         const double t = kp.hfact * hinv;
         const double rh = mi * (t * t * t);
         const double f = S0 - rh;
         const double fp = S1 + 3.0 * rh * hinv;
-        double hn;
+        double hn = h;
         if (kp.fixed_passes) {
           hn = h - f / fp;
           if (!(fp > 0.0))
@@ -1169,37 +1280,42 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
           else if (hn < 0.8 * h)
             hn = 0.8 * h;
           conv = (nit + 1) >= 3;
+          moved = true;
+        } else if (fabs(f) <= 3.0 * kp.h_tol * rh) {
+          // |f| / f' <= tol h (f' = 3 rho_h Omega / h): converged at this h
+          conv = true;
         } else {
           if (f < 0.0)
             hlo = fmax(hlo, h);
           else
             hhi = fmin(hhi, h);
           hn = h - f / fp;
-          // a step below the tolerance is accepted as it is (it may sit on
-          // the bracket end the current h just became)
-          const bool small = (fp > 0.0) && fabs(hn - h) <= kp.h_tol * h;
-          const bool bad = !small && (!(fp > 0.0) || !(hn >= 0.8 * h) || !(hn <= 1.2 * h) ||
-                                      !(hn > hlo) || !(hn < hhi));
+          const bool bad = !(fp > 0.0) || !(hn >= 0.8 * h) || !(hn <= 1.2 * h) ||
+                           !(hn > hlo) || !(hn < hhi);
           if (bad) {
             if (hlo > 0.0 && hhi < SPH_INF)
               hn = 0.5 * (hlo + hhi);
             else
               hn = (f < 0.0) ? 1.2 * h : h / 1.2;
           }
-          conv = small || fabs(hn - h) <= kp.h_tol * h || f == 0.0;
-          if (f == 0.0) hn = h;
+          // a step at the rounding level of h: sum once more there and stop
+          conv = fabs(hn - h) <= 4e-16 * h;
+          moved = true;
         }
-        h = hn;
-        if (h > hlim) {
-          hlim = h * margin;
-          need = true;
-        }
-        ++nit;
-        if (nit > kp.max_iter) {
-          err |= kErrNoConv;
-          conv = true;
+        if (moved) {
+          h = hn;
+          if (h > hlim) {
+            hlim = h * margin;
+            need = true;
+          }
+          ++nit;
+          if (nit > kp.max_iter) {
+            err |= kErrNoConv;
+            conv = true;
+          }
         }
       }
+      if (ballot64(!conv || moved) == 0ull) break;  // every slot summed at its final h
     }
     it_max = max(it_max, nit + 1);
     if (act && !failed && h > h0 * margin) grew = true;
@@ -1264,6 +1380,7 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
         pairs_final += nnb;
       }
     }
+   }
   }
   // one set of atomics per wave
   const bool ballot_any = ballot64(grew) != 0ull;
@@ -1745,10 +1862,14 @@ hipError_t launch_sort(sph_ctx* c) {
     const int src = pass & 1, dst = src ^ 1;
     hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(256), 0, c->stream, c->keys[src], n, shift,
                        c->radix_cnt, nblk);
-    hipError_t e = scan_u32(c, c->radix_cnt, (int64_t)256 * nblk, c->scan_total, nullptr);
-    if (e != hipSuccess) return e;
+    const int fused = 0;  // measured: the separate scan is faster even for few blocks
+    if (!fused) {
+      hipError_t e = scan_u32(c, c->radix_cnt, (int64_t)256 * nblk, c->scan_total, nullptr);
+      if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(256), 0, c->stream, c->keys[src],
-                       c->vals[src], c->keys[dst], c->vals[dst], n, shift, c->radix_cnt, nblk);
+                       c->vals[src], c->keys[dst], c->vals[dst], n, shift, c->radix_cnt, nblk,
+                       fused);
   }
   return hipGetLastError();  // 8 passes: the result is back in buffer 0
 }

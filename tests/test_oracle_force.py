@@ -177,3 +177,17 @@ def test_two_particle_viscosity_worked_example():
     o = oracle.force(s, p)
     for k, v in g["expect"].items():
         np.testing.assert_allclose(o[k], v, rtol=1e-14, atol=1e-15, err_msg=k)
+
+
+def test_subset_evaluation_equals_full():
+    """The sampled evaluation used at large sizes computes exactly what the
+    full evaluation computes, for the sampled particles."""
+    c = inputs.lattice(12, jitter=0.3, velocities=True)
+    p = oracle.make_params(c)
+    full = oracle.evaluate(c, p)
+    sel = np.random.default_rng(2).choice(c["n"], 40, replace=False)
+    sub = oracle.evaluate_subset(c, p, sel)
+    for k in ("h", "rho", "omega", "P", "cs", "ax", "ay", "az", "dudt", "vsig_dt", "anorm",
+              "unorm"):
+        np.testing.assert_array_equal(sub[k], full[k][sel], err_msg=k)
+    np.testing.assert_array_equal(sub["nneigh"], full["nneigh"][sel])
