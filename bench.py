@@ -9,9 +9,11 @@ the same steps are also timed in FP64 to give the mixed/FP64 ratio.
 
 Prints ONE JSON line (the last line of stdout).  ``value`` is
 particle-updates/s = N * steps / wall time of the timed steps, with the state
-resident in HBM.  ``roofline`` is for the force kernel, from its algorithmic
-FLOPs and its average launch time measured with HIP events on the library
-stream; ``cpu_baseline`` times the FP64 CPU oracle on the host cores.
+resident in HBM.  ``roofline`` is for the kernel with the longer launches
+(the density kernel, which also walks the tree, or the force kernel), from
+its algorithmic FLOPs and its average launch time measured with HIP events on
+the library stream; ``second_kernel_roofline`` is the other one.
+``cpu_baseline`` times the FP64 CPU oracle on the host cores.
 """
 from __future__ import annotations
 
@@ -77,6 +79,7 @@ def run(cfg, precision, steps, warmup):
     torch.cuda.synchronize()
     sph.sph_check(ctx)
     sph.sph_timings(ctx)  # drop the warm-up events
+    st0 = sph.sph_stats(ctx)
     t0 = time.perf_counter()
     for _ in range(steps):
         sph.sph_step(ctx, parts, 0.0)
@@ -85,6 +88,12 @@ def run(cfg, precision, steps, warmup):
     sph.sph_check(ctx)
     tim = sph.sph_timings(ctx)
     st = sph.sph_stats(ctx)
+    # work per launch over exactly the timed launches
+    nd = st["density_launches"] - st0["density_launches"]
+    nf = st["force_launches"] - st0["force_launches"]
+    st["density_pair_sums_per_launch"] = \
+        (st["total_density_pair_sums"] - st0["total_density_pair_sums"]) / max(nd, 1)
+    st["force_pairs_per_launch"] = (st["total_force_pairs"] - st0["total_force_pairs"]) / max(nf, 1)
     e = sph.sph_reduce(ctx, parts)
     ctx.close()
     wall = t1 - t0
@@ -92,6 +101,60 @@ def run(cfg, precision, steps, warmup):
     order = np.argsort(init["id"])
     return dict(wall=wall, rate=n * steps / wall, ms_per_step=1e3 * wall / steps, timings=tim,
                 stats=st, energy=e, init={k: v[order] for k, v in init.items()})
+
+
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1909_07439_amd", "csrc", "sph_kernels.hip")
+
+
+def source_digest() -> str:
+    import hashlib
+
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_record(kernel: str, cfg, precision: str):
+    """HBM bytes per launch of ``kernel`` from the committed PMC summary for
+    this workload, or None when there is none or when the kernel source has
+    changed since its counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{precision}_{cfg['workload']}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if ":" in line and not line.startswith((" ", "#")):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    if rec.get("kernel_source_sha256") != source_digest():
+        return None
+    try:
+        return float(rec["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(mib: int):
+    """A plain streaming kernel of known size for scaling the PMC byte
+    counters: torch.neg over a float64 buffer reads and writes ``mib`` MiB."""
+    import torch
+
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    print(f"[bench] copy calibration: torch.neg over {mib} MiB in, {mib} MiB out, 3 launches",
+          flush=True)
+
+
+def roofline(kernel, flops, launch_ms, units, flops_per_unit, traffic):
+    tf = flops / (launch_ms * 1e-3) / 1e12 if launch_ms > 0 else 0.0
+    return {"kernel": kernel, "bound": "alu", "achieved": round(tf, 4), "peak": ALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(tf / ALU_PEAK_TFLOPS, 5), "traffic": traffic,
+            "frac_of_packed_fp32_peak": round(tf / PACKED_FP32_PEAK_TFLOPS, 5),
+            "launch_ms": round(launch_ms, 5), "units_per_launch": units,
+            "flops_per_unit": flops_per_unit}
 
 
 def cpu_baseline(cfg, budget_s=12.0):
@@ -121,6 +184,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-group", type=int, default=None, help="particles per walk group")
     ap.add_argument("--n-leaf", type=int, default=None, help="particles per tree leaf")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the timed steps, run a plain streaming kernel over MIB MiB "
+                         "(scale for PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no "
@@ -149,18 +215,17 @@ def main():
         print(f"[bench] fp64: {other['rate']:.4e} upd/s, {other['ms_per_step']:.3f} ms/step, "
               f"phases {other['timings']}", flush=True)
     tim, st = main_run["timings"], main_run["stats"]
-    t_force = tim["force"] * 1e-3
-    t_dens = tim["density"] * 1e-3
-    force_tf = FORCE_FLOPS_PER_PAIR * st["force_pairs"] / t_force / 1e12 if t_force > 0 else 0.0
-    dens_tf = DENSITY_FLOPS_PER_PAIR_SUM * st["density_pair_sums"] / t_dens / 1e12 \
-        if t_dens > 0 else 0.0
-    roof = {"kernel": "k_force<mixed>" if prec == sph.SPH_PREC_MIXED else "k_force<fp64>",
-            "bound": "alu", "achieved": round(force_tf, 4), "peak": ALU_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(force_tf / ALU_PEAK_TFLOPS, 5), "traffic": None,
-            "frac_of_packed_fp32_peak": round(force_tf / PACKED_FP32_PEAK_TFLOPS, 5),
-            "launch_ms": round(tim["force"], 5), "pairs_per_launch": st["force_pairs"],
-            "flops_per_pair": FORCE_FLOPS_PER_PAIR}
-    inter = (st["density_pair_sums"] + st["force_pairs"]) / (main_run["ms_per_step"] * 1e-3)
+    tag = "mixed" if prec == sph.SPH_PREC_MIXED else "fp64"
+    fpl, dpl = st["force_pairs_per_launch"], st["density_pair_sums_per_launch"]
+    force = roofline(f"k_force<{tag}>", FORCE_FLOPS_PER_PAIR * fpl, tim["force"],
+                     {"force_pairs": fpl}, FORCE_FLOPS_PER_PAIR,
+                     traffic_record("k_force", cfg, tag))
+    dens = roofline(f"k_density<{tag}>", DENSITY_FLOPS_PER_PAIR_SUM * dpl,
+                    tim["density"], {"density_pair_sums": dpl},
+                    DENSITY_FLOPS_PER_PAIR_SUM, traffic_record("k_density", cfg, tag))
+    # the dominant kernel (longer average launch) carries the headline roofline
+    roof, second = (dens, force) if tim["density"] >= tim["force"] else (force, dens)
+    inter = (dpl + fpl) / (main_run["ms_per_step"] * 1e-3)
     out = {
         "metric": METRIC,
         "value": main_run["rate"],
@@ -178,10 +243,7 @@ def main():
                    "precision": args.precision, "kernel": "M4", "hfact": cfg["hfact"],
                    "n_leaf": cfg["n_leaf"], "n_group": cfg["n_group"]},
         "roofline": roof,
-        "density_roofline": {"bound": "alu", "achieved": round(dens_tf, 4),
-                             "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                             "frac": round(dens_tf / ALU_PEAK_TFLOPS, 5),
-                             "launch_ms": round(tim["density"], 5)},
+        "second_kernel_roofline": second,
         "phase_ms": {k: round(v, 5) for k, v in tim.items()},
         "interactions_per_s": inter,
         "true_pairs_per_particle": {"density": st["density_pairs"] / cfg["n"],
@@ -201,6 +263,8 @@ def main():
             "a_max_over_rms_a": float(max(np.max(np.abs(a[k] - b[k])) for k in ("ax", "ay", "az"))
                                       / scale),
         }
+    if args.copy_calibration > 0:
+        copy_calibration(args.copy_calibration)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)

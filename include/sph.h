@@ -177,18 +177,24 @@ sph_status sph_get_groups(sph_ctx* ctx, int64_t* n_groups, int64_t* first, int64
 sph_status sph_neighbours(sph_ctx* ctx, const sph_particles* p, int32_t mode, int64_t* offsets,
                           int32_t* idx, int64_t cap);
 
-/* Per-launch timing of the last call of each phase, in milliseconds, from
-   HIP events on the library stream: out[0..7] = {keys+sort, permute, tree,
-   density, force, integrate, total step, reserved}.  Synchronises. */
+/* Mean duration of the launches of each phase since the previous call, in
+   milliseconds, from HIP events recorded on the library stream around each
+   phase (at most 1024 launches per phase are kept): out[0..7] = {keys+sort,
+   permute, tree, density, force, integrate, total step, reserved}.  Each of
+   the density, force and integrate phases brackets exactly one kernel.
+   Clears the kept events.  Synchronises. */
 sph_status sph_timings(sph_ctx* ctx, double out[8]);
 
-/* Counters of the work since the last sph_build_tree / sph_step (for
-   throughput accounting): out[0..9] = {tree nodes, groups, most density sums
-   any group needed, true density neighbours (r < 2h, self included) at the
-   converged h, force pairs, density pair terms summed over all passes,
+/* Counters of the work done (for throughput accounting).  out[0..9] refer
+   to the last sph_build_tree / sph_step: {tree nodes, groups, most density
+   sums any group needed, true density neighbours (r < 2h, self included) at
+   the converged h, force pairs, density pair terms summed over all passes,
    density candidate tests, force candidate tests, walks done by the density
-   pass, device error word}.  Synchronises. */
-sph_status sph_stats(sph_ctx* ctx, int64_t out[10]);
+   pass, device error word}.  out[10..13] are running totals since
+   sph_create: {density pair terms, force pairs, density launches, force
+   launches}; differences of two calls give the work of the launches in
+   between.  Synchronises. */
+sph_status sph_stats(sph_ctx* ctx, int64_t out[14]);
 
 /* Human-readable description of the last failure of this context. */
 const char* sph_last_error(const sph_ctx* ctx);

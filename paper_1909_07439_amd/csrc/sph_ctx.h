@@ -91,5 +91,7 @@ struct sph_ctx {
   sph::DevState* hs = nullptr;  // pinned host mirror
   hipEvent_t ev[8] = {};
   bool timing = true;
+  int64_t density_launches = 0;  // launches of the density kernel so far
+  int64_t force_launches = 0;    // launches of the force kernel so far
   std::string err;
 };

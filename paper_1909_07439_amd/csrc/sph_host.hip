@@ -340,6 +340,7 @@ sph_status sph_density(sph_ctx* c, sph_particles* p, int32_t* iters_out) {
   ph_begin(c, kPhDensity);
   HIPCHK(c, sph::launch_density(c, p));
   ph_end(c, kPhDensity);
+  ++c->density_launches;
   if (iters_out) {
     st = sync_state(c, true);
     *iters_out = c->hs->max_iter;
@@ -358,6 +359,7 @@ sph_status sph_force(sph_ctx* c, sph_particles* p, double* dt_next_out) {
   ph_begin(c, kPhForce);
   HIPCHK(c, sph::launch_force(c, p, false));
   ph_end(c, kPhForce);
+  ++c->force_launches;
   if (dt_next_out) {
     st = sync_state(c, true);
     *dt_next_out = sph::dec_f64(c->hs->dt_min_enc);
@@ -380,11 +382,13 @@ sph_status sph_step(sph_ctx* c, sph_particles* p, double dt, double* dt_next_out
   ph_begin(c, kPhDensity);
   HIPCHK(c, sph::launch_density(c, p));
   ph_end(c, kPhDensity);
+  ++c->density_launches;
   HIPCHK(c, sph::launch_node_h(c, p));
   HIPCHK(c, sph::launch_force_reset(c));
   ph_begin(c, kPhForce);
   HIPCHK(c, sph::launch_force(c, p, true));
   ph_end(c, kPhForce);
+  ++c->force_launches;
   ph_begin(c, kPhIntegrate);
   HIPCHK(c, sph::launch_correct(c, p));
   ph_end(c, kPhIntegrate);
@@ -538,7 +542,7 @@ sph_status sph_timings(sph_ctx* c, double out[8]) {
   return SPH_OK;
 }
 
-sph_status sph_stats(sph_ctx* c, int64_t out[10]) {
+sph_status sph_stats(sph_ctx* c, int64_t out[14]) {
   if (!c || !out) return SPH_E_ARG;
   HIPCHK(c, hipMemcpyAsync(c->hs, c->ds, sizeof(sph::DevState), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -553,6 +557,10 @@ sph_status sph_stats(sph_ctx* c, int64_t out[10]) {
   out[7] = (int64_t)s.n_cand_force;
   out[8] = s.n_rewalk;
   out[9] = s.err;
+  out[10] = (int64_t)s.tot_sums_density;
+  out[11] = (int64_t)s.tot_pairs_force;
+  out[12] = c->density_launches;
+  out[13] = c->force_launches;
   return SPH_OK;
 }
 

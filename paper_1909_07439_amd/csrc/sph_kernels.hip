@@ -1400,6 +1400,7 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
     atomicMax(&ds->max_iter, it_max);
     atomicAdd(&ds->n_pairs_density, pf);
     atomicAdd(&ds->n_sums_density, sums);
+    atomicAdd(&ds->tot_sums_density, sums);
     atomicAdd(&ds->n_cand_density, cd);
     atomicAdd(&ds->n_rewalk, walks);
     if (ballot_any) atomicMax(&ds->leaf_state, 2);
@@ -1651,6 +1652,7 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
   if (lane == 0) {
     if (b) atomicOr(&ds->err, eall);
     atomicAdd(&ds->n_pairs_force, pf);
+    atomicAdd(&ds->tot_pairs_force, pf);
     atomicAdd(&ds->n_cand_force, cd);
     if (dm < SPH_INF) atomicMin(&ds->dt_min_enc, enc_f64(dm));
   }

@@ -187,7 +187,7 @@ def turbulent_box(n_side: int = 256, jitter: float = 0.05, kmin: float = 1.0,
     dot = (comps[0] * KX + comps[1] * KY + comps[2] * KZ) / K2s
     comps = [comps[0] - dot * KX, comps[1] - dot * KY, comps[2] - dot * KZ]
     del dot, K2s, KX, KY, KZ, K2, kk, shell, amp
-    vel = [np.fft.irfftn(c, s=(n_side, n_side, n_side)).ravel() for c in comps]
+    vel = [np.fft.irfftn(c, s=(n_side, n_side, n_side), axes=(0, 1, 2)).ravel() for c in comps]
     del comps
     rms = math.sqrt(float(np.mean(vel[0] ** 2 + vel[1] ** 2 + vel[2] ** 2)))
     vel = [v * (mach / rms) for v in vel]

@@ -295,10 +295,11 @@ def sph_timings(ctx: Context) -> dict:
 
 STATS = ("n_nodes", "n_groups", "max_density_sums", "density_pairs", "force_pairs",
          "density_pair_sums", "density_candidates", "force_candidates", "density_walks",
-         "error_word")
+         "error_word", "total_density_pair_sums", "total_force_pairs", "density_launches",
+         "force_launches")
 
 
 def sph_stats(ctx: Context) -> dict:
-    out = (ctypes.c_int64 * 10)()
+    out = (ctypes.c_int64 * len(STATS))()
     _check(ctx.h, ctx.lib.sph_stats(ctx.h, out), "sph_stats")
     return {k: int(out[i]) for i, k in enumerate(STATS)}
