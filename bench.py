@@ -249,6 +249,8 @@ def main():
         "true_pairs_per_particle": {"density": st["density_pairs"] / cfg["n"],
                                     "force": st["force_pairs"] / cfg["n"]},
         "density_sums_per_step_max": st["max_density_sums"],
+        "candidates_per_pair": {"density": st["density_candidates"] / max(st["density_pairs"], 1),
+                                "force": st["force_candidates"] / max(st["force_pairs"], 1)},
     }
     if other is not None:
         out["fp64_value"] = other["rate"]

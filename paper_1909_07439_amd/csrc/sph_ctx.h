@@ -10,6 +10,7 @@ constexpr int kMaxFields = 20;
 constexpr int kSortTile = 2048;  // keys per radix-sort block (256 threads x 8)
 constexpr int kTreeTile = 256;   // particles per tree block
 constexpr int kScanTile = 2048;  // elements per scan block
+constexpr int kChunk = 256;     // particles per chunk box of the node-box reduction
 
 // Per-particle data the force loop reads for a neighbour j (written by the
 // density pass once h, rho, Omega are final).
@@ -70,8 +71,7 @@ struct sph_ctx {
   int32_t* node_parent = nullptr;
   int32_t* node_child = nullptr;
   int32_t* node_nchild = nullptr;
-  unsigned long long* node_bb = nullptr;  // 6 per node: min xyz, max xyz (ordered encodings)
-  unsigned long long* node_hm = nullptr;  // 1 per node
+  double* chunk_box = nullptr;  // 8 per chunk of 256 sorted particles: lo xyz, hi xyz, h_max
   sph::WalkNode* wnode = nullptr;
   int32_t* grp_first = nullptr;
   int32_t* grp_count = nullptr;

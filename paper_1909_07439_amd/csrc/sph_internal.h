@@ -39,6 +39,8 @@ struct DevState {
   unsigned long long n_cand_force;     // candidate tests in the force walks
   int32_t n_rewalk;
   int32_t leaf_state;  // 0: no stored leaf lists, 1: valid for the force, 2: some h outgrew them
+  int32_t lists_missing;  // some group's leaf list could not be stored (its force pass walks)
+  int32_t pad0;
   unsigned long long tot_sums_density;  // n_sums_density summed over every launch so far
   unsigned long long tot_pairs_force;   // n_pairs_force summed over every launch so far
 };

@@ -157,8 +157,68 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* in, uint32_t
   }
 }
 
+// Exclusive scan of up to kScanSingleMax uint32 (n a multiple of 4, data
+// 16-byte aligned) by one block of 1024 threads in one launch: every thread
+// owns a contiguous run of at most 16 uint4, loaded all at once.
+constexpr int kScanSingleMax = 1024 * 64;
+
+__global__ __launch_bounds__(1024) void k_scan_single(uint32_t* __restrict__ data, int n,
+                                                       uint32_t* __restrict__ total_out,
+                                                       int32_t* __restrict__ total_i32) {
+  __shared__ uint32_t lds[16];
+  const int t = threadIdx.x;
+  const int q = (n + 4095) / 4096;  // uint4 per thread, <= 16
+  const int nq = n >> 2;
+  uint4* d4 = reinterpret_cast<uint4*>(data);
+  uint4 v[16];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int idx = t * q + k;
+    v[k] = (k < q && idx < nq) ? d4[idx] : make_uint4(0u, 0u, 0u, 0u);
+    s += v[k].x + v[k].y + v[k].z + v[k].w;
+  }
+  const uint32_t inc = wave_incl_scan_u32(s);
+  const int w = t >> 6, lane = t & 63;
+  if (lane == 63) lds[w] = inc;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const uint32_t x = lds[k];
+    off += (k < w) ? x : 0u;
+    tot += x;
+  }
+  off += inc - s;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int idx = t * q + k;
+    if (k < q && idx < nq) {
+      uint4 o;
+      o.x = off;
+      off += v[k].x;
+      o.y = off;
+      off += v[k].y;
+      o.z = off;
+      off += v[k].z;
+      o.w = off;
+      off += v[k].w;
+      d4[idx] = o;
+    }
+  }
+  if (t == 0) {
+    if (total_out) *total_out = tot;
+    if (total_i32) *total_i32 = (int32_t)tot;
+  }
+}
+
 static hipError_t scan_u32(sph_ctx* c, uint32_t* data, int64_t n, uint32_t* total,
                            int32_t* total_i32) {
+  if (n > 0 && n <= kScanSingleMax && (n & 3) == 0 && (reinterpret_cast<uintptr_t>(data) & 15) == 0) {
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, c->stream, data, (int)n, total,
+                       total_i32);
+    return hipGetLastError();
+  }
   const int nb = (int)((n + kScanTile - 1) / kScanTile);
   if (nb == 0) return hipSuccess;
   hipLaunchKernelGGL(k_scan_partials, dim3(nb), dim3(256), 0, c->stream, data, n, c->scan_part);
@@ -534,78 +594,85 @@ __global__ void k_tree_guard(DevState* ds, int64_t node_cap) {
   }
 }
 
-// ---- node boxes and largest h: leaves reduce their particles, then push
-// the result up with atomic min/max; a push stops at the first ancestor
-// that already holds a value at least as extreme (whoever wrote that value
-// is carrying it further up).  Min/max are order independent, so the result
-// is exact and deterministic.
-__global__ __launch_bounds__(256) void k_node_init(unsigned long long* __restrict__ bb,
-                                                    unsigned long long* __restrict__ hm,
-                                                    const DevState* __restrict__ ds, int do_bb) {
-  const int nn = ds->n_nodes;
-  const unsigned long long lo = enc_f64(SPH_INF), hi = enc_f64(-SPH_INF), z = enc_f64(0.0);
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nn; k += gridDim.x * blockDim.x) {
-    if (do_bb) {
-      bb[6 * (int64_t)k + 0] = lo;
-      bb[6 * (int64_t)k + 1] = lo;
-      bb[6 * (int64_t)k + 2] = lo;
-      bb[6 * (int64_t)k + 3] = hi;
-      bb[6 * (int64_t)k + 4] = hi;
-      bb[6 * (int64_t)k + 5] = hi;
+// ---- node and group boxes and largest h -----------------------------------
+// Every node and group covers a contiguous range of the sorted particles.
+// k_chunk_boxes reduces fixed chunks of kChunk particles; k_range_boxes then
+// gives each node or group to one wavefront, which reduces the particles of
+// its range directly and takes every whole chunk inside the range from the
+// chunk boxes.  No atomics; min/max are exact, so the boxes are exactly the
+// tight boxes of the particles.
+//
+// do_bb == 0 is the h-only refresh after the density; it is skipped (the
+// kernels return at once) while the force will replay the stored leaf lists,
+// which need neither node nor group h_max.
+__device__ __forceinline__ bool h_refresh_needed(const DevState* ds, int do_bb) {
+  return do_bb || ds->leaf_state != 1 || ds->lists_missing != 0;
+}
+
+struct Box7 {
+  double lo[3], hi[3], hm;
+};
+
+__device__ __forceinline__ void box_empty(Box7& b) {
+  for (int a = 0; a < 3; ++a) {
+    b.lo[a] = SPH_INF;
+    b.hi[a] = -SPH_INF;
+  }
+  b.hm = 0.0;
+}
+
+__device__ __forceinline__ void wave_box(Box7& b, int do_bb) {
+  if (do_bb)
+    for (int a = 0; a < 3; ++a) {
+      b.lo[a] = wave_min_f64(b.lo[a]);
+      b.hi[a] = wave_max_f64(b.hi[a]);
     }
-    hm[k] = z;
+  b.hm = wave_max_f64(b.hm);
+}
+
+// Lane-partial box of particles [a, e), lanes striding by 64.
+__device__ __forceinline__ void add_particles(Box7& b, int a, int e, const double* __restrict__ x,
+                                              const double* __restrict__ y,
+                                              const double* __restrict__ z,
+                                              const double* __restrict__ h, int do_bb) {
+#pragma unroll 4
+  for (int s = a + lane_id(); s < e; s += kWave) {
+    if (do_bb) {
+      const double px = x[s], py = y[s], pz = z[s];
+      b.lo[0] = fmin(b.lo[0], px);
+      b.hi[0] = fmax(b.hi[0], px);
+      b.lo[1] = fmin(b.lo[1], py);
+      b.hi[1] = fmax(b.hi[1], py);
+      b.lo[2] = fmin(b.lo[2], pz);
+      b.hi[2] = fmax(b.hi[2], pz);
+    }
+    b.hm = fmax(b.hm, h[s]);
   }
 }
 
-__global__ __launch_bounds__(256) void k_node_leaves(
-    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
-    const double* __restrict__ h, const int32_t* __restrict__ nfirst,
-    const int32_t* __restrict__ ncount, const int32_t* __restrict__ nparent,
-    const int32_t* __restrict__ nnchild, unsigned long long* __restrict__ bb,
-    unsigned long long* __restrict__ hm, const DevState* __restrict__ ds, int do_bb) {
-  const int nn = ds->n_nodes;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nn; k += gridDim.x * blockDim.x) {
-    if (nnchild[k] != 0) continue;
-    const int f = nfirst[k], e = f + ncount[k];
-    double lo0 = SPH_INF, lo1 = SPH_INF, lo2 = SPH_INF;
-    double hi0 = -SPH_INF, hi1 = -SPH_INF, hi2 = -SPH_INF, hmx = 0.0;
-    for (int s = f; s < e; ++s) {
-      if (do_bb) {
-        const double a = x[s], b = y[s], cc = z[s];
-        lo0 = fmin(lo0, a);
-        hi0 = fmax(hi0, a);
-        lo1 = fmin(lo1, b);
-        hi1 = fmax(hi1, b);
-        lo2 = fmin(lo2, cc);
-        hi2 = fmax(hi2, cc);
-      }
-      if (h) hmx = fmax(hmx, h[s]);
-    }
-    unsigned long long e6[6] = {enc_f64(lo0), enc_f64(lo1), enc_f64(lo2),
-                                enc_f64(hi0), enc_f64(hi1), enc_f64(hi2)};
-    const unsigned long long eh = enc_f64(hmx);
-    if (do_bb)
-      for (int q = 0; q < 6; ++q) bb[6 * (int64_t)k + q] = e6[q];
-    hm[k] = eh;
-    int p = nparent[k];
-    while (p >= 0 && p < nn) {
-      bool improved = false;
-      if (do_bb) {
-        for (int q = 0; q < 3; ++q) {
-          const unsigned long long old = atomicMin(&bb[6 * (int64_t)p + q], e6[q]);
-          improved |= e6[q] < old;
+// cb: 8 doubles per chunk (lo xyz, hi xyz, h_max, unused).
+__global__ __launch_bounds__(256) void k_chunk_boxes(const double* __restrict__ x,
+                                                      const double* __restrict__ y,
+                                                      const double* __restrict__ z,
+                                                      const double* __restrict__ h, int n,
+                                                      double* __restrict__ cb,
+                                                      const DevState* __restrict__ ds, int do_bb) {
+  if (!h_refresh_needed(ds, do_bb)) return;
+  const int nch = (n + kChunk - 1) / kChunk;
+  const int wpb = blockDim.x / kWave;
+  for (int c = blockIdx.x * wpb + (int)(threadIdx.x / kWave); c < nch; c += gridDim.x * wpb) {
+    Box7 b;
+    box_empty(b);
+    add_particles(b, c * kChunk, min(n, (c + 1) * kChunk), x, y, z, h, do_bb);
+    wave_box(b, do_bb);
+    if (lane_id() == 0) {
+      double* o = cb + 8 * (int64_t)c;
+      if (do_bb)
+        for (int a = 0; a < 3; ++a) {
+          o[a] = b.lo[a];
+          o[3 + a] = b.hi[a];
         }
-        for (int q = 3; q < 6; ++q) {
-          const unsigned long long old = atomicMax(&bb[6 * (int64_t)p + q], e6[q]);
-          improved |= e6[q] > old;
-        }
-      }
-      if (h) {
-        const unsigned long long old = atomicMax(&hm[p], eh);
-        improved |= eh > old;
-      }
-      if (!improved) break;
-      p = nparent[p];
+      o[6] = b.hm;
     }
   }
 }
@@ -616,62 +683,99 @@ __device__ __forceinline__ float f32_up(double v) {
   return f;
 }
 
-__global__ __launch_bounds__(256) void k_node_finalize(
-    const unsigned long long* __restrict__ bb, const unsigned long long* __restrict__ hm,
+// Items 0..n_nodes-1 are nodes (WalkNode written), the rest groups
+// (GroupInfo written).  An inner node's range ends where its next sibling
+// starts, or, for a last child, where its parent's range ends.
+__global__ __launch_bounds__(256) void k_range_boxes(
+    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
+    const double* __restrict__ h, int n, const double* __restrict__ cb,
     const int32_t* __restrict__ nfirst, const int32_t* __restrict__ ncount,
-    const int32_t* __restrict__ nchild, const int32_t* __restrict__ nnchild,
-    WalkNode* __restrict__ wn, const DevState* __restrict__ ds, int do_bb) {
-  const int nn = ds->n_nodes;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nn; k += gridDim.x * blockDim.x) {
-    WalkNode w = wn[k];
-    if (do_bb) {
-      for (int a = 0; a < 3; ++a) {
-        const double lo = dec_f64(bb[6 * (int64_t)k + a]);
-        const double hi = dec_f64(bb[6 * (int64_t)k + 3 + a]);
-        const double c = 0.5 * (lo + hi);
-        w.c[a] = c;
-        w.w[a] = f32_up(fmax(hi - c, c - lo));
+    const int32_t* __restrict__ nparent, const int32_t* __restrict__ nchild,
+    const int32_t* __restrict__ nnchild, WalkNode* __restrict__ wn,
+    const int32_t* __restrict__ gfirst, const int32_t* __restrict__ gcount,
+    GroupInfo* __restrict__ gi, const DevState* __restrict__ ds, int do_bb) {
+  if (!h_refresh_needed(ds, do_bb)) return;
+  const int nn = ds->n_nodes, ng = ds->n_groups;
+  const int wpb = blockDim.x / kWave;
+  for (int it = blockIdx.x * wpb + (int)(threadIdx.x / kWave); it < nn + ng;
+       it += gridDim.x * wpb) {
+    const bool is_node = it < nn;
+    int f, e, nc = 0;
+    if (is_node) {
+      f = nfirst[it];
+      nc = nnchild[it];
+      if (nc == 0) {
+        e = f + ncount[it];
+      } else {
+        e = n;
+        int k = it;
+        while (k > 0) {
+          const int p = nparent[k];
+          if (p < 0) break;
+          if (k + 1 < nchild[p] + nnchild[p]) {
+            e = nfirst[k + 1];
+            break;
+          }
+          k = p;
+        }
       }
-      w.first = nfirst[k];
-      w.count = ncount[k];
-      w.child = nnchild[k] ? nchild[k] : -1;
-      w.nchild = nnchild[k];
+    } else {
+      f = gfirst[it - nn];
+      e = f + gcount[it - nn];
     }
-    w.hmax = f32_up(dec_f64(hm[k]));
-    wn[k] = w;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_group_info(const double* __restrict__ x,
-                                                     const double* __restrict__ y,
-                                                     const double* __restrict__ z,
-                                                     const double* __restrict__ h,
-                                                     const int32_t* __restrict__ gfirst,
-                                                     const int32_t* __restrict__ gcount,
-                                                     GroupInfo* __restrict__ gi,
-                                                     const DevState* __restrict__ ds) {
-  const int ng = ds->n_groups;
-  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += gridDim.x * blockDim.x) {
-    const int f = gfirst[g], e = f + gcount[g];
-    double lo[3] = {SPH_INF, SPH_INF, SPH_INF}, hi[3] = {-SPH_INF, -SPH_INF, -SPH_INF};
-    double hmx = 0.0;
-    for (int s = f; s < e; ++s) {
-      const double c[3] = {x[s], y[s], z[s]};
-      for (int a = 0; a < 3; ++a) {
-        lo[a] = fmin(lo[a], c[a]);
-        hi[a] = fmax(hi[a], c[a]);
+    Box7 b;
+    box_empty(b);
+    const int c0 = (f + kChunk - 1) / kChunk, c1 = e / kChunk;
+    if (c1 > c0) {
+      add_particles(b, f, c0 * kChunk, x, y, z, h, do_bb);
+      for (int c = c0 + lane_id(); c < c1; c += kWave) {
+        const double* q = cb + 8 * (int64_t)c;
+        if (do_bb)
+          for (int a = 0; a < 3; ++a) {
+            b.lo[a] = fmin(b.lo[a], q[a]);
+            b.hi[a] = fmax(b.hi[a], q[3 + a]);
+          }
+        b.hm = fmax(b.hm, q[6]);
       }
-      hmx = fmax(hmx, h[s]);
+      add_particles(b, c1 * kChunk, e, x, y, z, h, do_bb);
+    } else {
+      add_particles(b, f, e, x, y, z, h, do_bb);
     }
-    GroupInfo G;
-    for (int a = 0; a < 3; ++a) {
-      G.c[a] = 0.5 * (lo[a] + hi[a]);
-      G.w[a] = fmax(hi[a] - G.c[a], G.c[a] - lo[a]);
+    wave_box(b, do_bb);
+    if (lane_id() == 0) {
+      if (is_node) {
+        if (do_bb) {
+          WalkNode w;
+          for (int a = 0; a < 3; ++a) {
+            const double c = 0.5 * (b.lo[a] + b.hi[a]);
+            w.c[a] = c;
+            w.w[a] = f32_up(fmax(b.hi[a] - c, c - b.lo[a]));
+          }
+          w.hmax = f32_up(b.hm);
+          w.first = f;
+          w.count = e - f;
+          w.child = nc ? nchild[it] : -1;
+          w.nchild = nc;
+          wn[it] = w;
+        } else {
+          wn[it].hmax = f32_up(b.hm);
+        }
+      } else {
+        if (do_bb) {
+          GroupInfo G;
+          for (int a = 0; a < 3; ++a) {
+            G.c[a] = 0.5 * (b.lo[a] + b.hi[a]);
+            G.w[a] = fmax(b.hi[a] - G.c[a], G.c[a] - b.lo[a]);
+          }
+          G.hmax = b.hm;
+          G.first = f;
+          G.count = e - f;
+          gi[it - nn] = G;
+        } else {
+          gi[it - nn].hmax = b.hm;
+        }
+      }
     }
-    G.hmax = hmx;
-    G.first = f;
-    G.count = e - f;
-    gi[g] = G;
   }
 }
 
@@ -1158,6 +1262,7 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
           if (lane == 0) {
             gl_off[g] = (int32_t)(rbase + gstart);
             gl_cnt[g] = (gover || failed) ? -1 : (int32_t)(rpos - gstart);
+            if (gover || failed) atomicOr(&ds->lists_missing, 1);
           }
           store = false;
         }
@@ -1260,7 +1365,7 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
       S0 = a0 * h3 * kInvPi;
       S1 = -a1 * h3 * hinv * kInvPi;
       nnb = cnt;
-      sums += (act && sub == 0) ? (unsigned long long)(stream ? cnt : (uint32_t)npair) : 0ull;
+      sums += (act && sub == 0) ? (unsigned long long)cnt : 0ull;
       // ---- decide: a slot is done when the h-rho relation holds at its
       // current h to the tolerance (then S0, S1 above are its final sums);
       // otherwise it takes a safeguarded Newton step and is summed again
@@ -1730,7 +1835,10 @@ __global__ void k_set_dt(DevState* ds, double dt_host) {
 }
 
 __global__ void k_set_leaf_state(DevState* ds, int v) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) ds->leaf_state = v;
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ds->leaf_state = v;
+    ds->lists_missing = 0;
+  }
 }
 
 __global__ void k_reset_force_state(DevState* ds) {
@@ -1747,6 +1855,7 @@ __global__ void k_reset_counters(DevState* ds) {
     ds->n_cand_force = 0;
     ds->n_rewalk = 0;
     ds->leaf_state = 0;
+    ds->lists_missing = 0;
   }
 }
 
@@ -1920,17 +2029,18 @@ hipError_t launch_tree(sph_ctx* c) {
 // Node boxes (positions) and largest h; group boxes.  The positions are the
 // current (sorted) ones; h may be the start value or the converged one.
 static hipError_t node_props(sph_ctx* c, const sph_particles* s, bool do_bb) {
-  const int nb = 2048;
-  hipLaunchKernelGGL(k_node_init, dim3(nb), dim3(256), 0, c->stream, c->node_bb, c->node_hm,
-                     c->ds, do_bb ? 1 : 0);
-  hipLaunchKernelGGL(k_node_leaves, dim3(nb), dim3(256), 0, c->stream, s->x, s->y, s->z, s->h,
-                     c->node_first, c->node_count, c->node_parent, c->node_nchild, c->node_bb,
-                     c->node_hm, c->ds, do_bb ? 1 : 0);
-  hipLaunchKernelGGL(k_node_finalize, dim3(nb), dim3(256), 0, c->stream, c->node_bb, c->node_hm,
-                     c->node_first, c->node_count, c->node_child, c->node_nchild, c->wnode,
-                     c->ds, do_bb ? 1 : 0);
-  hipLaunchKernelGGL(k_group_info, dim3(nb), dim3(256), 0, c->stream, s->x, s->y, s->z, s->h,
-                     c->grp_first, c->grp_count, c->ginfo, c->ds);
+  const int n = c->n;
+  const int nch = (n + kChunk - 1) / kChunk;
+  const int flag = do_bb ? 1 : 0;
+  hipLaunchKernelGGL(k_chunk_boxes, dim3((nch + 3) / 4), dim3(256), 0, c->stream, s->x, s->y,
+                     s->z, s->h, n, c->chunk_box, c->ds, flag);
+  // items: at most node_cap nodes + n groups; about two per wavefront
+  const int64_t items = c->node_cap + (int64_t)n;
+  const int nb = (int)std::min<int64_t>(std::max<int64_t>((items + 7) / 8, 64), 16384);
+  hipLaunchKernelGGL(k_range_boxes, dim3(nb), dim3(256), 0, c->stream, s->x, s->y, s->z, s->h,
+                     n, c->chunk_box, c->node_first, c->node_count, c->node_parent,
+                     c->node_child, c->node_nchild, c->wnode, c->grp_first, c->grp_count,
+                     c->ginfo, c->ds, flag);
   return hipGetLastError();
 }
 
