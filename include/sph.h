@@ -196,7 +196,8 @@ sph_status sph_timings(sph_ctx* ctx, double out[8]);
    between.  Synchronises. */
 sph_status sph_stats(sph_ctx* ctx, int64_t out[14]);
 
-/* Human-readable description of the last failure of this context. */
+/* Human-readable description of the last failure of this context; with
+   ctx == NULL, of the last failed sph_create on the calling thread. */
 const char* sph_last_error(const sph_ctx* ctx);
 
 #ifdef __cplusplus

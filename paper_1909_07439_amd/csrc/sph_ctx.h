@@ -89,7 +89,7 @@ struct sph_ctx {
   double* red_out = nullptr;   // 12 results
   sph::DevState* ds = nullptr;
   sph::DevState* hs = nullptr;  // pinned host mirror
-  hipEvent_t ev[8] = {};
+  struct sph_timing* tm = nullptr;  // phase event rings (host code)
   bool timing = true;
   int64_t density_launches = 0;  // launches of the density kernel so far
   int64_t force_launches = 0;    // launches of the force kernel so far

@@ -22,26 +22,21 @@ namespace {
 constexpr int kRing = 1024;  // timed launches kept per phase
 enum Phase { kPhSort = 0, kPhPermute, kPhTree, kPhDensity, kPhForce, kPhIntegrate, kPhStep, kNPh };
 
-struct Timing {
+}  // namespace
+
+// Event rings of the phase timings, owned by the context.
+struct sph_timing {
   hipEvent_t start[kNPh][kRing];
   hipEvent_t stop[kNPh][kRing];
   int count[kNPh];
   bool ready = false;
 };
 
-// Timing lives beside the context (keyed by pointer) so the context layout
-// stays plain; one per context.
-struct CtxExtra {
-  sph_ctx* ctx;
-  Timing t;
-};
-std::vector<CtxExtra*> g_extra;
+namespace {
 
-CtxExtra* extra_of(sph_ctx* c) {
-  for (auto* e : g_extra)
-    if (e->ctx == c) return e;
-  return nullptr;
-}
+// Reason of the last failed sph_create on this thread (no context exists to
+// hold it); returned by sph_last_error(NULL).
+thread_local std::string g_create_err;
 
 sph_status fail(sph_ctx* c, sph_status st, const char* what) {
   if (c) c->err = what;
@@ -62,18 +57,18 @@ sph_status hip_fail(sph_ctx* c, hipError_t e, const char* where) {
   } while (0)
 
 void ph_begin(sph_ctx* c, int ph) {
-  CtxExtra* x = extra_of(c);
-  if (!x || !x->t.ready || !c->timing) return;
-  const int k = x->t.count[ph];
-  if (k < kRing) (void)hipEventRecord(x->t.start[ph][k], c->stream);
+  sph_timing* x = c->tm;
+  if (!x || !x->ready || !c->timing) return;
+  const int k = x->count[ph];
+  if (k < kRing) (void)hipEventRecord(x->start[ph][k], c->stream);
 }
 void ph_end(sph_ctx* c, int ph) {
-  CtxExtra* x = extra_of(c);
-  if (!x || !x->t.ready || !c->timing) return;
-  const int k = x->t.count[ph];
+  sph_timing* x = c->tm;
+  if (!x || !x->ready || !c->timing) return;
+  const int k = x->count[ph];
   if (k < kRing) {
-    (void)hipEventRecord(x->t.stop[ph][k], c->stream);
-    x->t.count[ph] = k + 1;
+    (void)hipEventRecord(x->stop[ph][k], c->stream);
+    x->count[ph] = k + 1;
   }
 }
 
@@ -131,23 +126,33 @@ hipError_t dalloc(T** p, size_t count) {
 extern "C" {
 
 sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ctx** out) {
-  if (!out) return SPH_E_ARG;
+  auto reject = [](const char* why) {
+    g_create_err = std::string("sph_create: ") + why;
+    return SPH_E_ARG;
+  };
+  if (!out) return reject("out is NULL");
   *out = nullptr;
-  if (!prm || n_max < 1 || n_max > (int64_t)0x3fffffff) return SPH_E_ARG;
+  if (!prm) return reject("params is NULL");
+  if (n_max < 1 || n_max > (int64_t)0x3fffffff) return reject("n_max outside [1, 2^30)");
   const sph_params& P = *prm;
   for (int a = 0; a < 3; ++a)
-    if (!(P.box_len[a] > 0.0) || !isfinite(P.box_lo[a])) return SPH_E_ARG;
+    if (!(P.box_len[a] > 0.0) || !isfinite(P.box_lo[a])) return reject("bad box");
   if (!(P.hfact > 0.0) || !(P.gamma > 0.0) || !(P.gamma_minus_1 > 0.0) || !(P.c_cour > 0.0))
-    return SPH_E_ARG;
-  if (P.alpha_av < 0 || P.beta_av < 0 || P.alpha_u < 0) return SPH_E_ARG;
-  if (P.kernel != 0) return SPH_E_ARG;
-  if (P.n_leaf < 1 || P.n_leaf > 64) return SPH_E_ARG;
+    return reject("hfact, gamma, gamma_minus_1 and c_cour must be > 0");
+  if (P.alpha_av < 0 || P.beta_av < 0 || P.alpha_u < 0)
+    return reject("alpha_av, beta_av and alpha_u must be >= 0");
+  if (P.kernel != 0) return reject("unknown kernel");
+  if (P.n_leaf < 1 || P.n_leaf > 64) return reject("n_leaf outside [1, 64]");
   if (!(P.n_group == 4 || P.n_group == 8 || P.n_group == 16 || P.n_group == 32))
-    return SPH_E_ARG;
-  if (P.precision != SPH_PREC_FP64 && P.precision != SPH_PREC_MIXED) return SPH_E_ARG;
+    return reject("n_group must be 4, 8, 16 or 32");
+  if (P.precision != SPH_PREC_FP64 && P.precision != SPH_PREC_MIXED)
+    return reject("unknown precision");
 
   sph_ctx* c = new (std::nothrow) sph_ctx();
-  if (!c) return SPH_E_NOMEM;
+  if (!c) {
+    g_create_err = "sph_create: out of host memory";
+    return SPH_E_NOMEM;
+  }
   c->prm = P;
   c->n_max = n_max;
   c->stream = (hipStream_t)stream;
@@ -181,7 +186,9 @@ sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ct
   auto bail = [&](hipError_t e, const char* where) {
     sph_status st = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? SPH_E_NOMEM
                                                                                 : SPH_E_HIP;
-    (void)where;
+    char buf[512];
+    snprintf(buf, sizeof(buf), "sph_create: %s: %s", where, hipGetErrorString(e));
+    g_create_err = buf;
     sph_destroy(c);
     return st;
   };
@@ -254,22 +261,23 @@ sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ct
   e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return bail(e, "sync");
 #undef ALLOC
-  CtxExtra* x = new (std::nothrow) CtxExtra();
+  sph_timing* x = new (std::nothrow) sph_timing();
   if (!x) {
+    g_create_err = "sph_create: out of host memory";
     sph_destroy(c);
     return SPH_E_NOMEM;
   }
-  x->ctx = c;
+  c->tm = x;
   bool ok = true;
   for (int ph = 0; ph < kNPh && ok; ++ph) {
-    x->t.count[ph] = 0;
+    x->count[ph] = 0;
     for (int r = 0; r < kRing && ok; ++r) {
-      ok = hipEventCreate(&x->t.start[ph][r]) == hipSuccess &&
-           hipEventCreate(&x->t.stop[ph][r]) == hipSuccess;
+      ok = hipEventCreate(&x->start[ph][r]) == hipSuccess &&
+           hipEventCreate(&x->stop[ph][r]) == hipSuccess;
     }
   }
-  x->t.ready = ok;
-  g_extra.push_back(x);
+  x->ready = ok;
+  g_create_err.clear();
   *out = c;
   return SPH_OK;
 }
@@ -277,19 +285,15 @@ sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ct
 void sph_destroy(sph_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
-  for (size_t i = 0; i < g_extra.size(); ++i) {
-    if (g_extra[i]->ctx == c) {
-      CtxExtra* x = g_extra[i];
-      if (x->t.ready)
-        for (int ph = 0; ph < kNPh; ++ph)
-          for (int r = 0; r < kRing; ++r) {
-            (void)hipEventDestroy(x->t.start[ph][r]);
-            (void)hipEventDestroy(x->t.stop[ph][r]);
-          }
-      delete x;
-      g_extra.erase(g_extra.begin() + i);
-      break;
-    }
+  if (sph_timing* x = c->tm) {
+    // events that were created are destroyed; a failed creation left the rest null
+    for (int ph = 0; ph < kNPh; ++ph)
+      for (int r = 0; r < kRing; ++r) {
+        if (x->start[ph][r]) (void)hipEventDestroy(x->start[ph][r]);
+        if (x->stop[ph][r]) (void)hipEventDestroy(x->stop[ph][r]);
+      }
+    delete x;
+    c->tm = nullptr;
   }
   void* ptrs[] = {c->keys[0],   c->keys[1],     c->vals[0],      c->vals[1],     c->radix_cnt,
                   c->scan_part, c->scan_total,  c->gtmp,         c->gtmp_id,     c->dlev,
@@ -525,18 +529,18 @@ sph_status sph_timings(sph_ctx* c, double out[8]) {
   if (!c || !out) return SPH_E_ARG;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (int k = 0; k < 8; ++k) out[k] = 0.0;
-  CtxExtra* x = extra_of(c);
-  if (!x || !x->t.ready) return SPH_OK;
+  sph_timing* x = c->tm;
+  if (!x || !x->ready) return SPH_OK;
   const int map[7] = {0, 1, 2, 3, 4, 5, 6};
   for (int ph = 0; ph < kNPh; ++ph) {
     double s = 0.0;
-    const int n = x->t.count[ph];
+    const int n = x->count[ph];
     for (int r = 0; r < n; ++r) {
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, x->t.start[ph][r], x->t.stop[ph][r]) == hipSuccess) s += ms;
+      if (hipEventElapsedTime(&ms, x->start[ph][r], x->stop[ph][r]) == hipSuccess) s += ms;
     }
     out[map[ph]] = n ? s / n : 0.0;
-    x->t.count[ph] = 0;
+    x->count[ph] = 0;
   }
   return SPH_OK;
 }
@@ -564,7 +568,7 @@ sph_status sph_stats(sph_ctx* c, int64_t out[14]) {
 }
 
 const char* sph_last_error(const sph_ctx* c) {
-  if (!c) return "null context";
+  if (!c) return g_create_err.empty() ? "null context" : g_create_err.c_str();
   return c->err.c_str();
 }
 

@@ -81,6 +81,11 @@ def load() -> ctypes.CDLL:
             return _lib
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1909_07439_amd.build`")
+        # torch brings its own HIP runtime; importing it first makes the
+        # library bind to that same runtime instead of loading a second one
+        # (two runtimes in one process cannot both open the device)
+        import torch  # noqa: F401
+
         lib = ctypes.CDLL(LIB_PATH)
         vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         P = ctypes.POINTER
@@ -185,7 +190,8 @@ class Context:
         st = lib.sph_create(ctypes.byref(params), int(n_max), ctypes.c_void_p(stream),
                             ctypes.byref(h))
         if st != SPH_OK:
-            raise SphError(st, "sph_create")
+            msg = lib.sph_last_error(None)
+            raise SphError(st, msg.decode() if msg else "sph_create")
         self.h = h
 
     def close(self):
