@@ -249,6 +249,9 @@ def main():
         "true_pairs_per_particle": {"density": st["density_pairs"] / cfg["n"],
                                     "force": st["force_pairs"] / cfg["n"]},
         "density_sums_per_step_max": st["max_density_sums"],
+        "groups_walking_last_step": {"rows_overflow": st["groups_rows_overflow"],
+                                     "h_outgrew": st["groups_h_outgrew"],
+                                     "groups": st["n_groups"]},
         "candidates_per_pair": {"density": st["density_candidates"] / max(st["density_pairs"], 1),
                                 "force": st["force_candidates"] / max(st["force_pairs"], 1)},
     }

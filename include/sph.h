@@ -179,11 +179,12 @@ sph_status sph_neighbours(sph_ctx* ctx, const sph_particles* p, int32_t mode, in
 
 /* Mean duration of the launches of each phase since the previous call, in
    milliseconds, from HIP events recorded on the library stream around each
-   phase (at most 1024 launches per phase are kept): out[0..7] = {keys+sort,
-   permute, tree, density, force, integrate, total step, reserved}.  Each of
-   the density, force and integrate phases brackets exactly one kernel.
-   Clears the kept events.  Synchronises. */
-sph_status sph_timings(sph_ctx* ctx, double out[8]);
+   phase (at most 1024 launches per phase are kept): out[0..11] = {keys+sort,
+   permute, tree, density, force, integrate, total step, neighbour lists,
+   density of flagged groups, force of flagged groups, reserved, reserved}.
+   The density, force, integrate, neighbour-list and flagged-group phases each
+   bracket exactly one kernel.  Clears the kept events.  Synchronises. */
+sph_status sph_timings(sph_ctx* ctx, double out[12]);
 
 /* Counters of the work done (for throughput accounting).  out[0..9] refer
    to the last sph_build_tree / sph_step: {tree nodes, groups, most density
@@ -193,8 +194,10 @@ sph_status sph_timings(sph_ctx* ctx, double out[8]);
    pass, device error word}.  out[10..13] are running totals since
    sph_create: {density pair terms, force pairs, density launches, force
    launches}; differences of two calls give the work of the launches in
-   between.  Synchronises. */
-sph_status sph_stats(sph_ctx* ctx, int64_t out[14]);
+   between.  out[14..15] refer to the last density pass: {groups whose
+   neighbour-list rows overflowed, groups in which some h outgrew the rows};
+   both went through the walking kernels.  Synchronises. */
+sph_status sph_stats(sph_ctx* ctx, int64_t out[16]);
 
 /* Human-readable description of the last failure of this context; with
    ctx == NULL, of the last failed sph_create on the calling thread. */

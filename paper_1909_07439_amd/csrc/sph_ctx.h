@@ -11,6 +11,7 @@ constexpr int kSortTile = 2048;  // keys per radix-sort block (256 threads x 8)
 constexpr int kTreeTile = 256;   // particles per tree block
 constexpr int kScanTile = 2048;  // elements per scan block
 constexpr int kChunk = 256;     // particles per chunk box of the node-box reduction
+constexpr int kNLCap = 128;     // entries per neighbour-list row
 
 // Per-particle data the force loop reads for a neighbour j (written by the
 // density pass once h, rho, Omega are final).
@@ -18,11 +19,11 @@ struct alignas(16) FRec64 {
   double x, y, z, m;
   double vx, vy, vz, u;
   double hinv, hinv4pi, g, k;  // g = P/(rho^2 Omega), k = 1/(rho Omega)
-  double c, P, rho, pad;
+  double c, P, rho, h;
 };
 struct alignas(16) FRec32 {
   double x, y, z;
-  float m, pad0;
+  float m, h;
   float vx, vy, vz, u;
   float hinv, hinv4pi, g, k;
   float c, P, rho, pad1;
@@ -80,6 +81,9 @@ struct sph_ctx {
   int64_t pool_cap = 0;
   int32_t* gl_off = nullptr;   // per group: first pool entry
   int32_t* gl_cnt = nullptr;   // per group: entries, -1 if not stored
+  int32_t* nl_idx = nullptr;   // neighbour-list rows, kNLCap per particle
+  int32_t* nl_len = nullptr;   // entries found per particle (may exceed kNLCap)
+  int32_t* gflag = nullptr;    // per group: 0 lists complete, 1 row overflow, 2 h outgrew rows
   // density / force
   void* frec = nullptr;        // FRec64 or FRec32 per particle
   double* a1 = nullptr;        // 4 * n_max: new ax, ay, az, dudt inside sph_step

@@ -20,7 +20,19 @@ hipError_t launch_leaf_state(sph_ctx* c, int v);
 namespace {
 
 constexpr int kRing = 1024;  // timed launches kept per phase
-enum Phase { kPhSort = 0, kPhPermute, kPhTree, kPhDensity, kPhForce, kPhIntegrate, kPhStep, kNPh };
+enum Phase {
+  kPhSort = 0,
+  kPhPermute,
+  kPhTree,
+  kPhDensity,
+  kPhForce,
+  kPhIntegrate,
+  kPhStep,
+  kPhLists,
+  kPhDensityFb,
+  kPhForceFb,
+  kNPh
+};
 
 }  // namespace
 
@@ -241,6 +253,9 @@ sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ct
   ALLOC(c->leaf_pool, c->pool_cap);
   ALLOC(c->gl_off, N);
   ALLOC(c->gl_cnt, N);
+  ALLOC(c->nl_idx, (int64_t)sph::kNLCap * N);
+  ALLOC(c->nl_len, N);
+  ALLOC(c->gflag, N);
   {
     const size_t rec = (P.precision == SPH_PREC_MIXED) ? sizeof(sph::FRec32) : sizeof(sph::FRec64);
     e = hipMalloc(&c->frec, rec * (size_t)N);
@@ -302,7 +317,8 @@ void sph_destroy(sph_ctx* c) {
                   c->node_nchild, c->chunk_box, c->wnode,       c->grp_first,
                   c->grp_count, c->ginfo,       c->frec,         c->a1,          c->nb_cnt,
                   c->nb_off,    c->red_part,    c->red_out,      c->ds,
-                  c->leaf_pool, c->gl_off,      c->gl_cnt};
+                  c->leaf_pool, c->gl_off,      c->gl_cnt,       c->nl_idx,      c->nl_len,
+                  c->gflag};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->hs) (void)hipHostFree(c->hs);
@@ -334,16 +350,55 @@ sph_status sph_build_tree(sph_ctx* c, sph_particles* p) {
   return do_build(c, p, true, false);
 }
 
+// Density of the current tree: neighbour lists, the list density and the
+// walking kernel for flagged groups; or the walking kernel for all groups.
+static sph_status run_density(sph_ctx* c, sph_particles* p) {
+  if (sph::lists_mode(c)) {
+    ph_begin(c, kPhLists);
+    HIPCHK(c, sph::launch_lists(c, p));
+    ph_end(c, kPhLists);
+    ph_begin(c, kPhDensity);
+    HIPCHK(c, sph::launch_density_lists(c, p));
+    ph_end(c, kPhDensity);
+    ph_begin(c, kPhDensityFb);
+    HIPCHK(c, sph::launch_density(c, p, true));
+    ph_end(c, kPhDensityFb);
+  } else {
+    ph_begin(c, kPhDensity);
+    HIPCHK(c, sph::launch_density(c, p, false));
+    ph_end(c, kPhDensity);
+  }
+  ++c->density_launches;
+  return SPH_OK;
+}
+
+// Force: from the lists while they hold every pair, the walking kernel for
+// the rest (or for all groups).
+static sph_status run_force(sph_ctx* c, sph_particles* p, bool step_mode) {
+  if (sph::lists_mode(c)) {
+    ph_begin(c, kPhForce);
+    HIPCHK(c, sph::launch_force_lists(c, p, step_mode));
+    ph_end(c, kPhForce);
+    ph_begin(c, kPhForceFb);
+    HIPCHK(c, sph::launch_force(c, p, step_mode, true));
+    ph_end(c, kPhForceFb);
+  } else {
+    ph_begin(c, kPhForce);
+    HIPCHK(c, sph::launch_force(c, p, step_mode, false));
+    ph_end(c, kPhForce);
+  }
+  ++c->force_launches;
+  return SPH_OK;
+}
+
 sph_status sph_density(sph_ctx* c, sph_particles* p, int32_t* iters_out) {
   if (!c) return SPH_E_ARG;
   sph_status st = check_parts(c, p, false, true);
   if (st != SPH_OK) return st;
   if (p->n != c->n) return fail(c, SPH_E_ARG, "n differs from the last sph_build_tree");
   HIPCHK(c, sph::launch_leaf_state(c, 1));
-  ph_begin(c, kPhDensity);
-  HIPCHK(c, sph::launch_density(c, p));
-  ph_end(c, kPhDensity);
-  ++c->density_launches;
+  st = run_density(c, p);
+  if (st != SPH_OK) return st;
   if (iters_out) {
     st = sync_state(c, true);
     *iters_out = c->hs->max_iter;
@@ -359,10 +414,8 @@ sph_status sph_force(sph_ctx* c, sph_particles* p, double* dt_next_out) {
   if (p->n != c->n) return fail(c, SPH_E_ARG, "n differs from the last sph_build_tree");
   HIPCHK(c, sph::launch_node_h(c, p));
   HIPCHK(c, sph::launch_force_reset(c));
-  ph_begin(c, kPhForce);
-  HIPCHK(c, sph::launch_force(c, p, false));
-  ph_end(c, kPhForce);
-  ++c->force_launches;
+  st = run_force(c, p, false);
+  if (st != SPH_OK) return st;
   if (dt_next_out) {
     st = sync_state(c, true);
     *dt_next_out = sph::dec_f64(c->hs->dt_min_enc);
@@ -382,16 +435,12 @@ sph_status sph_step(sph_ctx* c, sph_particles* p, double dt, double* dt_next_out
   st = do_build(c, p, false, true);
   if (st != SPH_OK) return st;
   HIPCHK(c, sph::launch_leaf_state(c, 1));
-  ph_begin(c, kPhDensity);
-  HIPCHK(c, sph::launch_density(c, p));
-  ph_end(c, kPhDensity);
-  ++c->density_launches;
+  st = run_density(c, p);
+  if (st != SPH_OK) return st;
   HIPCHK(c, sph::launch_node_h(c, p));
   HIPCHK(c, sph::launch_force_reset(c));
-  ph_begin(c, kPhForce);
-  HIPCHK(c, sph::launch_force(c, p, true));
-  ph_end(c, kPhForce);
-  ++c->force_launches;
+  st = run_force(c, p, true);
+  if (st != SPH_OK) return st;
   ph_begin(c, kPhIntegrate);
   HIPCHK(c, sph::launch_correct(c, p));
   ph_end(c, kPhIntegrate);
@@ -525,13 +574,13 @@ sph_status sph_neighbours(sph_ctx* c, const sph_particles* p, int32_t mode, int6
   return sync_state(c, true);
 }
 
-sph_status sph_timings(sph_ctx* c, double out[8]) {
+sph_status sph_timings(sph_ctx* c, double out[12]) {
   if (!c || !out) return SPH_E_ARG;
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  for (int k = 0; k < 8; ++k) out[k] = 0.0;
+  for (int k = 0; k < 12; ++k) out[k] = 0.0;
   sph_timing* x = c->tm;
   if (!x || !x->ready) return SPH_OK;
-  const int map[7] = {0, 1, 2, 3, 4, 5, 6};
+  const int map[kNPh] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9};
   for (int ph = 0; ph < kNPh; ++ph) {
     double s = 0.0;
     const int n = x->count[ph];
@@ -545,7 +594,7 @@ sph_status sph_timings(sph_ctx* c, double out[8]) {
   return SPH_OK;
 }
 
-sph_status sph_stats(sph_ctx* c, int64_t out[14]) {
+sph_status sph_stats(sph_ctx* c, int64_t out[16]) {
   if (!c || !out) return SPH_E_ARG;
   HIPCHK(c, hipMemcpyAsync(c->hs, c->ds, sizeof(sph::DevState), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -564,6 +613,8 @@ sph_status sph_stats(sph_ctx* c, int64_t out[14]) {
   out[11] = (int64_t)s.tot_pairs_force;
   out[12] = c->density_launches;
   out[13] = c->force_launches;
+  out[14] = s.n_flag_rows;
+  out[15] = s.n_flag_grew;
   return SPH_OK;
 }
 

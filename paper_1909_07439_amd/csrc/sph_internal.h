@@ -25,24 +25,28 @@ enum : uint32_t {
 };
 
 // Device-resident scalars of one context.
+// Every wavefront of the walk kernels adds its counts once; the counters
+// that all of them update sit 256 bytes apart (separate cache lines and L2
+// channels), so those atomics do not queue behind each other.
 struct DevState {
   int32_t n_nodes;
   int32_t n_groups;
-  uint32_t err;
-  int32_t max_iter;               // most density sums any group needed
-  unsigned long long dt_min_enc;  // ordered encoding of min_i c_cour h_i / vsig_i
-  double dt_cur;                  // step used by the running sph_step
-  unsigned long long n_pairs_density;  // true neighbours (r < 2h) at the final pass
-  unsigned long long n_pairs_force;    // force pairs
-  unsigned long long n_sums_density;   // sum over groups of (density passes * pairs)
-  unsigned long long n_cand_density;   // candidate tests in the density walks
-  unsigned long long n_cand_force;     // candidate tests in the force walks
-  int32_t n_rewalk;
-  int32_t leaf_state;  // 0: no stored leaf lists, 1: valid for the force, 2: some h outgrew them
-  int32_t lists_missing;  // some group's leaf list could not be stored (its force pass walks)
-  int32_t pad0;
-  unsigned long long tot_sums_density;  // n_sums_density summed over every launch so far
-  unsigned long long tot_pairs_force;   // n_pairs_force summed over every launch so far
+  int32_t leaf_state;     // 0: no stored leaf lists, 1: valid for the force, 2: some h outgrew them
+  int32_t lists_missing;  // some group needs the walking kernels (h refresh needed)
+  int32_t n_flag_rows;    // groups whose neighbour-list rows overflowed (walking kernels)
+  int32_t n_flag_grew;    // groups in which some h outgrew the rows (walking kernels)
+  double dt_cur;          // step used by the running sph_step
+  alignas(256) uint32_t err;
+  alignas(256) int32_t max_iter;                  // most density sums any group needed
+  alignas(256) unsigned long long dt_min_enc;     // ordered encoding of min_i c_cour h_i / vsig_i
+  alignas(256) unsigned long long n_pairs_density;  // true neighbours (r < 2h) at the final pass
+  alignas(256) unsigned long long n_pairs_force;    // force pairs
+  alignas(256) unsigned long long n_sums_density;   // sum over groups of (density passes * pairs)
+  alignas(256) unsigned long long n_cand_density;   // candidate tests in the density walks
+  alignas(256) unsigned long long n_cand_force;     // candidate tests in the force walks
+  alignas(256) int32_t n_rewalk;
+  alignas(256) unsigned long long tot_sums_density;  // n_sums_density over every launch so far
+  alignas(256) unsigned long long tot_pairs_force;   // n_pairs_force over every launch so far
 };
 
 // Walk view of a tree node: centre, conservative half-widths, largest h.
@@ -116,8 +120,12 @@ hipError_t launch_sort(sph_ctx* c);
 hipError_t launch_permute(sph_ctx* c, const sph_particles* p, bool outputs_too);
 hipError_t launch_tree(sph_ctx* c);
 hipError_t launch_node_h(sph_ctx* c, const sph_particles* p);
-hipError_t launch_density(sph_ctx* c, const sph_particles* p);
-hipError_t launch_force(sph_ctx* c, const sph_particles* p, bool step_mode);
+bool lists_mode(const sph_ctx* c);
+hipError_t launch_lists(sph_ctx* c, const sph_particles* p);
+hipError_t launch_density_lists(sph_ctx* c, const sph_particles* p);
+hipError_t launch_density(sph_ctx* c, const sph_particles* p, bool flagged_only);
+hipError_t launch_force_lists(sph_ctx* c, const sph_particles* p, bool step_mode);
+hipError_t launch_force(sph_ctx* c, const sph_particles* p, bool step_mode, bool flagged_only);
 hipError_t launch_correct(sph_ctx* c, const sph_particles* p);
 hipError_t launch_set_dt(sph_ctx* c, double dt_host);
 hipError_t launch_reduce(sph_ctx* c, const sph_particles* p, double* dev_out);

@@ -683,8 +683,47 @@ __device__ __forceinline__ float f32_up(double v) {
   return f;
 }
 
-// Items 0..n_nodes-1 are nodes (WalkNode written), the rest groups
-// (GroupInfo written).  An inner node's range ends where its next sibling
+__device__ __forceinline__ void write_node_box(const Box7& b, int it, int f, int e, int nc,
+                                               const int32_t* __restrict__ nchild,
+                                               WalkNode* __restrict__ wn, int do_bb) {
+  if (do_bb) {
+    WalkNode w;
+    for (int a = 0; a < 3; ++a) {
+      const double c = 0.5 * (b.lo[a] + b.hi[a]);
+      w.c[a] = c;
+      w.w[a] = f32_up(fmax(b.hi[a] - c, c - b.lo[a]));
+    }
+    w.hmax = f32_up(b.hm);
+    w.first = f;
+    w.count = e - f;
+    w.child = nc ? nchild[it] : -1;
+    w.nchild = nc;
+    wn[it] = w;
+  } else {
+    wn[it].hmax = f32_up(b.hm);
+  }
+}
+
+__device__ __forceinline__ void write_group_box(const Box7& b, int g, int f, int e,
+                                                GroupInfo* __restrict__ gi, int do_bb) {
+  if (do_bb) {
+    GroupInfo G;
+    for (int a = 0; a < 3; ++a) {
+      G.c[a] = 0.5 * (b.lo[a] + b.hi[a]);
+      G.w[a] = fmax(b.hi[a] - G.c[a], G.c[a] - b.lo[a]);
+    }
+    G.hmax = b.hm;
+    G.first = f;
+    G.count = e - f;
+    gi[g] = G;
+  } else {
+    gi[g].hmax = b.hm;
+  }
+}
+
+// Blocks [0, nb_small): one thread per leaf or group (at most 64 particles
+// each; items 0..n_nodes-1 are nodes, the rest groups).  The other blocks:
+// one wavefront per inner node, whose range ends where its next sibling
 // starts, or, for a last child, where its parent's range ends.
 __global__ __launch_bounds__(256) void k_range_boxes(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
@@ -693,35 +732,54 @@ __global__ __launch_bounds__(256) void k_range_boxes(
     const int32_t* __restrict__ nparent, const int32_t* __restrict__ nchild,
     const int32_t* __restrict__ nnchild, WalkNode* __restrict__ wn,
     const int32_t* __restrict__ gfirst, const int32_t* __restrict__ gcount,
-    GroupInfo* __restrict__ gi, const DevState* __restrict__ ds, int do_bb) {
+    GroupInfo* __restrict__ gi, const DevState* __restrict__ ds, int do_bb, int nb_small) {
   if (!h_refresh_needed(ds, do_bb)) return;
   const int nn = ds->n_nodes, ng = ds->n_groups;
-  const int wpb = blockDim.x / kWave;
-  for (int it = blockIdx.x * wpb + (int)(threadIdx.x / kWave); it < nn + ng;
-       it += gridDim.x * wpb) {
-    const bool is_node = it < nn;
-    int f, e, nc = 0;
-    if (is_node) {
-      f = nfirst[it];
-      nc = nnchild[it];
-      if (nc == 0) {
-        e = f + ncount[it];
-      } else {
-        e = n;
-        int k = it;
-        while (k > 0) {
-          const int p = nparent[k];
-          if (p < 0) break;
-          if (k + 1 < nchild[p] + nnchild[p]) {
-            e = nfirst[k + 1];
-            break;
-          }
-          k = p;
+  if ((int)blockIdx.x < nb_small) {
+    for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < nn + ng;
+         it += nb_small * blockDim.x) {
+      const bool is_node = it < nn;
+      if (is_node && nnchild[it] != 0) continue;
+      const int f = is_node ? nfirst[it] : gfirst[it - nn];
+      const int e = f + (is_node ? ncount[it] : gcount[it - nn]);
+      Box7 b;
+      box_empty(b);
+#pragma unroll 4
+      for (int s = f; s < e; ++s) {
+        if (do_bb) {
+          const double px = x[s], py = y[s], pz = z[s];
+          b.lo[0] = fmin(b.lo[0], px);
+          b.hi[0] = fmax(b.hi[0], px);
+          b.lo[1] = fmin(b.lo[1], py);
+          b.hi[1] = fmax(b.hi[1], py);
+          b.lo[2] = fmin(b.lo[2], pz);
+          b.hi[2] = fmax(b.hi[2], pz);
         }
+        b.hm = fmax(b.hm, h[s]);
       }
-    } else {
-      f = gfirst[it - nn];
-      e = f + gcount[it - nn];
+      if (is_node)
+        write_node_box(b, it, f, e, 0, nchild, wn, do_bb);
+      else
+        write_group_box(b, it - nn, f, e, gi, do_bb);
+    }
+    return;
+  }
+  const int wpb = blockDim.x / kWave;
+  const int nw = (gridDim.x - nb_small) * wpb;
+  for (int it = (blockIdx.x - nb_small) * wpb + (int)(threadIdx.x / kWave); it < nn; it += nw) {
+    const int nc = nnchild[it];
+    if (nc == 0) continue;
+    const int f = nfirst[it];
+    int e = n;
+    int k = it;
+    while (k > 0) {
+      const int p = nparent[k];
+      if (p < 0) break;
+      if (k + 1 < nchild[p] + nnchild[p]) {
+        e = nfirst[k + 1];
+        break;
+      }
+      k = p;
     }
     Box7 b;
     box_empty(b);
@@ -742,40 +800,7 @@ __global__ __launch_bounds__(256) void k_range_boxes(
       add_particles(b, f, e, x, y, z, h, do_bb);
     }
     wave_box(b, do_bb);
-    if (lane_id() == 0) {
-      if (is_node) {
-        if (do_bb) {
-          WalkNode w;
-          for (int a = 0; a < 3; ++a) {
-            const double c = 0.5 * (b.lo[a] + b.hi[a]);
-            w.c[a] = c;
-            w.w[a] = f32_up(fmax(b.hi[a] - c, c - b.lo[a]));
-          }
-          w.hmax = f32_up(b.hm);
-          w.first = f;
-          w.count = e - f;
-          w.child = nc ? nchild[it] : -1;
-          w.nchild = nc;
-          wn[it] = w;
-        } else {
-          wn[it].hmax = f32_up(b.hm);
-        }
-      } else {
-        if (do_bb) {
-          GroupInfo G;
-          for (int a = 0; a < 3; ++a) {
-            G.c[a] = 0.5 * (b.lo[a] + b.hi[a]);
-            G.w[a] = fmax(b.hi[a] - G.c[a], G.c[a] - b.lo[a]);
-          }
-          G.hmax = b.hm;
-          G.first = f;
-          G.count = e - f;
-          gi[it - nn] = G;
-        } else {
-          gi[it - nn].hmax = b.hm;
-        }
-      }
-    }
+    if (lane_id() == 0) write_node_box(b, it, f, e, nc, nchild, wn, do_bb);
   }
 }
 
@@ -1086,6 +1111,83 @@ __device__ __forceinline__ float fast_rcp(float v) { return __builtin_amdgcn_rcp
 // ============================================================================
 constexpr double kInvPi = 0.318309886183790671537767526745;
 
+// Global Courant minimum: the atomic is skipped when the stored value is
+// already smaller (most wavefronts once the first ones have finished).
+__device__ __forceinline__ void dt_min_update(DevState* ds, double dm) {
+  const unsigned long long e = enc_f64(dm);
+  const unsigned long long cur =
+      __hip_atomic_load(&ds->dt_min_enc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (e < cur) atomicMin(&ds->dt_min_enc, e);
+}
+
+// rho, Omega, P, c_s of particle i at its converged h (Sect. 2.2 and the
+// ideal-gas closure), and the record the force loop reads for it; stored by
+// the lane with `write`.
+template <bool MIXED>
+__device__ __forceinline__ void density_outputs(const KParams& kp, const Parts& p,
+                                                void* __restrict__ frec_out, int i, double xi,
+                                                double yi, double zi, double mi, double h,
+                                                double S0, double S1, double minhalf,
+                                                uint32_t& err, bool write) {
+  const double rho = S0;
+  const double omega = 1.0 + h * S1 / (3.0 * rho);
+  const double u = p.u[i];
+  const double P = kp.gm1 * rho * u;
+  const double cs = sqrt(kp.gamma * kp.gm1 * u);
+  if (!(isfinite(rho) && isfinite(omega) && isfinite(P) && isfinite(cs))) err |= kErrNonFinite;
+  if (2.0 * h >= minhalf) err |= kErrDomain;
+  if (!write) return;
+  p.h[i] = h;
+  p.rho[i] = rho;
+  p.omega[i] = omega;
+  p.P[i] = P;
+  p.cs[i] = cs;
+  const double hinv = 1.0 / h;
+  const double g = P / (rho * rho * omega);
+  const double kk = 1.0 / (rho * omega);
+  const double hinv4pi = hinv * hinv * hinv * hinv * kInvPi;
+  if constexpr (MIXED) {
+    FRec32 r;
+    r.x = xi;
+    r.y = yi;
+    r.z = zi;
+    r.m = (float)mi;
+    r.h = (float)h;
+    r.vx = (float)p.vx[i];
+    r.vy = (float)p.vy[i];
+    r.vz = (float)p.vz[i];
+    r.u = (float)u;
+    r.hinv = (float)hinv;
+    r.hinv4pi = (float)hinv4pi;
+    r.g = (float)g;
+    r.k = (float)kk;
+    r.c = (float)cs;
+    r.P = (float)P;
+    r.rho = (float)rho;
+    r.pad1 = 0.f;
+    reinterpret_cast<FRec32*>(frec_out)[i] = r;
+  } else {
+    FRec64 r;
+    r.x = xi;
+    r.y = yi;
+    r.z = zi;
+    r.m = mi;
+    r.vx = p.vx[i];
+    r.vy = p.vy[i];
+    r.vz = p.vz[i];
+    r.u = u;
+    r.hinv = hinv;
+    r.hinv4pi = hinv4pi;
+    r.g = g;
+    r.k = kk;
+    r.c = cs;
+    r.P = P;
+    r.rho = rho;
+    r.h = h;
+    reinterpret_cast<FRec64*>(frec_out)[i] = r;
+  }
+}
+
 template <bool MIXED, int LPI>
 __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
                                                 const WalkNode* __restrict__ nodes,
@@ -1094,9 +1196,13 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
                                                 int2* __restrict__ pool, int64_t pool_cap,
                                                 int32_t* __restrict__ gl_off,
                                                 int32_t* __restrict__ gl_cnt,
+                                                const int32_t* __restrict__ gflag,
                                                 DevState* __restrict__ ds) {
   using R = typename std::conditional<MIXED, float, double>::type;
   constexpr int GS = kWave / LPI;
+  // gflag != nullptr: only the groups the neighbour-list kernels flagged,
+  // each with its own walk and without storing leaf lists
+  const bool fb = gflag != nullptr;
   __shared__ WalkLds L;
   __shared__ TileOf<R> T;
   __shared__ R s_r[kPMax * GS];
@@ -1129,6 +1235,7 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
 
   for (int sg = sbeg + local; sg < send; sg += nloc) {
    const int g0 = sg * kSG, g1 = min(g0 + kSG, ng);
+   if (fb && ballot64(lane < g1 - g0 && gflag[g0 + lane] != 0) == 0ull) continue;
    // ---- super-group box (union of the group boxes) and largest start h
    GroupInfo SG;
    {
@@ -1162,10 +1269,18 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
        nsl += nleaf;
        __syncthreads();
      };
-     if (!group_walk(nodes, SG, kp, L, sradius, sflush)) sok = false;
-     ++walks;
+     if (fb) {
+       sok = false;  // flagged groups walk on their own
+     } else {
+       if (!group_walk(nodes, SG, kp, L, sradius, sflush)) sok = false;
+       ++walks;
+     }
    }
    for (int g = g0; g < g1; ++g) {
+    if (fb) {
+      if (gflag[g] == 0) continue;
+      if (lane == 0) gl_cnt[g] = -1;  // its force pass walks
+    }
     const GroupInfo G = groups[g];
     const bool act = slot < G.count;
     const int i = G.first + (act ? slot : 0);
@@ -1186,7 +1301,7 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
     double hlo = 0.0, hhi = SPH_INF;
     bool conv = !act;
     bool need = true;
-    bool store = true;  // the first walk stores the leaf list
+    bool store = !fb;  // the first walk stores the leaf list
     const int64_t gstart = rpos;
     bool gover = false;
     int npair = 0;
@@ -1425,63 +1540,9 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
     it_max = max(it_max, nit + 1);
     if (act && !failed && h > h0 * margin) grew = true;
     if (act && !failed) {
-      const double rho = S0;
-      const double omega = 1.0 + h * S1 / (3.0 * rho);
-      const double u = p.u[i];
-      const double P = kp.gm1 * rho * u;
-      const double cs = sqrt(kp.gamma * kp.gm1 * u);
-      if (!(isfinite(rho) && isfinite(omega) && isfinite(P) && isfinite(cs))) err |= kErrNonFinite;
-      if (2.0 * h >= minhalf) err |= kErrDomain;
+      density_outputs<MIXED>(kp, p, frec_out, i, xi, yi, zi, mi, h, S0, S1, minhalf, err,
+                             sub == 0);
       if (sub == 0) {
-        p.h[i] = h;
-        p.rho[i] = rho;
-        p.omega[i] = omega;
-        p.P[i] = P;
-        p.cs[i] = cs;
-        const double hinv = 1.0 / h;
-        const double g = P / (rho * rho * omega);
-        const double kk = 1.0 / (rho * omega);
-        const double hinv4pi = hinv * hinv * hinv * hinv * kInvPi;
-        if constexpr (MIXED) {
-          FRec32 r;
-          r.x = xi;
-          r.y = yi;
-          r.z = zi;
-          r.m = (float)mi;
-          r.pad0 = 0.f;
-          r.vx = (float)p.vx[i];
-          r.vy = (float)p.vy[i];
-          r.vz = (float)p.vz[i];
-          r.u = (float)u;
-          r.hinv = (float)hinv;
-          r.hinv4pi = (float)hinv4pi;
-          r.g = (float)g;
-          r.k = (float)kk;
-          r.c = (float)cs;
-          r.P = (float)P;
-          r.rho = (float)rho;
-          r.pad1 = 0.f;
-          reinterpret_cast<FRec32*>(frec_out)[i] = r;
-        } else {
-          FRec64 r;
-          r.x = xi;
-          r.y = yi;
-          r.z = zi;
-          r.m = mi;
-          r.vx = p.vx[i];
-          r.vy = p.vy[i];
-          r.vz = p.vz[i];
-          r.u = u;
-          r.hinv = hinv;
-          r.hinv4pi = hinv4pi;
-          r.g = g;
-          r.k = kk;
-          r.c = cs;
-          r.P = P;
-          r.rho = rho;
-          r.pad = 0.0;
-          reinterpret_cast<FRec64*>(frec_out)[i] = r;
-        }
         pairs_final += nnb;
       }
     }
@@ -1502,12 +1563,12 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
   sums = sm;
   if (lane == 0) {
     if (b) atomicOr(&ds->err, eall);
-    atomicMax(&ds->max_iter, it_max);
-    atomicAdd(&ds->n_pairs_density, pf);
-    atomicAdd(&ds->n_sums_density, sums);
-    atomicAdd(&ds->tot_sums_density, sums);
-    atomicAdd(&ds->n_cand_density, cd);
-    atomicAdd(&ds->n_rewalk, walks);
+    if (it_max > 0) atomicMax(&ds->max_iter, it_max);
+    if (pf) atomicAdd(&ds->n_pairs_density, pf);
+    if (sums) atomicAdd(&ds->n_sums_density, sums);
+    if (sums && !fb) atomicAdd(&ds->tot_sums_density, sums);
+    if (cd) atomicAdd(&ds->n_cand_density, cd);
+    if (walks) atomicAdd(&ds->n_rewalk, walks);
     if (ballot_any) atomicMax(&ds->leaf_state, 2);
   }
 }
@@ -1539,6 +1600,7 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
                                               double* __restrict__ out_ay,
                                               double* __restrict__ out_az,
                                               double* __restrict__ out_du,
+                                              const int32_t* __restrict__ gflag,
                                               DevState* __restrict__ ds) {
   using Rec = typename FRecOf<MIXED>::T;
   using R = typename std::conditional<MIXED, float, double>::type;
@@ -1560,6 +1622,9 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
   double dtmin = SPH_INF;
 
   for (int g = gbeg + local; g < gend; g += nloc) {
+    // gflag != nullptr: while the neighbour lists hold every pair
+    // (leaf_state 1) the list kernel does the unflagged groups
+    if (gflag != nullptr && use_lists && gflag[g] == 0) continue;
     const GroupInfo G = groups[g];
     const bool act = slot < G.count;
     const int i = G.first + (act ? slot : 0);
@@ -1756,10 +1821,564 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
   const double dm = wave_min_f64(dtmin);
   if (lane == 0) {
     if (b) atomicOr(&ds->err, eall);
-    atomicAdd(&ds->n_pairs_force, pf);
-    atomicAdd(&ds->tot_pairs_force, pf);
-    atomicAdd(&ds->n_cand_force, cd);
-    if (dm < SPH_INF) atomicMin(&ds->dt_min_enc, enc_f64(dm));
+    if (pf) atomicAdd(&ds->n_pairs_force, pf);
+    if (pf && gflag == nullptr) atomicAdd(&ds->tot_pairs_force, pf);
+    if (cd) atomicAdd(&ds->n_cand_force, cd);
+    if (dm < SPH_INF) dt_min_update(ds, dm);
+  }
+}
+
+// ============================================================================
+// Neighbour lists (Sect. 3.2).  k_lists: one wavefront per super-group of
+// kSG groups.  The super-group walk collects every leaf any of its groups can
+// need; each group culls that list against its own box and writes, for each
+// of its particles i, the indices j of every particle with
+//     r_ij < 2 max(hl_i, hl_j),   hl = h_margin * (h at the start),
+// into the fixed-capacity row i of nl_idx (self included).  As long as no h
+// grows past its hl, a row is a superset of the density neighbours (r < 2 h_i)
+// and of the force pairs (r < 2 max(h_i, h_j)); the density and force list
+// kernels apply the exact predicates.  A group with an overflowing row or a
+// failed walk is flagged (gflag = 1) and left to the walking kernels.
+// ============================================================================
+template <bool MIXED, int LPI>
+__global__ __launch_bounds__(64) void k_lists(KParams kp, Parts p,
+                                              const WalkNode* __restrict__ nodes,
+                                              const GroupInfo* __restrict__ groups,
+                                              int32_t* __restrict__ nl_idx,
+                                              int32_t* __restrict__ nl_len,
+                                              int32_t* __restrict__ gflag,
+                                              DevState* __restrict__ ds) {
+  using R = typename std::conditional<MIXED, float, double>::type;
+  constexpr int GS = kWave / LPI;
+  __shared__ WalkLds L;
+  __shared__ TileOf<R> T;
+  __shared__ int s_sl[kSLCap];
+  const int lane = threadIdx.x;
+  const int slot = lane / LPI, sub = lane % LPI;
+  const int ng = ds->n_groups;
+  const int nsg = (ng + kSG - 1) / kSG;
+  const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, nloc = gridDim.x >> 3;
+  const int chunk = (nsg + 7) >> 3;
+  const int sbeg = xcd * chunk, send = min(sbeg + chunk, nsg);
+  const double margin = kp.h_margin;
+  bool flagged = false;
+  int nflag = 0;
+  unsigned long long cands = 0;
+  int walks = 0;
+  (void)GS;
+
+  for (int sg = sbeg + local; sg < send; sg += nloc) {
+    const int g0 = sg * kSG, g1 = min(g0 + kSG, ng);
+    GroupInfo SG;
+    {
+      const bool v = lane < g1 - g0;
+      GroupInfo Gk;
+      if (v) Gk = groups[g0 + lane];
+      for (int a = 0; a < 3; ++a) {
+        const double lo = wave_min_f64(v ? Gk.c[a] - Gk.w[a] : SPH_INF);
+        const double hi = wave_max_f64(v ? Gk.c[a] + Gk.w[a] : -SPH_INF);
+        SG.c[a] = 0.5 * (lo + hi);
+        SG.w[a] = fmax(hi - SG.c[a], SG.c[a] - lo);
+      }
+      SG.hmax = wave_max_f64(v ? Gk.hmax : 0.0);
+      SG.first = 0;
+      SG.count = 0;
+    }
+    int nsl = 0;
+    bool sok = true;
+    {
+      const double hs = margin * SG.hmax;
+      auto sradius = [&](const WalkNode& nd) {
+        return 2.0 * fmax(hs, margin * (double)nd.hmax) * (1.0 + 4e-9);
+      };
+      auto sflush = [&](int nleaf) {
+        if (nsl + nleaf <= kSLCap) {
+          for (int q = lane; q < nleaf; q += kWave) s_sl[nsl + q] = L.lnode[q];
+        } else {
+          sok = false;
+        }
+        nsl += nleaf;
+        __syncthreads();
+      };
+      if (!group_walk(nodes, SG, kp, L, sradius, sflush)) sok = false;
+      ++walks;
+    }
+    for (int g = g0; g < g1; ++g) {
+      const GroupInfo G = groups[g];
+      const bool act = slot < G.count;
+      const int i = G.first + (act ? slot : 0);
+      const double xi = p.x[i], yi = p.y[i], zi = p.z[i];
+      const double hl = margin * p.h[i];
+      float xr = 0.f, yr = 0.f, zr = 0.f;
+      if constexpr (MIXED) {
+        xr = (float)fold(xi - G.c[0], kp.len[0], kp.half[0], kp.periodic[0]);
+        yr = (float)fold(yi - G.c[1], kp.len[1], kp.half[1], kp.periodic[1]);
+        zr = (float)fold(zi - G.c[2], kp.len[2], kp.half[2], kp.periodic[2]);
+      }
+      const float hlf = (float)hl, marginf = (float)margin;
+      const double hm = wave_max_f64(act ? hl : 0.0);
+      int32_t* __restrict__ row = nl_idx + (int64_t)i * kNLCap;
+      int npair = 0;
+      auto radius = [&](const WalkNode& nd) {
+        return 2.0 * fmax(hm, margin * (double)nd.hmax) * (1.0 + 4e-9);
+      };
+      auto flush = [&](int nleaf) {
+        const int total = leaf_offsets(L, nleaf);
+        cands += (unsigned long long)total * ((act && sub == 0) ? 1u : 0u);
+        for_tiles<LPI, R>(L, nleaf, total, sub, p.x, p.y, p.z, p.h, T, G, kp,
+                          [&](bool valid, int c) {
+          bool pred = false;
+          const int j = valid ? T.j[c] : -1;
+          if (valid && act) {
+            if constexpr (MIXED) {
+              const float dx = xr - T.x[c], dy = yr - T.y[c], dz = zr - T.z[c];
+              const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+              const float sr = 2.0f * fmaxf(hlf, marginf * T.a[c]);
+              pred = r2 < sr * sr * 1.00001f;
+            } else {
+              const double dx = fold(xi - T.x[c], kp.len[0], kp.half[0], kp.periodic[0]);
+              const double dy = fold(yi - T.y[c], kp.len[1], kp.half[1], kp.periodic[1]);
+              const double dz = fold(zi - T.z[c], kp.len[2], kp.half[2], kp.periodic[2]);
+              const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+              const double sr = 2.0 * fmax(hl, margin * T.a[c]);
+              pred = r2 < sr * sr;
+            }
+          }
+          const uint64_t b = ballot64(pred);
+          const uint32_t seg = (uint32_t)((b >> (slot * LPI)) & ((LPI == 64) ? ~0ull : ((1ull << LPI) - 1ull)));
+          const int pos = npair + __popc(seg & ((1u << sub) - 1u));
+          if (pred && pos < kNLCap) row[pos] = j;
+          npair += __popc(seg);
+        });
+        __syncthreads();
+      };
+      bool wok = true;
+      if (sok) {
+        list_walk(nodes, s_sl, nsl, G, kp, L, radius, flush);
+      } else {
+        wok = group_walk(nodes, G, kp, L, radius, flush);
+        ++walks;
+      }
+      if (act && sub == 0) nl_len[i] = npair;
+      const bool bad = !wok || ballot64(act && npair > kNLCap) != 0ull;
+      if (lane == 0) gflag[g] = bad ? 1 : 0;
+      flagged |= bad;
+      nflag += bad ? 1 : 0;
+    }
+  }
+  unsigned long long cd = cands;
+  for (int d = 32; d > 0; d >>= 1) cd += __shfl_xor(cd, d, kWave);
+  if (lane == 0) {
+    if (cd) atomicAdd(&ds->n_cand_density, cd);
+    if (walks) atomicAdd(&ds->n_rewalk, walks);
+    if (flagged) {
+      atomicOr(&ds->lists_missing, 1);
+      atomicAdd(&ds->n_flag_rows, nflag);
+    }
+  }
+}
+
+// Groups of this wave under the XCD-aware static schedule: block b works on
+// the contiguous eighth of the groups that belongs to XCD b mod 8.
+struct GroupRange {
+  int beg, end, step;
+};
+__device__ __forceinline__ GroupRange xcd_groups(int ng) {
+  const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, nloc = gridDim.x >> 3;
+  const int chunk = (ng + 7) >> 3;
+  const int gbeg = xcd * chunk;
+  return GroupRange{gbeg + local, min(gbeg + chunk, ng), nloc};
+}
+
+// ============================================================================
+// Density from the neighbour lists (Sect. 2.2, Sect. 3.2.1): one wavefront
+// per group, LPI lanes per particle.  Each lane gathers the separations and
+// masses of its share of the row once (registers), then the h iteration
+// re-sums them: Newton-Raphson on f(h) = S0(h) - m (hfact/h)^3 with the same
+// safeguards as the walking kernel, a wavefront ballot deciding when the
+// group is done.  A group in which some h passes hl (its rows may then miss
+// neighbours) is flagged (gflag = 2) for the walking kernel, and the force
+// pass then walks for every group (leaf_state 2).
+// ============================================================================
+template <bool MIXED, int LPI>
+__global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
+                                                      const GroupInfo* __restrict__ groups,
+                                                      const int32_t* __restrict__ nl_idx,
+                                                      const int32_t* __restrict__ nl_len,
+                                                      int32_t* __restrict__ gflag,
+                                                      void* __restrict__ frec_out,
+                                                      DevState* __restrict__ ds) {
+  using R = typename std::conditional<MIXED, float, double>::type;
+  constexpr int E = kNLCap / LPI;  // row entries per lane
+  constexpr int GS = kWave / LPI;
+  __shared__ R s_r[kNLCap * GS];  // separation and mass of row entry k of slot s at [k * GS + s]
+  __shared__ R s_m[kNLCap * GS];
+  const int lane = threadIdx.x;
+  const int slot = lane / LPI, sub = lane % LPI;
+  const GroupRange gr = xcd_groups(ds->n_groups);
+  const double margin = kp.h_margin;
+  double minhalf = SPH_INF;
+  for (int a = 0; a < 3; ++a)
+    if (kp.periodic[a]) minhalf = fmin(minhalf, kp.half[a]);
+  uint32_t err = 0;
+  int it_max = 0;
+  unsigned long long pairs_final = 0, sums = 0;
+  bool outgrew_any = false;
+  int ngrew = 0;
+
+  for (int g = gr.beg; g < gr.end; g += gr.step) {
+    if (gflag[g] != 0) continue;
+    const GroupInfo G = groups[g];
+    const bool act = slot < G.count;
+    const int i = G.first + (act ? slot : 0);
+    const double xi = p.x[i], yi = p.y[i], zi = p.z[i], mi = p.m[i];
+    double h = p.h[i];
+    if (!(h > 0.0) || !isfinite(h)) {
+      err |= kErrNonFinite;
+      h = 1.0;
+    }
+    const double hl = margin * h;
+    const int len = act ? nl_len[i] : 0;
+    const int32_t* __restrict__ row = nl_idx + (int64_t)i * kNLCap;
+    int lmax = len;
+    for (int d = 32; d > 0; d >>= 1) lmax = max(lmax, __shfl_xor(lmax, d, kWave));
+    // ---- gather: separation and mass of every row entry into LDS, four
+    // entries per lane at a time (their loads in flight together)
+    for (int t0 = 0; t0 < E; t0 += 4) {
+      if (__builtin_amdgcn_readfirstlane(t0 * LPI) >= lmax) break;
+      int jj[4];
+      bool vv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = sub + LPI * (t0 + q);
+        vv[q] = k < len;
+        jj[q] = vv[q] ? row[k] : i;
+      }
+      double gx[4], gy[4], gz[4], gm[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        gx[q] = p.x[jj[q]];
+        gy[q] = p.y[jj[q]];
+        gz[q] = p.z[jj[q]];
+        gm[q] = p.m[jj[q]];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (!vv[q]) continue;
+        const int k = sub + LPI * (t0 + q);
+        const double dx = fold(xi - gx[q], kp.len[0], kp.half[0], kp.periodic[0]);
+        const double dy = fold(yi - gy[q], kp.len[1], kp.half[1], kp.periodic[1]);
+        const double dz = fold(zi - gz[q], kp.len[2], kp.half[2], kp.periodic[2]);
+        if constexpr (MIXED) {
+          const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+          s_r[k * GS + slot] = fast_sqrt(fmaf(fz, fz, fmaf(fy, fy, fx * fx)));
+          s_m[k * GS + slot] = (float)gm[q];
+        } else {
+          s_r[k * GS + slot] = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
+          s_m[k * GS + slot] = gm[q];
+        }
+      }
+    }
+    // ---- h iteration over the gathered entries
+    double hlo = 0.0, hhi = SPH_INF;
+    bool conv = !act, outgrew = false;
+    int nit = 0;
+    double S0 = 0.0, S1 = 0.0;
+    uint32_t nnb = 0;
+    while (true) {
+      const double hinv = 1.0 / h;
+      double a0 = 0.0, a1 = 0.0;
+      uint32_t cnt = 0;
+      if constexpr (MIXED) {
+        // each lane sums its few terms in FP32; lanes are combined in FP64
+        const float hinvf = (float)hinv, twohf = (float)(2.0 * h);
+        float s0 = 0.f, s1 = 0.f;
+        for (int k = sub; k < len; k += LPI) {
+          const float r = s_r[k * GS + slot], m = s_m[k * GS + slot];
+          const float q = r * hinvf;
+          float f, df;
+          m4_f_df<float>(q, f, df);
+          s0 = fmaf(m, f, s0);
+          s1 = fmaf(m, fmaf(q, df, 3.0f * f), s1);
+          cnt += (r < twohf) ? 1u : 0u;
+        }
+        a0 = (double)s0;
+        a1 = (double)s1;
+      } else {
+        const double twoh = 2.0 * h;
+        for (int k = sub; k < len; k += LPI) {
+          const double r = s_r[k * GS + slot], m = s_m[k * GS + slot];
+          const double q = r * hinv;
+          double f, df;
+          m4_f_df<double>(q, f, df);
+          a0 += m * f;
+          a1 += m * (3.0 * f + q * df);
+          cnt += (r < twoh) ? 1u : 0u;
+        }
+      }
+      a0 = seg_sum<LPI>(a0);
+      a1 = seg_sum<LPI>(a1);
+      cnt = seg_sum_u32<LPI>(cnt);
+      const double h3 = hinv * hinv * hinv;
+      S0 = a0 * h3 * kInvPi;
+      S1 = -a1 * h3 * hinv * kInvPi;
+      nnb = cnt;
+      sums += (act && sub == 0) ? (unsigned long long)cnt : 0ull;
+      bool moved = false;
+      if (!conv) {
+        const double t = kp.hfact * hinv;
+        const double rh = mi * (t * t * t);
+        const double f = S0 - rh;
+        const double fp = S1 + 3.0 * rh * hinv;
+        double hn = h;
+        if (kp.fixed_passes) {
+          hn = h - f / fp;
+          if (!(fp > 0.0))
+            hn = h;
+          else if (hn > 1.2 * h)
+            hn = 1.2 * h;
+          else if (hn < 0.8 * h)
+            hn = 0.8 * h;
+          conv = (nit + 1) >= 3;
+          moved = true;
+        } else if (fabs(f) <= 3.0 * kp.h_tol * rh) {
+          conv = true;
+        } else {
+          if (f < 0.0)
+            hlo = fmax(hlo, h);
+          else
+            hhi = fmin(hhi, h);
+          hn = h - f / fp;
+          const bool bad = !(fp > 0.0) || !(hn >= 0.8 * h) || !(hn <= 1.2 * h) ||
+                           !(hn > hlo) || !(hn < hhi);
+          if (bad) {
+            if (hlo > 0.0 && hhi < SPH_INF)
+              hn = 0.5 * (hlo + hhi);
+            else
+              hn = (f < 0.0) ? 1.2 * h : h / 1.2;
+          }
+          conv = fabs(hn - h) <= 4e-16 * h;
+          moved = true;
+        }
+        if (moved) {
+          h = hn;
+          if (h > hl) outgrew = true;
+          ++nit;
+          if (nit > kp.max_iter) {
+            err |= kErrNoConv;
+            conv = true;
+          }
+        }
+      }
+      if (ballot64(outgrew) != 0ull) break;  // rows too short: the walking kernel redoes it
+      if (ballot64(!conv || moved) == 0ull) break;
+    }
+    if (ballot64(outgrew) != 0ull) {
+      if (lane == 0) gflag[g] = 2;
+      outgrew_any = true;
+      ++ngrew;
+      continue;
+    }
+    it_max = max(it_max, nit + 1);
+    if (act) {
+      density_outputs<MIXED>(kp, p, frec_out, i, xi, yi, zi, mi, h, S0, S1, minhalf, err,
+                             sub == 0);
+      if (sub == 0) pairs_final += nnb;
+    }
+  }
+  const uint64_t b = ballot64(err != 0);
+  uint32_t eall = err;
+  for (int d = 32; d > 0; d >>= 1) eall |= __shfl_xor(eall, d, kWave);
+  unsigned long long pf = pairs_final, sm = sums;
+  for (int d = 32; d > 0; d >>= 1) {
+    pf += __shfl_xor(pf, d, kWave);
+    sm += __shfl_xor(sm, d, kWave);
+  }
+  if (lane == 0) {
+    if (b) atomicOr(&ds->err, eall);
+    if (it_max > 0) atomicMax(&ds->max_iter, it_max);
+    if (pf) atomicAdd(&ds->n_pairs_density, pf);
+    if (sm) atomicAdd(&ds->n_sums_density, sm);
+    if (sm) atomicAdd(&ds->tot_sums_density, sm);
+    if (outgrew_any) {
+      atomicMax(&ds->leaf_state, 2);
+      atomicOr(&ds->lists_missing, 1);
+      atomicAdd(&ds->n_flag_grew, ngrew);
+    }
+  }
+}
+
+// ============================================================================
+// Force from the neighbour lists (Sect. 2.4-2.6): one wavefront per group,
+// LPI lanes per particle, each lane walking its share of row i.  The exact
+// pair predicate (j != i, r < 2 max(h_i, h_j) with the converged h) is applied
+// to every entry; accepted pairs add the pressure, viscosity and conductivity
+// terms.  Runs only while every row is complete (leaf_state 1); flagged
+// groups are left to the walking kernel.
+// ============================================================================
+template <bool MIXED, int LPI>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
+void k_force_lists(KParams kp, Parts p,
+                                                    const GroupInfo* __restrict__ groups,
+                                                    const void* __restrict__ frec_in,
+                                                    const int32_t* __restrict__ nl_idx,
+                                                    const int32_t* __restrict__ nl_len,
+                                                    const int32_t* __restrict__ gflag,
+                                                    double* __restrict__ out_ax,
+                                                    double* __restrict__ out_ay,
+                                                    double* __restrict__ out_az,
+                                                    double* __restrict__ out_du,
+                                                    DevState* __restrict__ ds) {
+  if (ds->leaf_state != 1) return;
+  using Rec = typename FRecOf<MIXED>::T;
+  const Rec* __restrict__ rec = reinterpret_cast<const Rec*>(frec_in);
+  const int lane = threadIdx.x;
+  const int slot = lane / LPI, sub = lane % LPI;
+  const GroupRange gr = xcd_groups(ds->n_groups);
+  uint32_t err = 0;
+  unsigned long long pairs = 0, cands = 0;
+  double dtmin = SPH_INF;
+
+  for (int g = gr.beg; g < gr.end; g += gr.step) {
+    if (gflag[g] != 0) continue;
+    const GroupInfo G = groups[g];
+    const bool act = slot < G.count;
+    const int i = G.first + (act ? slot : 0);
+    const double xi = p.x[i], yi = p.y[i], zi = p.z[i], hi = p.h[i];
+    const Rec ri = rec[i];
+    const int len = act ? nl_len[i] : 0;
+    const int32_t* __restrict__ row = nl_idx + (int64_t)i * kNLCap;
+    int lmax = len;
+    for (int d = 32; d > 0; d >>= 1) lmax = max(lmax, __shfl_xor(lmax, d, kWave));
+    cands += (act && sub == 0) ? (unsigned long long)len : 0ull;
+    double ax = 0.0, ay = 0.0, az = 0.0, du = 0.0, vmax = 0.0;
+    if constexpr (MIXED) {
+      const float al = (float)kp.alpha, be = (float)kp.beta, au = (float)kp.alpha_u;
+      const float vxi = ri.vx, vyi = ri.vy, vzi = ri.vz, hif = (float)hi;
+      const float hinvi = ri.hinv, h4i = ri.hinv4pi, gi = ri.g, ki = ri.k, ci = ri.c;
+      const float Pi = ri.P, rhoi = ri.rho, ui = ri.u;
+      auto pair = [&](const Rec& rj) {
+        const float dx = (float)fold(xi - rj.x, kp.len[0], kp.half[0], kp.periodic[0]);
+        const float dy = (float)fold(yi - rj.y, kp.len[1], kp.half[1], kp.periodic[1]);
+        const float dz = (float)fold(zi - rj.z, kp.len[2], kp.half[2], kp.periodic[2]);
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        const float sr = 2.0f * fmaxf(hif, rj.h);
+        if (!(r2 < sr * sr * 1.00001f)) return;
+        ++pairs;
+        const float rinv = __builtin_amdgcn_rsqf(r2);
+        const float r = r2 * rinv;
+        const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
+        const float w = fmaf(vzi - rj.vz, ez, fmaf(vyi - rj.vy, ey, (vxi - rj.vx) * ex));
+        const float Fi = m4_df<float>(r * hinvi) * h4i;
+        const float Fj = m4_df<float>(r * rj.hinv) * rj.hinv4pi;
+        const float aw = fabsf(w);
+        const bool app = w < 0.0f;
+        const float vsi = fmaf(be, aw, al * ci);
+        const float vsj = fmaf(be, aw, al * rj.c);
+        const float ti = app ? fmaf(-0.5f * vsi * w, ki, gi) : gi;
+        const float tj = app ? fmaf(-0.5f * vsj * w, rj.k, rj.g) : rj.g;
+        const float pa = rj.m * fmaf(ti, Fi, tj * Fj);
+        ax -= (double)(pa * ex);
+        ay -= (double)(pa * ey);
+        az -= (double)(pa * ez);
+        const float mwF = rj.m * w * Fi;
+        float e = gi * mwF;
+        if (app) e = fmaf(-0.5f * ki * vsi * w, mwF, e);
+        const float dP = fabsf(Pi - rj.P);
+        const float vu = fast_sqrt(dP * fast_rcp(0.5f * (rhoi + rj.rho)));
+        e = fmaf(rj.m * au * vu * (ui - rj.u), 0.5f * fmaf(Fi, ki, Fj * rj.k), e);
+        du += (double)e;
+        vmax = fmax(vmax, (double)vsi);
+      };
+      for (int k = sub; k < lmax; k += 2 * LPI) {
+        const int k2 = k + LPI;
+        const bool v1 = k < len, v2 = k2 < len;
+        const int j1 = v1 ? row[k] : i;
+        const int j2 = v2 ? row[k2] : i;
+        const Rec r1 = rec[j1];
+        const Rec r2 = rec[j2];
+        if (v1 && j1 != i) pair(r1);
+        if (v2 && j2 != i) pair(r2);
+      }
+    } else {
+      const double al = kp.alpha, be = kp.beta, au = kp.alpha_u;
+      const double vxi = ri.vx, vyi = ri.vy, vzi = ri.vz;
+      const double hinvi = ri.hinv, h4i = ri.hinv4pi, gi = ri.g, ki = ri.k, ci = ri.c;
+      const double Pi = ri.P, rhoi = ri.rho, ui = ri.u;
+      auto pair = [&](const Rec& rj) {
+        const double dx = fold(xi - rj.x, kp.len[0], kp.half[0], kp.periodic[0]);
+        const double dy = fold(yi - rj.y, kp.len[1], kp.half[1], kp.periodic[1]);
+        const double dz = fold(zi - rj.z, kp.len[2], kp.half[2], kp.periodic[2]);
+        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        const double sr = 2.0 * (hi > rj.h ? hi : rj.h);
+        if (!(r2 < sr * sr)) return;
+        ++pairs;
+        const double r = sqrt(r2);
+        const double rinv = 1.0 / r;
+        const double ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
+        const double w = fma(vzi - rj.vz, ez, fma(vyi - rj.vy, ey, (vxi - rj.vx) * ex));
+        const double Fi = m4_df<double>(r * hinvi) * h4i;
+        const double Fj = m4_df<double>(r * rj.hinv) * rj.hinv4pi;
+        const double aw = fabs(w);
+        const bool app = w < 0.0;
+        const double vsi = fma(be, aw, al * ci);
+        const double vsj = fma(be, aw, al * rj.c);
+        const double ti = app ? fma(-0.5 * vsi * w, ki, gi) : gi;
+        const double tj = app ? fma(-0.5 * vsj * w, rj.k, rj.g) : rj.g;
+        const double pa = rj.m * fma(ti, Fi, tj * Fj);
+        ax -= pa * ex;
+        ay -= pa * ey;
+        az -= pa * ez;
+        const double mwF = rj.m * w * Fi;
+        double e = gi * mwF;
+        if (app) e = fma(-0.5 * ki * vsi * w, mwF, e);
+        const double vu = sqrt(fabs(Pi - rj.P) / (0.5 * (rhoi + rj.rho)));
+        e = fma(rj.m * au * vu * (ui - rj.u), 0.5 * fma(Fi, ki, Fj * rj.k), e);
+        du += e;
+        vmax = fmax(vmax, vsi);
+      };
+      // one 128-byte record in flight per lane (registers)
+      for (int k = sub; k < lmax; k += LPI) {
+        const bool v = k < len;
+        const int j = v ? row[k] : i;
+        const Rec rj = rec[j];
+        if (v && j != i) pair(rj);
+      }
+    }
+    ax = seg_sum<LPI>(ax);
+    ay = seg_sum<LPI>(ay);
+    az = seg_sum<LPI>(az);
+    du = seg_sum<LPI>(du);
+    vmax = seg_max<LPI>(vmax);
+    if (act) {
+      const double v0 = (kp.alpha == 0.0) ? (double)ri.c : kp.alpha * (double)ri.c;
+      const double vs = fmax(vmax, v0);
+      if (!(isfinite(ax) && isfinite(ay) && isfinite(az) && isfinite(du))) err |= kErrNonFinite;
+      if (sub == 0) {
+        out_ax[i] = ax;
+        out_ay[i] = ay;
+        out_az[i] = az;
+        out_du[i] = du;
+        p.vsig[i] = vs;
+      }
+      dtmin = fmin(dtmin, kp.c_cour * hi / vs);
+    }
+  }
+  const uint64_t b = ballot64(err != 0);
+  uint32_t eall = err;
+  for (int d = 32; d > 0; d >>= 1) eall |= __shfl_xor(eall, d, kWave);
+  unsigned long long pf = pairs, cd = cands;
+  for (int d = 32; d > 0; d >>= 1) {
+    pf += __shfl_xor(pf, d, kWave);
+    cd += __shfl_xor(cd, d, kWave);
+  }
+  const double dm = wave_min_f64(dtmin);
+  if (lane == 0) {
+    if (b) atomicOr(&ds->err, eall);
+    if (pf) atomicAdd(&ds->n_pairs_force, pf);
+    if (pf) atomicAdd(&ds->tot_pairs_force, pf);
+    if (cd) atomicAdd(&ds->n_cand_force, cd);
+    if (dm < SPH_INF) dt_min_update(ds, dm);
   }
 }
 
@@ -1838,6 +2457,8 @@ __global__ void k_set_leaf_state(DevState* ds, int v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     ds->leaf_state = v;
     ds->lists_missing = 0;
+    ds->n_flag_rows = 0;
+    ds->n_flag_grew = 0;
   }
 }
 
@@ -1856,6 +2477,8 @@ __global__ void k_reset_counters(DevState* ds) {
     ds->n_rewalk = 0;
     ds->leaf_state = 0;
     ds->lists_missing = 0;
+    ds->n_flag_rows = 0;
+    ds->n_flag_grew = 0;
   }
 }
 
@@ -2034,44 +2657,155 @@ static hipError_t node_props(sph_ctx* c, const sph_particles* s, bool do_bb) {
   const int flag = do_bb ? 1 : 0;
   hipLaunchKernelGGL(k_chunk_boxes, dim3((nch + 3) / 4), dim3(256), 0, c->stream, s->x, s->y,
                      s->z, s->h, n, c->chunk_box, c->ds, flag);
-  // items: at most node_cap nodes + n groups; about two per wavefront
+  // leaves and groups: about one per thread; inner nodes (about a seventh of
+  // the nodes): about two per wavefront
   const int64_t items = c->node_cap + (int64_t)n;
-  const int nb = (int)std::min<int64_t>(std::max<int64_t>((items + 7) / 8, 64), 16384);
-  hipLaunchKernelGGL(k_range_boxes, dim3(nb), dim3(256), 0, c->stream, s->x, s->y, s->z, s->h,
-                     n, c->chunk_box, c->node_first, c->node_count, c->node_parent,
-                     c->node_child, c->node_nchild, c->wnode, c->grp_first, c->grp_count,
-                     c->ginfo, c->ds, flag);
+  const int nb_small = (int)std::min<int64_t>(std::max<int64_t>((items / 2 + 255) / 256, 16), 4096);
+  const int nb_inner = (int)std::min<int64_t>(std::max<int64_t>((items / 2 + 63) / 64, 16), 4096);
+  hipLaunchKernelGGL(k_range_boxes, dim3(nb_small + nb_inner), dim3(256), 0, c->stream, s->x,
+                     s->y, s->z, s->h, n, c->chunk_box, c->node_first, c->node_count,
+                     c->node_parent, c->node_child, c->node_nchild, c->wnode, c->grp_first,
+                     c->grp_count, c->ginfo, c->ds, flag, nb_small);
   return hipGetLastError();
 }
 
 hipError_t launch_node_h(sph_ctx* c, const sph_particles* s) { return node_props(c, s, false); }
 hipError_t launch_node_boxes(sph_ctx* c, const sph_particles* s) { return node_props(c, s, true); }
 
+// Density and force of groups of 4 or 8 particles go through the neighbour
+// lists; larger groups (and flagged groups) through the walking kernels.
+bool lists_mode(const sph_ctx* c) { return c->kp.n_group == 4 || c->kp.n_group == 8; }
+
+#define SPH_LPI_SWITCH(NG, BODY)      \
+  switch (NG) {                       \
+    case 4: {                         \
+      constexpr int LPI = 16;         \
+      BODY;                           \
+    } break;                          \
+    case 8: {                         \
+      constexpr int LPI = 8;          \
+      BODY;                           \
+    } break;                          \
+    case 16: {                        \
+      constexpr int LPI = 4;          \
+      BODY;                           \
+    } break;                          \
+    default: {                        \
+      constexpr int LPI = 2;          \
+      BODY;                           \
+    } break;                          \
+  }
+
+#define SPH_LPI_SWITCH_LISTS(NG, BODY) \
+  switch (NG) {                        \
+    case 4: {                          \
+      constexpr int LPI = 16;          \
+      BODY;                            \
+    } break;                           \
+    default: {                         \
+      constexpr int LPI = 8;           \
+      BODY;                            \
+    } break;                           \
+  }
+
 template <bool MIXED>
-static hipError_t density_dispatch(sph_ctx* c, const sph_particles* s) {
+static hipError_t density_dispatch(sph_ctx* c, const sph_particles* s, const int32_t* gflag) {
   const Parts p = parts_of(s);
   const dim3 grid(c->walk_blocks), block(64);
-  switch (c->kp.n_group) {
-    case 4:
-      hipLaunchKernelGGL((k_density<MIXED, 16>), grid, block, 0, c->stream, c->kp, p, c->wnode,
-                         c->ginfo, c->frec, c->leaf_pool, c->pool_cap, c->gl_off, c->gl_cnt,
-                         c->ds);
-      break;
-    case 8:
-      hipLaunchKernelGGL((k_density<MIXED, 8>), grid, block, 0, c->stream, c->kp, p, c->wnode,
-                         c->ginfo, c->frec, c->leaf_pool, c->pool_cap, c->gl_off, c->gl_cnt,
-                         c->ds);
-      break;
-    case 16:
-      hipLaunchKernelGGL((k_density<MIXED, 4>), grid, block, 0, c->stream, c->kp, p, c->wnode,
-                         c->ginfo, c->frec, c->leaf_pool, c->pool_cap, c->gl_off, c->gl_cnt,
-                         c->ds);
-      break;
-    default:
-      hipLaunchKernelGGL((k_density<MIXED, 2>), grid, block, 0, c->stream, c->kp, p, c->wnode,
-                         c->ginfo, c->frec, c->leaf_pool, c->pool_cap, c->gl_off, c->gl_cnt,
-                         c->ds);
-      break;
+  SPH_LPI_SWITCH(c->kp.n_group,
+                 hipLaunchKernelGGL((k_density<MIXED, LPI>), grid, block, 0, c->stream, c->kp, p,
+                                    c->wnode, c->ginfo, c->frec, c->leaf_pool, c->pool_cap,
+                                    c->gl_off, c->gl_cnt, gflag, c->ds));
+  return hipGetLastError();
+}
+
+hipError_t launch_density(sph_ctx* c, const sph_particles* s, bool flagged_only) {
+  c->kp.n = c->n;
+  const int32_t* gf = flagged_only ? c->gflag : nullptr;
+  return c->kp.precision == SPH_PREC_MIXED ? density_dispatch<true>(c, s, gf)
+                                           : density_dispatch<false>(c, s, gf);
+}
+
+hipError_t launch_lists(sph_ctx* c, const sph_particles* s) {
+  c->kp.n = c->n;
+  const Parts p = parts_of(s);
+  const dim3 grid(c->walk_blocks), block(64);
+  if (c->kp.precision == SPH_PREC_MIXED) {
+    SPH_LPI_SWITCH_LISTS(c->kp.n_group,
+                         hipLaunchKernelGGL((k_lists<true, LPI>), grid, block, 0, c->stream,
+                                            c->kp, p, c->wnode, c->ginfo, c->nl_idx, c->nl_len,
+                                            c->gflag, c->ds));
+  } else {
+    SPH_LPI_SWITCH_LISTS(c->kp.n_group,
+                         hipLaunchKernelGGL((k_lists<false, LPI>), grid, block, 0, c->stream,
+                                            c->kp, p, c->wnode, c->ginfo, c->nl_idx, c->nl_len,
+                                            c->gflag, c->ds));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_density_lists(sph_ctx* c, const sph_particles* s) {
+  c->kp.n = c->n;
+  const Parts p = parts_of(s);
+  const dim3 grid(c->walk_blocks), block(64);
+  if (c->kp.precision == SPH_PREC_MIXED) {
+    SPH_LPI_SWITCH_LISTS(c->kp.n_group,
+                         hipLaunchKernelGGL((k_density_lists<true, LPI>), grid, block, 0,
+                                            c->stream, c->kp, p, c->ginfo, c->nl_idx, c->nl_len,
+                                            c->gflag, c->frec, c->ds));
+  } else {
+    SPH_LPI_SWITCH_LISTS(c->kp.n_group,
+                         hipLaunchKernelGGL((k_density_lists<false, LPI>), grid, block, 0,
+                                            c->stream, c->kp, p, c->ginfo, c->nl_idx, c->nl_len,
+                                            c->gflag, c->frec, c->ds));
+  }
+  return hipGetLastError();
+}
+
+template <bool MIXED>
+static hipError_t force_dispatch(sph_ctx* c, const sph_particles* s, double* oax, double* oay,
+                                 double* oaz, double* odu, const int32_t* gflag) {
+  const Parts p = parts_of(s);
+  const dim3 grid(c->walk_blocks), block(64);
+  SPH_LPI_SWITCH(c->kp.n_group,
+                 hipLaunchKernelGGL((k_force<MIXED, LPI>), grid, block, 0, c->stream, c->kp, p,
+                                    c->wnode, c->ginfo, c->frec, c->leaf_pool, c->gl_off,
+                                    c->gl_cnt, oax, oay, oaz, odu, gflag, c->ds));
+  return hipGetLastError();
+}
+
+static void force_outputs(sph_ctx* c, const sph_particles* s, bool step_mode, double** o) {
+  o[0] = step_mode ? c->a1 : s->ax;
+  o[1] = step_mode ? c->a1 + c->n_max : s->ay;
+  o[2] = step_mode ? c->a1 + 2 * c->n_max : s->az;
+  o[3] = step_mode ? c->a1 + 3 * c->n_max : s->dudt;
+}
+
+hipError_t launch_force(sph_ctx* c, const sph_particles* s, bool step_mode, bool flagged_only) {
+  c->kp.n = c->n;
+  double* o[4];
+  force_outputs(c, s, step_mode, o);
+  const int32_t* gf = flagged_only ? c->gflag : nullptr;
+  return c->kp.precision == SPH_PREC_MIXED ? force_dispatch<true>(c, s, o[0], o[1], o[2], o[3], gf)
+                                           : force_dispatch<false>(c, s, o[0], o[1], o[2], o[3], gf);
+}
+
+hipError_t launch_force_lists(sph_ctx* c, const sph_particles* s, bool step_mode) {
+  c->kp.n = c->n;
+  double* o[4];
+  force_outputs(c, s, step_mode, o);
+  const Parts p = parts_of(s);
+  const dim3 grid(c->walk_blocks), block(64);
+  if (c->kp.precision == SPH_PREC_MIXED) {
+    SPH_LPI_SWITCH_LISTS(c->kp.n_group,
+                         hipLaunchKernelGGL((k_force_lists<true, LPI>), grid, block, 0,
+                                            c->stream, c->kp, p, c->ginfo, c->frec, c->nl_idx,
+                                            c->nl_len, c->gflag, o[0], o[1], o[2], o[3], c->ds));
+  } else {
+    SPH_LPI_SWITCH_LISTS(c->kp.n_group,
+                         hipLaunchKernelGGL((k_force_lists<false, LPI>), grid, block, 0,
+                                            c->stream, c->kp, p, c->ginfo, c->frec, c->nl_idx,
+                                            c->nl_len, c->gflag, o[0], o[1], o[2], o[3], c->ds));
   }
   return hipGetLastError();
 }
@@ -2081,55 +2815,9 @@ hipError_t launch_leaf_state(sph_ctx* c, int v) {
   return hipGetLastError();
 }
 
-hipError_t launch_density(sph_ctx* c, const sph_particles* s) {
-  c->kp.n = c->n;
-  return c->kp.precision == SPH_PREC_MIXED ? density_dispatch<true>(c, s)
-                                           : density_dispatch<false>(c, s);
-}
-
-template <bool MIXED>
-static hipError_t force_dispatch(sph_ctx* c, const sph_particles* s, double* oax, double* oay,
-                                 double* oaz, double* odu) {
-  const Parts p = parts_of(s);
-  const dim3 grid(c->walk_blocks), block(64);
-  switch (c->kp.n_group) {
-    case 4:
-      hipLaunchKernelGGL((k_force<MIXED, 16>), grid, block, 0, c->stream, c->kp, p, c->wnode,
-                         c->ginfo, c->frec, c->leaf_pool, c->gl_off, c->gl_cnt, oax, oay, oaz,
-                         odu, c->ds);
-      break;
-    case 8:
-      hipLaunchKernelGGL((k_force<MIXED, 8>), grid, block, 0, c->stream, c->kp, p, c->wnode,
-                         c->ginfo, c->frec, c->leaf_pool, c->gl_off, c->gl_cnt, oax, oay, oaz,
-                         odu, c->ds);
-      break;
-    case 16:
-      hipLaunchKernelGGL((k_force<MIXED, 4>), grid, block, 0, c->stream, c->kp, p, c->wnode,
-                         c->ginfo, c->frec, c->leaf_pool, c->gl_off, c->gl_cnt, oax, oay, oaz,
-                         odu, c->ds);
-      break;
-    default:
-      hipLaunchKernelGGL((k_force<MIXED, 2>), grid, block, 0, c->stream, c->kp, p, c->wnode,
-                         c->ginfo, c->frec, c->leaf_pool, c->gl_off, c->gl_cnt, oax, oay, oaz,
-                         odu, c->ds);
-      break;
-  }
-  return hipGetLastError();
-}
-
 hipError_t launch_force_reset(sph_ctx* c) {
   hipLaunchKernelGGL(k_reset_force_state, dim3(1), dim3(64), 0, c->stream, c->ds);
   return hipGetLastError();
-}
-
-hipError_t launch_force(sph_ctx* c, const sph_particles* s, bool step_mode) {
-  c->kp.n = c->n;
-  double* oax = step_mode ? c->a1 : s->ax;
-  double* oay = step_mode ? c->a1 + c->n_max : s->ay;
-  double* oaz = step_mode ? c->a1 + 2 * c->n_max : s->az;
-  double* odu = step_mode ? c->a1 + 3 * c->n_max : s->dudt;
-  return c->kp.precision == SPH_PREC_MIXED ? force_dispatch<true>(c, s, oax, oay, oaz, odu)
-                                           : force_dispatch<false>(c, s, oax, oay, oaz, odu);
 }
 
 hipError_t launch_correct(sph_ctx* c, const sph_particles* s) {

@@ -290,11 +290,12 @@ def sph_neighbours(ctx: Context, p: Particles, mode: int):
     return off, idx[:total]
 
 
-PHASES = ("keys_sort", "permute", "tree", "density", "force", "integrate", "step")
+PHASES = ("keys_sort", "permute", "tree", "density", "force", "integrate", "step",
+          "lists", "density_fallback", "force_fallback")
 
 
 def sph_timings(ctx: Context) -> dict:
-    out = (ctypes.c_double * 8)()
+    out = (ctypes.c_double * 12)()
     _check(ctx.h, ctx.lib.sph_timings(ctx.h, out), "sph_timings")
     return {k: float(out[i]) for i, k in enumerate(PHASES)}
 
@@ -302,7 +303,7 @@ def sph_timings(ctx: Context) -> dict:
 STATS = ("n_nodes", "n_groups", "max_density_sums", "density_pairs", "force_pairs",
          "density_pair_sums", "density_candidates", "force_candidates", "density_walks",
          "error_word", "total_density_pair_sums", "total_force_pairs", "density_launches",
-         "force_launches")
+         "force_launches", "groups_rows_overflow", "groups_h_outgrew")
 
 
 def sph_stats(ctx: Context) -> dict:
