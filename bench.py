@@ -9,10 +9,10 @@ the same steps are also timed in FP64 to give the mixed/FP64 ratio.
 
 Prints ONE JSON line (the last line of stdout).  ``value`` is
 particle-updates/s = N * steps / wall time of the timed steps, with the state
-resident in HBM.  ``roofline`` is for the kernel with the longer launches
-(the density kernel, which also walks the tree, or the force kernel), from
-its algorithmic FLOPs and its average launch time measured with HIP events on
-the library stream; ``second_kernel_roofline`` is the other one.
+resident in HBM.  ``roofline`` is for the kernel with the longest mean launch
+among the neighbour-list, density and force kernels, from its algorithmic
+FLOPs and its mean launch time measured with HIP events on the library
+stream; ``other_kernel_rooflines`` holds the other two.
 ``cpu_baseline`` times the FP64 CPU oracle on the host cores.
 """
 from __future__ import annotations
@@ -37,6 +37,10 @@ FORCE_FLOPS_PER_PAIR = 85
 #   density pair term per smoothing-length pass: q 1, M4 f and f' 14,
 #   two accumulations 7
 DENSITY_FLOPS_PER_PAIR_SUM = 22
+#   candidate test of the neighbour-list kernel: separation 3, r^2 5, list
+#   radius 2 max(hl_i, h_margin h_j) 3, its square with the FP32 guard 2,
+#   compare 1
+LIST_FLOPS_PER_CANDIDATE = 14
 # Vector ALU peak of the 256 CUs at 2.4 GHz for non-packed FP32 (and FP64)
 # FMA: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz.  The published FP32
 # figure of 157.3 TFLOP/s needs packed FP32 instructions, which this build
@@ -91,6 +95,9 @@ def run(cfg, precision, steps, warmup):
     # work per launch over exactly the timed launches
     nd = st["density_launches"] - st0["density_launches"]
     nf = st["force_launches"] - st0["force_launches"]
+    nl = st["lists_launches"] - st0["lists_launches"]
+    st["list_candidates_per_launch"] = \
+        (st["total_list_candidates"] - st0["total_list_candidates"]) / max(nl, 1)
     st["density_pair_sums_per_launch"] = \
         (st["total_density_pair_sums"] - st0["total_density_pair_sums"]) / max(nd, 1)
     st["force_pairs_per_launch"] = (st["total_force_pairs"] - st0["total_force_pairs"]) / max(nf, 1)
@@ -223,8 +230,17 @@ def main():
     dens = roofline(f"k_density<{tag}>", DENSITY_FLOPS_PER_PAIR_SUM * dpl,
                     tim["density"], {"density_pair_sums": dpl},
                     DENSITY_FLOPS_PER_PAIR_SUM, traffic_record("k_density", cfg, tag))
-    # the dominant kernel (longer average launch) carries the headline roofline
-    roof, second = (dens, force) if tim["density"] >= tim["force"] else (force, dens)
+    kernels = [(tim["density"], dens), (tim["force"], force)]
+    if tim.get("lists", 0.0) > 0.0:
+        lpl = st["list_candidates_per_launch"]
+        kernels.append((tim["lists"], roofline(
+            f"k_lists<{tag}>", LIST_FLOPS_PER_CANDIDATE * lpl, tim["lists"],
+            {"candidate_tests": lpl}, LIST_FLOPS_PER_CANDIDATE,
+            traffic_record("k_lists", cfg, tag))))
+    # the dominant kernel (longest mean launch) carries the headline roofline
+    kernels.sort(key=lambda kv: -kv[0])
+    roof = kernels[0][1]
+    others = [k for _, k in kernels[1:]]
     inter = (dpl + fpl) / (main_run["ms_per_step"] * 1e-3)
     out = {
         "metric": METRIC,
@@ -243,7 +259,7 @@ def main():
                    "precision": args.precision, "kernel": "M4", "hfact": cfg["hfact"],
                    "n_leaf": cfg["n_leaf"], "n_group": cfg["n_group"]},
         "roofline": roof,
-        "second_kernel_roofline": second,
+        "other_kernel_rooflines": others,
         "phase_ms": {k: round(v, 5) for k, v in tim.items()},
         "interactions_per_s": inter,
         "true_pairs_per_particle": {"density": st["density_pairs"] / cfg["n"],

@@ -196,8 +196,10 @@ sph_status sph_timings(sph_ctx* ctx, double out[12]);
    launches}; differences of two calls give the work of the launches in
    between.  out[14..15] refer to the last density pass: {groups whose
    neighbour-list rows overflowed, groups in which some h outgrew the rows};
-   both went through the walking kernels.  Synchronises. */
-sph_status sph_stats(sph_ctx* ctx, int64_t out[16]);
+   both went through the walking kernels.  out[16..17] are running totals:
+   {candidate tests of the neighbour-list kernel, its launches}.
+   Synchronises. */
+sph_status sph_stats(sph_ctx* ctx, int64_t out[18]);
 
 /* Human-readable description of the last failure of this context; with
    ctx == NULL, of the last failed sph_create on the calling thread. */

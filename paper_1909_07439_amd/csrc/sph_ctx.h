@@ -84,6 +84,7 @@ struct sph_ctx {
   int32_t* nl_idx = nullptr;   // neighbour-list rows, kNLCap per particle
   int32_t* nl_len = nullptr;   // entries found per particle (may exceed kNLCap)
   int32_t* gflag = nullptr;    // per group: 0 lists complete, 1 row overflow, 2 h outgrew rows
+  int32_t* flag_list = nullptr;  // indices of the flagged groups (DevState::n_flagged of them)
   // density / force
   void* frec = nullptr;        // FRec64 or FRec32 per particle
   double* a1 = nullptr;        // 4 * n_max: new ax, ay, az, dudt inside sph_step
@@ -97,5 +98,6 @@ struct sph_ctx {
   bool timing = true;
   int64_t density_launches = 0;  // launches of the density kernel so far
   int64_t force_launches = 0;    // launches of the force kernel so far
+  int64_t lists_launches = 0;    // launches of the neighbour-list kernel so far
   std::string err;
 };

@@ -256,6 +256,7 @@ sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ct
   ALLOC(c->nl_idx, (int64_t)sph::kNLCap * N);
   ALLOC(c->nl_len, N);
   ALLOC(c->gflag, N);
+  ALLOC(c->flag_list, N);
   {
     const size_t rec = (P.precision == SPH_PREC_MIXED) ? sizeof(sph::FRec32) : sizeof(sph::FRec64);
     e = hipMalloc(&c->frec, rec * (size_t)N);
@@ -318,7 +319,7 @@ void sph_destroy(sph_ctx* c) {
                   c->grp_count, c->ginfo,       c->frec,         c->a1,          c->nb_cnt,
                   c->nb_off,    c->red_part,    c->red_out,      c->ds,
                   c->leaf_pool, c->gl_off,      c->gl_cnt,       c->nl_idx,      c->nl_len,
-                  c->gflag};
+                  c->gflag,     c->flag_list};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->hs) (void)hipHostFree(c->hs);
@@ -357,6 +358,7 @@ static sph_status run_density(sph_ctx* c, sph_particles* p) {
     ph_begin(c, kPhLists);
     HIPCHK(c, sph::launch_lists(c, p));
     ph_end(c, kPhLists);
+    ++c->lists_launches;
     ph_begin(c, kPhDensity);
     HIPCHK(c, sph::launch_density_lists(c, p));
     ph_end(c, kPhDensity);
@@ -594,7 +596,7 @@ sph_status sph_timings(sph_ctx* c, double out[12]) {
   return SPH_OK;
 }
 
-sph_status sph_stats(sph_ctx* c, int64_t out[16]) {
+sph_status sph_stats(sph_ctx* c, int64_t out[18]) {
   if (!c || !out) return SPH_E_ARG;
   HIPCHK(c, hipMemcpyAsync(c->hs, c->ds, sizeof(sph::DevState), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -615,6 +617,8 @@ sph_status sph_stats(sph_ctx* c, int64_t out[16]) {
   out[13] = c->force_launches;
   out[14] = s.n_flag_rows;
   out[15] = s.n_flag_grew;
+  out[16] = (int64_t)s.tot_cand_lists;
+  out[17] = c->lists_launches;
   return SPH_OK;
 }
 

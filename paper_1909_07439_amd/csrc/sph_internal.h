@@ -35,6 +35,8 @@ struct DevState {
   int32_t lists_missing;  // some group needs the walking kernels (h refresh needed)
   int32_t n_flag_rows;    // groups whose neighbour-list rows overflowed (walking kernels)
   int32_t n_flag_grew;    // groups in which some h outgrew the rows (walking kernels)
+  int32_t n_flagged;      // entries of the flagged-group list (both kinds)
+  int32_t pad1;
   double dt_cur;          // step used by the running sph_step
   alignas(256) uint32_t err;
   alignas(256) int32_t max_iter;                  // most density sums any group needed
@@ -47,6 +49,7 @@ struct DevState {
   alignas(256) int32_t n_rewalk;
   alignas(256) unsigned long long tot_sums_density;  // n_sums_density over every launch so far
   alignas(256) unsigned long long tot_pairs_force;   // n_pairs_force over every launch so far
+  alignas(256) unsigned long long tot_cand_lists;    // candidate tests of the list kernel so far
 };
 
 // Walk view of a tree node: centre, conservative half-widths, largest h.

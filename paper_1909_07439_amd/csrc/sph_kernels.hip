@@ -845,7 +845,6 @@ __device__ __forceinline__ double box_gap2(const WalkNode& nd, const GroupInfo& 
 }
 
 struct WalkLds {
-  int front[2][kFCap];
   int lfirst[kLCap];
   int lcnt[kLCap];
   int lnode[kLCap];
@@ -871,10 +870,11 @@ struct TileOf {
 // frontier overflow.
 template <typename RadiusFn, typename FlushFn>
 __device__ bool group_walk(const WalkNode* __restrict__ nodes, const GroupInfo& G,
-                           const KParams& kp, WalkLds& L, RadiusFn open_r, FlushFn flush) {
+                           const KParams& kp, WalkLds& L, int (&front)[2][kFCap],
+                           RadiusFn open_r, FlushFn flush) {
   const int lane = threadIdx.x;
   int nf = 1, cur = 0, nleaf = 0;
-  if (lane == 0) L.front[0][0] = 0;
+  if (lane == 0) front[0][0] = 0;
   __syncthreads();
   bool ok = true;
   while (nf > 0) {
@@ -885,7 +885,7 @@ __device__ bool group_walk(const WalkNode* __restrict__ nodes, const GroupInfo& 
       WalkNode nd;
       bool open = false;
       if (act) {
-        nd = nodes[L.front[cur][k]];
+        nd = nodes[front[cur][k]];
         const double R = open_r(nd);
         open = box_gap2(nd, G, kp) < R * R;
       }
@@ -901,7 +901,7 @@ __device__ bool group_walk(const WalkNode* __restrict__ nodes, const GroupInfo& 
         const int pos = nleaf + popc64(lb & lanemask_lt());
         L.lfirst[pos] = nd.first;
         L.lcnt[pos] = nd.count;
-        L.lnode[pos] = L.front[cur][k];
+        L.lnode[pos] = front[cur][k];
       }
       nleaf += nl;
       const uint32_t nc = inner ? (uint32_t)nd.nchild : 0u;
@@ -911,7 +911,7 @@ __device__ bool group_walk(const WalkNode* __restrict__ nodes, const GroupInfo& 
         ok = false;
       } else {
         const int o = nn + (int)(inc - nc);
-        for (uint32_t q = 0; q < nc; ++q) L.front[cur ^ 1][o + q] = nd.child + (int)q;
+        for (uint32_t q = 0; q < nc; ++q) front[cur ^ 1][o + q] = nd.child + (int)q;
         nn += (int)tot;
       }
       __syncthreads();
@@ -1196,14 +1196,15 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
                                                 int2* __restrict__ pool, int64_t pool_cap,
                                                 int32_t* __restrict__ gl_off,
                                                 int32_t* __restrict__ gl_cnt,
-                                                const int32_t* __restrict__ gflag,
+                                                const int32_t* __restrict__ flag_list,
                                                 DevState* __restrict__ ds) {
   using R = typename std::conditional<MIXED, float, double>::type;
   constexpr int GS = kWave / LPI;
-  // gflag != nullptr: only the groups the neighbour-list kernels flagged,
-  // each with its own walk and without storing leaf lists
-  const bool fb = gflag != nullptr;
+  // flag_list != nullptr: only the groups the neighbour-list kernels
+  // flagged, each with its own walk and without storing leaf lists
+  const bool fb = flag_list != nullptr;
   __shared__ WalkLds L;
+  __shared__ int s_front[2][kFCap];
   __shared__ TileOf<R> T;
   __shared__ R s_r[kPMax * GS];
   __shared__ R s_m[kPMax * GS];
@@ -1214,10 +1215,15 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
   const int ng = ds->n_groups;
   // waves take super-groups of kSG consecutive groups; each XCD a contiguous
   // range of them, so that neighbouring groups share that XCD's L2
-  const int nsg = (ng + kSG - 1) / kSG;
+  // flagged groups are spread one per wavefront (they are few, and heavy)
+  // (striped over all wavefronts of all XCDs)
+  const int sgs = fb ? 1 : kSG;
+  const int nsg = fb ? ds->n_flagged : (ng + sgs - 1) / sgs;
   const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, nloc = gridDim.x >> 3;
   const int chunk = (nsg + 7) >> 3;
-  const int sbeg = xcd * chunk, send = min(sbeg + chunk, nsg);
+  const int sbeg = fb ? (int)blockIdx.x : xcd * chunk;
+  const int send = fb ? nsg : min(sbeg + chunk, nsg);
+  const int sstep = fb ? (int)gridDim.x : nloc;
   const double margin = kp.h_margin;
   double minhalf = SPH_INF;
   for (int a = 0; a < 3; ++a)
@@ -1233,9 +1239,8 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
   int walks = 0;
   bool grew = false;
 
-  for (int sg = sbeg + local; sg < send; sg += nloc) {
-   const int g0 = sg * kSG, g1 = min(g0 + kSG, ng);
-   if (fb && ballot64(lane < g1 - g0 && gflag[g0 + lane] != 0) == 0ull) continue;
+  for (int sg = fb ? sbeg : sbeg + local; sg < send; sg += sstep) {
+   const int g0 = fb ? flag_list[sg] : sg * sgs, g1 = min(g0 + sgs, ng);
    // ---- super-group box (union of the group boxes) and largest start h
    GroupInfo SG;
    {
@@ -1272,15 +1277,12 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
      if (fb) {
        sok = false;  // flagged groups walk on their own
      } else {
-       if (!group_walk(nodes, SG, kp, L, sradius, sflush)) sok = false;
+       if (!group_walk(nodes, SG, kp, L, s_front, sradius, sflush)) sok = false;
        ++walks;
      }
    }
    for (int g = g0; g < g1; ++g) {
-    if (fb) {
-      if (gflag[g] == 0) continue;
-      if (lane == 0) gl_cnt[g] = -1;  // its force pass walks
-    }
+    if (fb && lane == 0) gl_cnt[g] = -1;  // its force pass walks
     const GroupInfo G = groups[g];
     const bool act = slot < G.count;
     const int i = G.first + (act ? slot : 0);
@@ -1368,7 +1370,7 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
         if (store && sok)
           wok = true, list_walk(nodes, s_sl, nsl, G, kp, L, radius, flush);
         else
-          wok = group_walk(nodes, G, kp, L, radius, flush);
+          wok = group_walk(nodes, G, kp, L, s_front, radius, flush);
         if (!wok) {
           err |= kErrFrontier;
           failed = true;
@@ -1436,7 +1438,7 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
           });
           __syncthreads();
         };
-        if (!group_walk(nodes, G, kp, L, radius, flush)) {
+        if (!group_walk(nodes, G, kp, L, s_front, radius, flush)) {
           err |= kErrFrontier;
           failed = true;
         }
@@ -1600,12 +1602,13 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
                                               double* __restrict__ out_ay,
                                               double* __restrict__ out_az,
                                               double* __restrict__ out_du,
-                                              const int32_t* __restrict__ gflag,
+                                              const int32_t* __restrict__ flag_list,
                                               DevState* __restrict__ ds) {
   using Rec = typename FRecOf<MIXED>::T;
   using R = typename std::conditional<MIXED, float, double>::type;
   constexpr int GS = kWave / LPI;
   __shared__ WalkLds L;
+  __shared__ int s_front[2][kFCap];
   __shared__ TileOf<R> T;
   __shared__ int s_j[kPMax * GS];
   const bool use_lists = ds->leaf_state == 1;
@@ -1621,10 +1624,15 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
   unsigned long long pairs = 0, cands = 0;
   double dtmin = SPH_INF;
 
-  for (int g = gbeg + local; g < gend; g += nloc) {
-    // gflag != nullptr: while the neighbour lists hold every pair
-    // (leaf_state 1) the list kernel does the unflagged groups
-    if (gflag != nullptr && use_lists && gflag[g] == 0) continue;
+  // flag_list != nullptr while the neighbour lists hold every pair (leaf_state
+  // 1): the list kernel does the unflagged groups, and the few flagged ones
+  // are striped over all wavefronts
+  const bool only_flagged = flag_list != nullptr && use_lists;
+  const int g_first = only_flagged ? (int)blockIdx.x : gbeg + local;
+  const int g_end = only_flagged ? ds->n_flagged : gend;
+  const int g_step = only_flagged ? (int)gridDim.x : nloc;
+  for (int gk = g_first; gk < g_end; gk += g_step) {
+    const int g = only_flagged ? flag_list[gk] : gk;
     const GroupInfo G = groups[g];
     const bool act = slot < G.count;
     const int i = G.first + (act ? slot : 0);
@@ -1786,7 +1794,7 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
         load_leaves(L, pool, off, b, nl);
         flush(nl);
       }
-    } else if (!group_walk(nodes, G, kp, L, radius, flush)) {
+    } else if (!group_walk(nodes, G, kp, L, s_front, radius, flush)) {
       err |= kErrFrontier;
     }
     __syncthreads();
@@ -1822,7 +1830,7 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
   if (lane == 0) {
     if (b) atomicOr(&ds->err, eall);
     if (pf) atomicAdd(&ds->n_pairs_force, pf);
-    if (pf && gflag == nullptr) atomicAdd(&ds->tot_pairs_force, pf);
+    if (pf && flag_list == nullptr) atomicAdd(&ds->tot_pairs_force, pf);
     if (cd) atomicAdd(&ds->n_cand_force, cd);
     if (dm < SPH_INF) dt_min_update(ds, dm);
   }
@@ -1847,12 +1855,19 @@ __global__ __launch_bounds__(64) void k_lists(KParams kp, Parts p,
                                               int32_t* __restrict__ nl_idx,
                                               int32_t* __restrict__ nl_len,
                                               int32_t* __restrict__ gflag,
+                                              int32_t* __restrict__ flag_list,
                                               DevState* __restrict__ ds) {
   using R = typename std::conditional<MIXED, float, double>::type;
   constexpr int GS = kWave / LPI;
   __shared__ WalkLds L;
-  __shared__ TileOf<R> T;
+  // the frontier is live only during the super-group walk, the candidate
+  // tile only during the group passes: they share their LDS
+  __shared__ union {
+    int front[2][kFCap];
+    TileOf<R> tile;
+  } U;
   __shared__ int s_sl[kSLCap];
+  TileOf<R>& T = U.tile;
   const int lane = threadIdx.x;
   const int slot = lane / LPI, sub = lane % LPI;
   const int ng = ds->n_groups;
@@ -1900,7 +1915,8 @@ __global__ __launch_bounds__(64) void k_lists(KParams kp, Parts p,
         nsl += nleaf;
         __syncthreads();
       };
-      if (!group_walk(nodes, SG, kp, L, sradius, sflush)) sok = false;
+      if (!group_walk(nodes, SG, kp, L, U.front, sradius, sflush)) sok = false;
+      __syncthreads();  // the frontier's LDS becomes the tile
       ++walks;
     }
     for (int g = g0; g < g1; ++g) {
@@ -1952,16 +1968,34 @@ __global__ __launch_bounds__(64) void k_lists(KParams kp, Parts p,
         });
         __syncthreads();
       };
-      bool wok = true;
-      if (sok) {
-        list_walk(nodes, s_sl, nsl, G, kp, L, radius, flush);
-      } else {
-        wok = group_walk(nodes, G, kp, L, radius, flush);
+      // a super-group whose leaf list overflowed: each group walks for its
+      // own leaf list first (the frontier and the tile are never live at
+      // once); a group whose list overflows too is left to the walking kernels
+      bool gok = sok;
+      int ngl = nsl;
+      if (!sok) {
+        ngl = 0;
+        gok = true;
+        auto gflush = [&](int nleaf) {
+          if (ngl + nleaf <= kSLCap) {
+            for (int q = lane; q < nleaf; q += kWave) s_sl[ngl + q] = L.lnode[q];
+          } else {
+            gok = false;
+          }
+          ngl += nleaf;
+          __syncthreads();
+        };
+        if (!group_walk(nodes, G, kp, L, U.front, radius, gflush)) gok = false;
+        __syncthreads();
         ++walks;
       }
+      if (gok) list_walk(nodes, s_sl, ngl, G, kp, L, radius, flush);
       if (act && sub == 0) nl_len[i] = npair;
-      const bool bad = !wok || ballot64(act && npair > kNLCap) != 0ull;
-      if (lane == 0) gflag[g] = bad ? 1 : 0;
+      const bool bad = !gok || ballot64(act && npair > kNLCap) != 0ull;
+      if (lane == 0) {
+        gflag[g] = bad ? 1 : 0;
+        if (bad) flag_list[atomicAdd(&ds->n_flagged, 1)] = g;
+      }
       flagged |= bad;
       nflag += bad ? 1 : 0;
     }
@@ -1970,6 +2004,7 @@ __global__ __launch_bounds__(64) void k_lists(KParams kp, Parts p,
   for (int d = 32; d > 0; d >>= 1) cd += __shfl_xor(cd, d, kWave);
   if (lane == 0) {
     if (cd) atomicAdd(&ds->n_cand_density, cd);
+    if (cd) atomicAdd(&ds->tot_cand_lists, cd);
     if (walks) atomicAdd(&ds->n_rewalk, walks);
     if (flagged) {
       atomicOr(&ds->lists_missing, 1);
@@ -2006,6 +2041,7 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
                                                       const int32_t* __restrict__ nl_idx,
                                                       const int32_t* __restrict__ nl_len,
                                                       int32_t* __restrict__ gflag,
+                                                      int32_t* __restrict__ flag_list,
                                                       void* __restrict__ frec_out,
                                                       DevState* __restrict__ ds) {
   using R = typename std::conditional<MIXED, float, double>::type;
@@ -2174,7 +2210,10 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
       if (ballot64(!conv || moved) == 0ull) break;
     }
     if (ballot64(outgrew) != 0ull) {
-      if (lane == 0) gflag[g] = 2;
+      if (lane == 0) {
+        gflag[g] = 2;
+        flag_list[atomicAdd(&ds->n_flagged, 1)] = g;
+      }
       outgrew_any = true;
       ++ngrew;
       continue;
@@ -2290,15 +2329,21 @@ void k_force_lists(KParams kp, Parts p,
         du += (double)e;
         vmax = fmax(vmax, (double)vsi);
       };
+      // row indices one iteration ahead, so that each iteration waits for
+      // one gather of the two records only
+      int j1 = (sub < len) ? row[sub] : i;
+      int j2 = (sub + LPI < len) ? row[sub + LPI] : i;
       for (int k = sub; k < lmax; k += 2 * LPI) {
-        const int k2 = k + LPI;
-        const bool v1 = k < len, v2 = k2 < len;
-        const int j1 = v1 ? row[k] : i;
-        const int j2 = v2 ? row[k2] : i;
+        const bool v1 = k < len, v2 = k + LPI < len;
         const Rec r1 = rec[j1];
         const Rec r2 = rec[j2];
+        const int kn = k + 2 * LPI;
+        const int jn1 = (kn < len) ? row[kn] : i;
+        const int jn2 = (kn + LPI < len) ? row[kn + LPI] : i;
         if (v1 && j1 != i) pair(r1);
         if (v2 && j2 != i) pair(r2);
+        j1 = jn1;
+        j2 = jn2;
       }
     } else {
       const double al = kp.alpha, be = kp.beta, au = kp.alpha_u;
@@ -2337,12 +2382,15 @@ void k_force_lists(KParams kp, Parts p,
         du += e;
         vmax = fmax(vmax, vsi);
       };
-      // one 128-byte record in flight per lane (registers)
+      // one 128-byte record in flight per lane (registers); row index one
+      // iteration ahead
+      int j = (sub < len) ? row[sub] : i;
       for (int k = sub; k < lmax; k += LPI) {
         const bool v = k < len;
-        const int j = v ? row[k] : i;
         const Rec rj = rec[j];
+        const int jn = (k + LPI < len) ? row[k + LPI] : i;
         if (v && j != i) pair(rj);
+        j = jn;
       }
     }
     ax = seg_sum<LPI>(ax);
@@ -2395,6 +2443,7 @@ __global__ __launch_bounds__(64) void k_neighbours(KParams kp, Parts p, int mode
                                                    int32_t* __restrict__ idx,
                                                    DevState* __restrict__ ds) {
   __shared__ WalkLds L;
+  __shared__ int s_front[2][kFCap];
   __shared__ TileOf<double> T;
   const int lane = threadIdx.x;
   const int slot = lane / LPI, sub = lane % LPI;
@@ -2438,7 +2487,7 @@ __global__ __launch_bounds__(64) void k_neighbours(KParams kp, Parts p, int mode
       });
       __syncthreads();
     };
-    if (!group_walk(nodes, G, kp, L, radius, flush)) err |= kErrFrontier;
+    if (!group_walk(nodes, G, kp, L, s_front, radius, flush)) err |= kErrFrontier;
     if (act && sub == 0 && !idx) counts[i] = cnt;
   }
   if (err) atomicOr(&ds->err, err);
@@ -2459,6 +2508,7 @@ __global__ void k_set_leaf_state(DevState* ds, int v) {
     ds->lists_missing = 0;
     ds->n_flag_rows = 0;
     ds->n_flag_grew = 0;
+    ds->n_flagged = 0;
   }
 }
 
@@ -2479,6 +2529,7 @@ __global__ void k_reset_counters(DevState* ds) {
     ds->lists_missing = 0;
     ds->n_flag_rows = 0;
     ds->n_flag_grew = 0;
+    ds->n_flagged = 0;
   }
 }
 
@@ -2721,7 +2772,7 @@ static hipError_t density_dispatch(sph_ctx* c, const sph_particles* s, const int
 
 hipError_t launch_density(sph_ctx* c, const sph_particles* s, bool flagged_only) {
   c->kp.n = c->n;
-  const int32_t* gf = flagged_only ? c->gflag : nullptr;
+  const int32_t* gf = flagged_only ? c->flag_list : nullptr;
   return c->kp.precision == SPH_PREC_MIXED ? density_dispatch<true>(c, s, gf)
                                            : density_dispatch<false>(c, s, gf);
 }
@@ -2734,12 +2785,12 @@ hipError_t launch_lists(sph_ctx* c, const sph_particles* s) {
     SPH_LPI_SWITCH_LISTS(c->kp.n_group,
                          hipLaunchKernelGGL((k_lists<true, LPI>), grid, block, 0, c->stream,
                                             c->kp, p, c->wnode, c->ginfo, c->nl_idx, c->nl_len,
-                                            c->gflag, c->ds));
+                                            c->gflag, c->flag_list, c->ds));
   } else {
     SPH_LPI_SWITCH_LISTS(c->kp.n_group,
                          hipLaunchKernelGGL((k_lists<false, LPI>), grid, block, 0, c->stream,
                                             c->kp, p, c->wnode, c->ginfo, c->nl_idx, c->nl_len,
-                                            c->gflag, c->ds));
+                                            c->gflag, c->flag_list, c->ds));
   }
   return hipGetLastError();
 }
@@ -2752,12 +2803,12 @@ hipError_t launch_density_lists(sph_ctx* c, const sph_particles* s) {
     SPH_LPI_SWITCH_LISTS(c->kp.n_group,
                          hipLaunchKernelGGL((k_density_lists<true, LPI>), grid, block, 0,
                                             c->stream, c->kp, p, c->ginfo, c->nl_idx, c->nl_len,
-                                            c->gflag, c->frec, c->ds));
+                                            c->gflag, c->flag_list, c->frec, c->ds));
   } else {
     SPH_LPI_SWITCH_LISTS(c->kp.n_group,
                          hipLaunchKernelGGL((k_density_lists<false, LPI>), grid, block, 0,
                                             c->stream, c->kp, p, c->ginfo, c->nl_idx, c->nl_len,
-                                            c->gflag, c->frec, c->ds));
+                                            c->gflag, c->flag_list, c->frec, c->ds));
   }
   return hipGetLastError();
 }
@@ -2785,7 +2836,7 @@ hipError_t launch_force(sph_ctx* c, const sph_particles* s, bool step_mode, bool
   c->kp.n = c->n;
   double* o[4];
   force_outputs(c, s, step_mode, o);
-  const int32_t* gf = flagged_only ? c->gflag : nullptr;
+  const int32_t* gf = flagged_only ? c->flag_list : nullptr;
   return c->kp.precision == SPH_PREC_MIXED ? force_dispatch<true>(c, s, o[0], o[1], o[2], o[3], gf)
                                            : force_dispatch<false>(c, s, o[0], o[1], o[2], o[3], gf);
 }

@@ -303,7 +303,8 @@ def sph_timings(ctx: Context) -> dict:
 STATS = ("n_nodes", "n_groups", "max_density_sums", "density_pairs", "force_pairs",
          "density_pair_sums", "density_candidates", "force_candidates", "density_walks",
          "error_word", "total_density_pair_sums", "total_force_pairs", "density_launches",
-         "force_launches", "groups_rows_overflow", "groups_h_outgrew")
+         "force_launches", "groups_rows_overflow", "groups_h_outgrew",
+         "total_list_candidates", "lists_launches")
 
 
 def sph_stats(ctx: Context) -> dict:
