@@ -12,6 +12,7 @@ constexpr int kTreeTile = 256;   // particles per tree block
 constexpr int kScanTile = 2048;  // elements per scan block
 constexpr int kChunk = 256;     // particles per chunk box of the node-box reduction
 constexpr int kNLCap = 128;     // entries per neighbour-list row
+constexpr int kSpill = 4096;    // walk frontier entries per level beyond LDS, per wavefront
 
 // Per-particle data the force loop reads for a neighbour j (written by the
 // density pass once h, rho, Omega are final).
@@ -85,6 +86,8 @@ struct sph_ctx {
   int32_t* nl_len = nullptr;   // entries found per particle (may exceed kNLCap)
   int32_t* gflag = nullptr;    // per group: 0 lists complete, 1 row overflow, 2 h outgrew rows
   int32_t* flag_list = nullptr;  // indices of the flagged groups (DevState::n_flagged of them)
+  int32_t* walk_spill = nullptr; // 2 * kSpill frontier entries per walk wavefront
+  int32_t* grp_of = nullptr;     // group of each particle (neighbour-list kernel)
   // density / force
   void* frec = nullptr;        // FRec64 or FRec32 per particle
   double* a1 = nullptr;        // 4 * n_max: new ax, ay, az, dudt inside sph_step

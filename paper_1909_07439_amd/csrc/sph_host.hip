@@ -106,7 +106,8 @@ sph_status status_of_err(sph_ctx* c, uint32_t e) {
   if (e & kErrDomain) s += " 2h reaches half a periodic box length;";
   if (e & kErrNoConv) s += " smoothing length did not converge;";
   if (e & kErrNodes) s += " tree node capacity exceeded;";
-  if (e & kErrFrontier) s += " walk frontier capacity exceeded;";
+  if (e & kErrFrontier) s += " walk frontier capacity exceeded (density);";
+  if (e & kErrFrontierForce) s += " walk frontier capacity exceeded (force);";
   if (e & kErrPairs) s += " pair list capacity exceeded;";
   c->err = s;
   if (e & kErrNonFinite) return SPH_E_NONFINITE;
@@ -257,6 +258,8 @@ sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ct
   ALLOC(c->nl_len, N);
   ALLOC(c->gflag, N);
   ALLOC(c->flag_list, N);
+  ALLOC(c->walk_spill, (int64_t)2 * sph::kSpill * c->walk_blocks);
+  ALLOC(c->grp_of, N);
   {
     const size_t rec = (P.precision == SPH_PREC_MIXED) ? sizeof(sph::FRec32) : sizeof(sph::FRec64);
     e = hipMalloc(&c->frec, rec * (size_t)N);
@@ -319,7 +322,7 @@ void sph_destroy(sph_ctx* c) {
                   c->grp_count, c->ginfo,       c->frec,         c->a1,          c->nb_cnt,
                   c->nb_off,    c->red_part,    c->red_out,      c->ds,
                   c->leaf_pool, c->gl_off,      c->gl_cnt,       c->nl_idx,      c->nl_len,
-                  c->gflag,     c->flag_list};
+                  c->gflag,     c->flag_list,   c->walk_spill,   c->grp_of};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->hs) (void)hipHostFree(c->hs);

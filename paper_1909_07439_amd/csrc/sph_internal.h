@@ -22,6 +22,7 @@ enum : uint32_t {
   kErrDomain = 16u,    // 2h >= L/2 on a periodic axis
   kErrNonFinite = 32u,
   kErrLeaves = 64u,
+  kErrFrontierForce = 128u,  // walk frontier capacity in the force pass
 };
 
 // Device-resident scalars of one context.

@@ -808,11 +808,14 @@ __global__ __launch_bounds__(256) void k_range_boxes(
 // Group tree walk (Sect. 3.2): one wavefront per group, breadth-first.  The
 // frontier lives in LDS; nodes are tested 64 at a time, opened inner nodes
 // push their (contiguous) children, opened leaves append (first, count) to an
-// LDS leaf list that is flushed through a candidate loop when it fills.
+// LDS leaf list that is flushed through a candidate loop when it fills.  An
+// inner node that lies wholly within the opening radius is appended whole
+// (its particle range), which keeps the frontier to the nodes that straddle
+// the edge of the search region.
 // The opening test is conservative (a superset); the exact pair predicate is
 // applied in the candidate loop.
 // ============================================================================
-constexpr int kFCap = 512;  // frontier entries per level
+constexpr int kFCap = 512;  // frontier entries per level in LDS
 constexpr int kLCap = 128;  // leaves per flush
 constexpr int kPMax = 128;  // pairs per particle slot
 constexpr int kTile = 256;  // candidates staged in LDS at a time
@@ -827,6 +830,22 @@ __device__ __forceinline__ double fold(double d, double len, double half, int pe
       d += len;
   }
   return d;
+}
+
+// Largest squared distance between a point of the group box and a point of
+// the node box, along the nearest periodic image of the centres (an upper
+// bound of the minimum-image distance of every such pair).
+__device__ __forceinline__ double box_far2(const WalkNode& nd, const GroupInfo& G,
+                                           const KParams& kp) {
+  double d2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double dc = nd.c[a] - G.c[a];
+    if (kp.periodic[a]) dc = dc - kp.len[a] * rint(dc * kp.inv_len[a]);
+    const double far = fabs(dc) + (double)nd.w[a] + G.w[a];
+    d2 = d2 + far * far;
+  }
+  return d2;
 }
 
 // min-image squared distance between a node box and the group box
@@ -866,13 +885,29 @@ struct TileOf {
 };
 
 // Breadth-first walk.  open_r(node) returns the opening radius for a node;
-// flush(nleaf) consumes the leaf list (loff filled).  Returns false on
+// flush(nleaf) consumes the leaf list (loff filled).  A level's frontier
+// holds kFCap entries in LDS and continues in this wavefront's region of
+// global memory (`spill`, kSpill entries per level; search regions much
+// larger than the local particle spacing need it).  Returns false on
 // frontier overflow.
 template <typename RadiusFn, typename FlushFn>
 __device__ bool group_walk(const WalkNode* __restrict__ nodes, const GroupInfo& G,
                            const KParams& kp, WalkLds& L, int (&front)[2][kFCap],
-                           RadiusFn open_r, FlushFn flush) {
+                           int* __restrict__ spill, RadiusFn open_r, FlushFn flush) {
   const int lane = threadIdx.x;
+  const int cap = kFCap + kSpill;
+  auto fget = [&](int lvl, int k) -> int {
+    return k < kFCap ? front[lvl][k]
+                     : __hip_atomic_load(&spill[lvl * kSpill + (k - kFCap)], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+  };
+  auto fput = [&](int lvl, int k, int v) {
+    if (k < kFCap)
+      front[lvl][k] = v;
+    else
+      __hip_atomic_store(&spill[lvl * kSpill + (k - kFCap)], v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  };
   int nf = 1, cur = 0, nleaf = 0;
   if (lane == 0) front[0][0] = 0;
   __syncthreads();
@@ -883,14 +918,19 @@ __device__ bool group_walk(const WalkNode* __restrict__ nodes, const GroupInfo& 
       const int k = base + lane;
       const bool act = k < nf;
       WalkNode nd;
-      bool open = false;
+      bool open = false, inside = false;
+      int id = 0;
       if (act) {
-        nd = nodes[front[cur][k]];
+        id = fget(cur, k);
+        nd = nodes[id];
         const double R = open_r(nd);
         open = box_gap2(nd, G, kp) < R * R;
+        // an inner node wholly within the radius of every point of the group
+        // box is taken whole, like a leaf: all of its leaves would be opened
+        inside = open && nd.nchild > 0 && box_far2(nd, G, kp) < R * R;
       }
-      const bool leaf = open && nd.nchild == 0;
-      const bool inner = open && nd.nchild > 0;
+      const bool leaf = open && (nd.nchild == 0 || inside);
+      const bool inner = open && nd.nchild > 0 && !inside;
       const uint64_t lb = ballot64(leaf);
       const int nl = popc64(lb);
       if (nleaf + nl > kLCap) {
@@ -901,17 +941,17 @@ __device__ bool group_walk(const WalkNode* __restrict__ nodes, const GroupInfo& 
         const int pos = nleaf + popc64(lb & lanemask_lt());
         L.lfirst[pos] = nd.first;
         L.lcnt[pos] = nd.count;
-        L.lnode[pos] = front[cur][k];
+        L.lnode[pos] = id;
       }
       nleaf += nl;
       const uint32_t nc = inner ? (uint32_t)nd.nchild : 0u;
       const uint32_t inc = wave_incl_scan_u32(nc);
       const uint32_t tot = __shfl(inc, kWave - 1, kWave);
-      if (nn + (int)tot > kFCap) {
+      if (nn + (int)tot > cap) {
         ok = false;
       } else {
         const int o = nn + (int)(inc - nc);
-        for (uint32_t q = 0; q < nc; ++q) front[cur ^ 1][o + q] = nd.child + (int)q;
+        for (uint32_t q = 0; q < nc; ++q) fput(cur ^ 1, o + q, nd.child + (int)q);
         nn += (int)tot;
       }
       __syncthreads();
@@ -1197,7 +1237,9 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
                                                 int32_t* __restrict__ gl_off,
                                                 int32_t* __restrict__ gl_cnt,
                                                 const int32_t* __restrict__ flag_list,
-                                                DevState* __restrict__ ds) {
+                                                int32_t* __restrict__ walk_spill,
+    DevState* __restrict__ ds) {
+  int* __restrict__ spill = walk_spill + (int64_t)blockIdx.x * 2 * kSpill;
   using R = typename std::conditional<MIXED, float, double>::type;
   constexpr int GS = kWave / LPI;
   // flag_list != nullptr: only the groups the neighbour-list kernels
@@ -1240,11 +1282,11 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
   bool grew = false;
 
   for (int sg = fb ? sbeg : sbeg + local; sg < send; sg += sstep) {
-   const int g0 = fb ? flag_list[sg] : sg * sgs, g1 = min(g0 + sgs, ng);
+   const int g0 = fb ? flag_list[sg] : sg * sgs, g1 = fb ? g0 + 1 : min(g0 + sgs, ng);
    // ---- super-group box (union of the group boxes) and largest start h
    GroupInfo SG;
    {
-     const bool v = lane < g1 - g0;
+     const bool v = !fb && lane < g1 - g0;
      GroupInfo Gk;
      if (v) Gk = groups[g0 + lane];
      for (int a = 0; a < 3; ++a) {
@@ -1277,7 +1319,7 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
      if (fb) {
        sok = false;  // flagged groups walk on their own
      } else {
-       if (!group_walk(nodes, SG, kp, L, s_front, sradius, sflush)) sok = false;
+       if (!group_walk(nodes, SG, kp, L, s_front, spill, sradius, sflush)) sok = false;
        ++walks;
      }
    }
@@ -1370,7 +1412,7 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
         if (store && sok)
           wok = true, list_walk(nodes, s_sl, nsl, G, kp, L, radius, flush);
         else
-          wok = group_walk(nodes, G, kp, L, s_front, radius, flush);
+          wok = group_walk(nodes, G, kp, L, s_front, spill, radius, flush);
         if (!wok) {
           err |= kErrFrontier;
           failed = true;
@@ -1438,7 +1480,7 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
           });
           __syncthreads();
         };
-        if (!group_walk(nodes, G, kp, L, s_front, radius, flush)) {
+        if (!group_walk(nodes, G, kp, L, s_front, spill, radius, flush)) {
           err |= kErrFrontier;
           failed = true;
         }
@@ -1603,7 +1645,9 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
                                               double* __restrict__ out_az,
                                               double* __restrict__ out_du,
                                               const int32_t* __restrict__ flag_list,
-                                              DevState* __restrict__ ds) {
+                                              int32_t* __restrict__ walk_spill,
+    DevState* __restrict__ ds) {
+  int* __restrict__ spill = walk_spill + (int64_t)blockIdx.x * 2 * kSpill;
   using Rec = typename FRecOf<MIXED>::T;
   using R = typename std::conditional<MIXED, float, double>::type;
   constexpr int GS = kWave / LPI;
@@ -1794,8 +1838,8 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
         load_leaves(L, pool, off, b, nl);
         flush(nl);
       }
-    } else if (!group_walk(nodes, G, kp, L, s_front, radius, flush)) {
-      err |= kErrFrontier;
+    } else if (!group_walk(nodes, G, kp, L, s_front, spill, radius, flush)) {
+      err |= kErrFrontierForce;
     }
     __syncthreads();
     compute();
@@ -1846,7 +1890,9 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
 // grows past its hl, a row is a superset of the density neighbours (r < 2 h_i)
 // and of the force pairs (r < 2 max(h_i, h_j)); the density and force list
 // kernels apply the exact predicates.  A group with an overflowing row or a
-// failed walk is flagged (gflag = 1) and left to the walking kernels.
+// failed walk is flagged (gflag = 1) and left to the walking kernels.  The
+// group of every particle is kept (grp_of) for the list kernels, which work
+// on chunks of consecutive particles instead of groups.
 // ============================================================================
 template <bool MIXED, int LPI>
 __global__ __launch_bounds__(64) void k_lists(KParams kp, Parts p,
@@ -1856,7 +1902,10 @@ __global__ __launch_bounds__(64) void k_lists(KParams kp, Parts p,
                                               int32_t* __restrict__ nl_len,
                                               int32_t* __restrict__ gflag,
                                               int32_t* __restrict__ flag_list,
-                                              DevState* __restrict__ ds) {
+                                              int32_t* __restrict__ grp_of,
+                                              int32_t* __restrict__ walk_spill,
+    DevState* __restrict__ ds) {
+  int* __restrict__ spill = walk_spill + (int64_t)blockIdx.x * 2 * kSpill;
   using R = typename std::conditional<MIXED, float, double>::type;
   constexpr int GS = kWave / LPI;
   __shared__ WalkLds L;
@@ -1880,7 +1929,6 @@ __global__ __launch_bounds__(64) void k_lists(KParams kp, Parts p,
   int nflag = 0;
   unsigned long long cands = 0;
   int walks = 0;
-  (void)GS;
 
   for (int sg = sbeg + local; sg < send; sg += nloc) {
     const int g0 = sg * kSG, g1 = min(g0 + kSG, ng);
@@ -1915,83 +1963,90 @@ __global__ __launch_bounds__(64) void k_lists(KParams kp, Parts p,
         nsl += nleaf;
         __syncthreads();
       };
-      if (!group_walk(nodes, SG, kp, L, U.front, sradius, sflush)) sok = false;
+      if (!group_walk(nodes, SG, kp, L, U.front, spill, sradius, sflush)) sok = false;
       __syncthreads();  // the frontier's LDS becomes the tile
       ++walks;
     }
     for (int g = g0; g < g1; ++g) {
       const GroupInfo G = groups[g];
-      const bool act = slot < G.count;
-      const int i = G.first + (act ? slot : 0);
-      const double xi = p.x[i], yi = p.y[i], zi = p.z[i];
-      const double hl = margin * p.h[i];
-      float xr = 0.f, yr = 0.f, zr = 0.f;
-      if constexpr (MIXED) {
-        xr = (float)fold(xi - G.c[0], kp.len[0], kp.half[0], kp.periodic[0]);
-        yr = (float)fold(yi - G.c[1], kp.len[1], kp.half[1], kp.periodic[1]);
-        zr = (float)fold(zi - G.c[2], kp.len[2], kp.half[2], kp.periodic[2]);
-      }
-      const float hlf = (float)hl, marginf = (float)margin;
-      const double hm = wave_max_f64(act ? hl : 0.0);
-      int32_t* __restrict__ row = nl_idx + (int64_t)i * kNLCap;
-      int npair = 0;
-      auto radius = [&](const WalkNode& nd) {
-        return 2.0 * fmax(hm, margin * (double)nd.hmax) * (1.0 + 4e-9);
-      };
-      auto flush = [&](int nleaf) {
-        const int total = leaf_offsets(L, nleaf);
-        cands += (unsigned long long)total * ((act && sub == 0) ? 1u : 0u);
-        for_tiles<LPI, R>(L, nleaf, total, sub, p.x, p.y, p.z, p.h, T, G, kp,
-                          [&](bool valid, int c) {
-          bool pred = false;
-          const int j = valid ? T.j[c] : -1;
-          if (valid && act) {
-            if constexpr (MIXED) {
-              const float dx = xr - T.x[c], dy = yr - T.y[c], dz = zr - T.z[c];
-              const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-              const float sr = 2.0f * fmaxf(hlf, marginf * T.a[c]);
-              pred = r2 < sr * sr * 1.00001f;
-            } else {
-              const double dx = fold(xi - T.x[c], kp.len[0], kp.half[0], kp.periodic[0]);
-              const double dy = fold(yi - T.y[c], kp.len[1], kp.half[1], kp.periodic[1]);
-              const double dz = fold(zi - T.z[c], kp.len[2], kp.half[2], kp.periodic[2]);
-              const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-              const double sr = 2.0 * fmax(hl, margin * T.a[c]);
-              pred = r2 < sr * sr;
+      // rows of the particles of G; true if G must go to the walking kernels
+      auto unit = [&](const GroupInfo& G) -> bool {
+        const bool act = slot < G.count;
+        const int i = G.first + (act ? slot : 0);
+        const double xi = p.x[i], yi = p.y[i], zi = p.z[i];
+        const double hl = margin * p.h[i];
+        float xr = 0.f, yr = 0.f, zr = 0.f;
+        if constexpr (MIXED) {
+          xr = (float)fold(xi - G.c[0], kp.len[0], kp.half[0], kp.periodic[0]);
+          yr = (float)fold(yi - G.c[1], kp.len[1], kp.half[1], kp.periodic[1]);
+          zr = (float)fold(zi - G.c[2], kp.len[2], kp.half[2], kp.periodic[2]);
+        }
+        const float hlf = (float)hl, marginf = (float)margin;
+        const double hm = wave_max_f64(act ? hl : 0.0);
+        int32_t* __restrict__ row = nl_idx + (int64_t)i * kNLCap;
+        int npair = 0;
+        auto radius = [&](const WalkNode& nd) {
+          return 2.0 * fmax(hm, margin * (double)nd.hmax) * (1.0 + 4e-9);
+        };
+        auto flush = [&](int nleaf) {
+          const int total = leaf_offsets(L, nleaf);
+          cands += (unsigned long long)total * ((act && sub == 0) ? 1u : 0u);
+          for_tiles<LPI, R>(L, nleaf, total, sub, p.x, p.y, p.z, p.h, T, G, kp,
+                            [&](bool valid, int c) {
+            bool pred = false;
+            const int j = valid ? T.j[c] : -1;
+            if (valid && act) {
+              if constexpr (MIXED) {
+                const float dx = xr - T.x[c], dy = yr - T.y[c], dz = zr - T.z[c];
+                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                const float sr = 2.0f * fmaxf(hlf, marginf * T.a[c]);
+                pred = r2 < sr * sr * 1.00001f;
+              } else {
+                const double dx = fold(xi - T.x[c], kp.len[0], kp.half[0], kp.periodic[0]);
+                const double dy = fold(yi - T.y[c], kp.len[1], kp.half[1], kp.periodic[1]);
+                const double dz = fold(zi - T.z[c], kp.len[2], kp.half[2], kp.periodic[2]);
+                const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                const double sr = 2.0 * fmax(hl, margin * T.a[c]);
+                pred = r2 < sr * sr;
+              }
             }
-          }
-          const uint64_t b = ballot64(pred);
-          const uint32_t seg = (uint32_t)((b >> (slot * LPI)) & ((LPI == 64) ? ~0ull : ((1ull << LPI) - 1ull)));
-          const int pos = npair + __popc(seg & ((1u << sub) - 1u));
-          if (pred && pos < kNLCap) row[pos] = j;
-          npair += __popc(seg);
-        });
-        __syncthreads();
-      };
-      // a super-group whose leaf list overflowed: each group walks for its
-      // own leaf list first (the frontier and the tile are never live at
-      // once); a group whose list overflows too is left to the walking kernels
-      bool gok = sok;
-      int ngl = nsl;
-      if (!sok) {
-        ngl = 0;
-        gok = true;
-        auto gflush = [&](int nleaf) {
-          if (ngl + nleaf <= kSLCap) {
-            for (int q = lane; q < nleaf; q += kWave) s_sl[ngl + q] = L.lnode[q];
-          } else {
-            gok = false;
-          }
-          ngl += nleaf;
+            const uint64_t b = ballot64(pred);
+            const uint32_t seg = (uint32_t)((b >> (slot * LPI)) & ((LPI == 64) ? ~0ull : ((1ull << LPI) - 1ull)));
+            const int pos = npair + __popc(seg & ((1u << sub) - 1u));
+            if (pred && pos < kNLCap) row[pos] = j;
+            npair += __popc(seg);
+          });
           __syncthreads();
         };
-        if (!group_walk(nodes, G, kp, L, U.front, radius, gflush)) gok = false;
-        __syncthreads();
-        ++walks;
-      }
-      if (gok) list_walk(nodes, s_sl, ngl, G, kp, L, radius, flush);
-      if (act && sub == 0) nl_len[i] = npair;
-      const bool bad = !gok || ballot64(act && npair > kNLCap) != 0ull;
+        // a super-group whose leaf list overflowed: each group walks for its
+        // own leaf list first (the frontier and the tile are never live at
+        // once); a group whose list overflows too is left to the walking kernels
+        bool gok = sok;
+        int ngl = nsl;
+        if (!sok) {
+          ngl = 0;
+          gok = true;
+          auto gflush = [&](int nleaf) {
+            if (ngl + nleaf <= kSLCap) {
+              for (int q = lane; q < nleaf; q += kWave) s_sl[ngl + q] = L.lnode[q];
+            } else {
+              gok = false;
+            }
+            ngl += nleaf;
+            __syncthreads();
+          };
+          if (!group_walk(nodes, G, kp, L, U.front, spill, radius, gflush)) gok = false;
+          __syncthreads();
+          ++walks;
+        }
+        if (gok) list_walk(nodes, s_sl, ngl, G, kp, L, radius, flush);
+        if (act && sub == 0) {
+          nl_len[i] = npair;
+          grp_of[i] = g;
+        }
+        return !gok || ballot64(act && npair > kNLCap) != 0ull;
+      };
+      const bool bad = unit(G);
       if (lane == 0) {
         gflag[g] = bad ? 1 : 0;
         if (bad) flag_list[atomicAdd(&ds->n_flagged, 1)] = g;
@@ -2042,6 +2097,7 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
                                                       const int32_t* __restrict__ nl_len,
                                                       int32_t* __restrict__ gflag,
                                                       int32_t* __restrict__ flag_list,
+                                                      const int32_t* __restrict__ grp_of,
                                                       void* __restrict__ frec_out,
                                                       DevState* __restrict__ ds) {
   using R = typename std::conditional<MIXED, float, double>::type;
@@ -2051,7 +2107,9 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
   __shared__ R s_m[kNLCap * GS];
   const int lane = threadIdx.x;
   const int slot = lane / LPI, sub = lane % LPI;
-  const GroupRange gr = xcd_groups(ds->n_groups);
+  constexpr int CS = kWave / LPI;  // particles per chunk
+  const int nch = (kp.n + CS - 1) / CS;
+  const GroupRange gr = xcd_groups(nch);
   const double margin = kp.h_margin;
   double minhalf = SPH_INF;
   for (int a = 0; a < 3; ++a)
@@ -2063,10 +2121,13 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
   int ngrew = 0;
 
   for (int g = gr.beg; g < gr.end; g += gr.step) {
-    if (gflag[g] != 0) continue;
-    const GroupInfo G = groups[g];
-    const bool act = slot < G.count;
-    const int i = G.first + (act ? slot : 0);
+    const int first = g * CS, count = min(CS, kp.n - first);
+    const bool inr = slot < count;
+    const int i = first + (inr ? slot : 0);
+    // particles of groups the list kernel flagged are left to the walking kernel
+    const int gi = grp_of[i];
+    const bool act = inr && gflag[gi] == 0;
+    if (ballot64(act) == 0ull) continue;
     const double xi = p.x[i], yi = p.y[i], zi = p.z[i], mi = p.m[i];
     double h = p.h[i];
     if (!(h > 0.0) || !isfinite(h)) {
@@ -2210,12 +2271,12 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
       if (ballot64(!conv || moved) == 0ull) break;
     }
     if (ballot64(outgrew) != 0ull) {
-      if (lane == 0) {
-        gflag[g] = 2;
-        flag_list[atomicAdd(&ds->n_flagged, 1)] = g;
+      // the groups of every particle of this chunk go to the walking kernel
+      if (act && sub == 0 && atomicCAS(&gflag[gi], 0, 2) == 0) {
+        flag_list[atomicAdd(&ds->n_flagged, 1)] = gi;
+        ++ngrew;
       }
       outgrew_any = true;
-      ++ngrew;
       continue;
     }
     it_max = max(it_max, nit + 1);
@@ -2232,7 +2293,9 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
   for (int d = 32; d > 0; d >>= 1) {
     pf += __shfl_xor(pf, d, kWave);
     sm += __shfl_xor(sm, d, kWave);
+    ngrew += __shfl_xor(ngrew, d, kWave);
   }
+  outgrew_any = ballot64(outgrew_any) != 0ull;
   if (lane == 0) {
     if (b) atomicOr(&ds->err, eall);
     if (it_max > 0) atomicMax(&ds->max_iter, it_max);
@@ -2263,6 +2326,7 @@ void k_force_lists(KParams kp, Parts p,
                                                     const int32_t* __restrict__ nl_idx,
                                                     const int32_t* __restrict__ nl_len,
                                                     const int32_t* __restrict__ gflag,
+                                                    const int32_t* __restrict__ grp_of,
                                                     double* __restrict__ out_ax,
                                                     double* __restrict__ out_ay,
                                                     double* __restrict__ out_az,
@@ -2273,16 +2337,20 @@ void k_force_lists(KParams kp, Parts p,
   const Rec* __restrict__ rec = reinterpret_cast<const Rec*>(frec_in);
   const int lane = threadIdx.x;
   const int slot = lane / LPI, sub = lane % LPI;
-  const GroupRange gr = xcd_groups(ds->n_groups);
+  constexpr int CS = kWave / LPI;  // particles per chunk
+  const int nch = (kp.n + CS - 1) / CS;
+  const GroupRange gr = xcd_groups(nch);
   uint32_t err = 0;
   unsigned long long pairs = 0, cands = 0;
   double dtmin = SPH_INF;
 
   for (int g = gr.beg; g < gr.end; g += gr.step) {
-    if (gflag[g] != 0) continue;
-    const GroupInfo G = groups[g];
-    const bool act = slot < G.count;
-    const int i = G.first + (act ? slot : 0);
+    const int first = g * CS, count = min(CS, kp.n - first);
+    const bool inr = slot < count;
+    const int i = first + (inr ? slot : 0);
+    // particles of flagged groups are left to the walking kernel
+    const bool act = inr && gflag[grp_of[i]] == 0;
+    if (ballot64(act) == 0ull) continue;
     const double xi = p.x[i], yi = p.y[i], zi = p.z[i], hi = p.h[i];
     const Rec ri = rec[i];
     const int len = act ? nl_len[i] : 0;
@@ -2441,7 +2509,9 @@ __global__ __launch_bounds__(64) void k_neighbours(KParams kp, Parts p, int mode
                                                    int32_t* __restrict__ counts,
                                                    const int64_t* __restrict__ offsets,
                                                    int32_t* __restrict__ idx,
-                                                   DevState* __restrict__ ds) {
+                                                   int32_t* __restrict__ walk_spill,
+    DevState* __restrict__ ds) {
+  int* __restrict__ spill = walk_spill + (int64_t)blockIdx.x * 2 * kSpill;
   __shared__ WalkLds L;
   __shared__ int s_front[2][kFCap];
   __shared__ TileOf<double> T;
@@ -2487,7 +2557,7 @@ __global__ __launch_bounds__(64) void k_neighbours(KParams kp, Parts p, int mode
       });
       __syncthreads();
     };
-    if (!group_walk(nodes, G, kp, L, s_front, radius, flush)) err |= kErrFrontier;
+    if (!group_walk(nodes, G, kp, L, s_front, spill, radius, flush)) err |= kErrFrontier;
     if (act && sub == 0 && !idx) counts[i] = cnt;
   }
   if (err) atomicOr(&ds->err, err);
@@ -2766,7 +2836,7 @@ static hipError_t density_dispatch(sph_ctx* c, const sph_particles* s, const int
   SPH_LPI_SWITCH(c->kp.n_group,
                  hipLaunchKernelGGL((k_density<MIXED, LPI>), grid, block, 0, c->stream, c->kp, p,
                                     c->wnode, c->ginfo, c->frec, c->leaf_pool, c->pool_cap,
-                                    c->gl_off, c->gl_cnt, gflag, c->ds));
+                                    c->gl_off, c->gl_cnt, gflag, c->walk_spill, c->ds));
   return hipGetLastError();
 }
 
@@ -2785,12 +2855,14 @@ hipError_t launch_lists(sph_ctx* c, const sph_particles* s) {
     SPH_LPI_SWITCH_LISTS(c->kp.n_group,
                          hipLaunchKernelGGL((k_lists<true, LPI>), grid, block, 0, c->stream,
                                             c->kp, p, c->wnode, c->ginfo, c->nl_idx, c->nl_len,
-                                            c->gflag, c->flag_list, c->ds));
+                                            c->gflag, c->flag_list, c->grp_of, c->walk_spill,
+                                            c->ds));
   } else {
     SPH_LPI_SWITCH_LISTS(c->kp.n_group,
                          hipLaunchKernelGGL((k_lists<false, LPI>), grid, block, 0, c->stream,
                                             c->kp, p, c->wnode, c->ginfo, c->nl_idx, c->nl_len,
-                                            c->gflag, c->flag_list, c->ds));
+                                            c->gflag, c->flag_list, c->grp_of, c->walk_spill,
+                                            c->ds));
   }
   return hipGetLastError();
 }
@@ -2803,12 +2875,12 @@ hipError_t launch_density_lists(sph_ctx* c, const sph_particles* s) {
     SPH_LPI_SWITCH_LISTS(c->kp.n_group,
                          hipLaunchKernelGGL((k_density_lists<true, LPI>), grid, block, 0,
                                             c->stream, c->kp, p, c->ginfo, c->nl_idx, c->nl_len,
-                                            c->gflag, c->flag_list, c->frec, c->ds));
+                                            c->gflag, c->flag_list, c->grp_of, c->frec, c->ds));
   } else {
     SPH_LPI_SWITCH_LISTS(c->kp.n_group,
                          hipLaunchKernelGGL((k_density_lists<false, LPI>), grid, block, 0,
                                             c->stream, c->kp, p, c->ginfo, c->nl_idx, c->nl_len,
-                                            c->gflag, c->flag_list, c->frec, c->ds));
+                                            c->gflag, c->flag_list, c->grp_of, c->frec, c->ds));
   }
   return hipGetLastError();
 }
@@ -2821,7 +2893,7 @@ static hipError_t force_dispatch(sph_ctx* c, const sph_particles* s, double* oax
   SPH_LPI_SWITCH(c->kp.n_group,
                  hipLaunchKernelGGL((k_force<MIXED, LPI>), grid, block, 0, c->stream, c->kp, p,
                                     c->wnode, c->ginfo, c->frec, c->leaf_pool, c->gl_off,
-                                    c->gl_cnt, oax, oay, oaz, odu, gflag, c->ds));
+                                    c->gl_cnt, oax, oay, oaz, odu, gflag, c->walk_spill, c->ds));
   return hipGetLastError();
 }
 
@@ -2851,12 +2923,14 @@ hipError_t launch_force_lists(sph_ctx* c, const sph_particles* s, bool step_mode
     SPH_LPI_SWITCH_LISTS(c->kp.n_group,
                          hipLaunchKernelGGL((k_force_lists<true, LPI>), grid, block, 0,
                                             c->stream, c->kp, p, c->ginfo, c->frec, c->nl_idx,
-                                            c->nl_len, c->gflag, o[0], o[1], o[2], o[3], c->ds));
+                                            c->nl_len, c->gflag, c->grp_of, o[0], o[1], o[2], o[3],
+                                            c->ds));
   } else {
     SPH_LPI_SWITCH_LISTS(c->kp.n_group,
                          hipLaunchKernelGGL((k_force_lists<false, LPI>), grid, block, 0,
                                             c->stream, c->kp, p, c->ginfo, c->frec, c->nl_idx,
-                                            c->nl_len, c->gflag, o[0], o[1], o[2], o[3], c->ds));
+                                            c->nl_len, c->gflag, c->grp_of, o[0], o[1], o[2], o[3],
+                                            c->ds));
   }
   return hipGetLastError();
 }
@@ -2897,19 +2971,19 @@ hipError_t launch_neighbours(sph_ctx* c, const sph_particles* s, int mode, int32
   switch (c->kp.n_group) {
     case 4:
       hipLaunchKernelGGL((k_neighbours<16>), grid, block, 0, c->stream, c->kp, p, mode, c->wnode,
-                         c->ginfo, counts, offsets, idx, c->ds);
+                         c->ginfo, counts, offsets, idx, c->walk_spill, c->ds);
       break;
     case 8:
       hipLaunchKernelGGL((k_neighbours<8>), grid, block, 0, c->stream, c->kp, p, mode, c->wnode,
-                         c->ginfo, counts, offsets, idx, c->ds);
+                         c->ginfo, counts, offsets, idx, c->walk_spill, c->ds);
       break;
     case 16:
       hipLaunchKernelGGL((k_neighbours<4>), grid, block, 0, c->stream, c->kp, p, mode, c->wnode,
-                         c->ginfo, counts, offsets, idx, c->ds);
+                         c->ginfo, counts, offsets, idx, c->walk_spill, c->ds);
       break;
     default:
       hipLaunchKernelGGL((k_neighbours<2>), grid, block, 0, c->stream, c->kp, p, mode, c->wnode,
-                         c->ginfo, counts, offsets, idx, c->ds);
+                         c->ginfo, counts, offsets, idx, c->walk_spill, c->ds);
       break;
   }
   return hipGetLastError();
