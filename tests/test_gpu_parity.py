@@ -302,3 +302,52 @@ def test_many_neighbours_use_streaming_density_and_chunked_force(precision):
         # the FP32 filter admits pairs up to a relative 1e-5 beyond 2h (where F = 0)
         assert abs(info["stats"]["force_pairs"] - int(o["nneigh_force"].sum())) \
             <= 1e-4 * o["nneigh_force"].sum()
+
+
+@pytest.mark.parametrize("n_group", [4, 16, 32])
+def test_density_force_other_group_sizes(n_group):
+    """n_group 4 runs the neighbour-list kernels with 16 lanes per particle;
+    16 and 32 run the walking kernels for every group."""
+    cfg = inputs.lattice(16, jitter=0.3, velocities=True)
+    cfg["n_group"] = n_group
+    g, ctx, parts, info = gpu_eval(cfg)
+    o = oracle.evaluate(cfg, oracle.make_params(cfg))
+    compare_fp64(g, o)
+    assert info["stats"]["force_pairs"] == int(o["nneigh_force"].sum())
+
+
+@pytest.mark.parametrize("precision", [sph.SPH_PREC_FP64, sph.SPH_PREC_MIXED])
+def test_smoothing_length_outgrowing_the_lists(precision):
+    """Start values of h far below the root: h grows past the list radius
+    (h_margin times the start h), the affected groups are redone by the
+    walking kernels and the force walks for every group."""
+    cfg = inputs.lattice(14, jitter=0.3, velocities=True)
+    cfg["h"] = cfg["h"] * 0.7
+    g, ctx, parts, info = gpu_eval(cfg, precision)
+    assert info["stats"]["groups_h_outgrew"] > 0
+    o = oracle.evaluate(cfg, oracle.make_params(cfg))
+    if precision == sph.SPH_PREC_FP64:
+        compare_fp64(g, o)
+        assert info["stats"]["force_pairs"] == int(o["nneigh_force"].sum())
+    else:
+        assert rel_err(g["rho"], o["rho"]).max() < 1e-5
+        assert max((np.abs(g[k] - o[k]) / o["anorm"]).max() for k in ("ax", "ay", "az")) < 2e-5
+
+
+def test_list_rows_overflow_fall_back_per_group():
+    """A few particles with a large h see more neighbours than a list row
+    holds: only their groups go through the walking kernels."""
+    cfg = inputs.lattice(16, jitter=0.2, velocities=True)
+    rng = np.random.default_rng(7)
+    big = rng.choice(cfg["n"], 12, replace=False)
+    cfg["u"] = cfg["u"].copy()
+    cfg["m"] = cfg["m"].copy()
+    cfg["m"][big] *= 12.0  # heavy particles: h grows by 12^(1/3)
+    cfg["h"] = cfg["h"].copy()
+    cfg["h"][big] *= 12.0 ** (1 / 3)
+    g, ctx, parts, info = gpu_eval(cfg)
+    st = info["stats"]
+    assert 0 < st["groups_rows_overflow"] < st["n_groups"]
+    o = oracle.evaluate(cfg, oracle.make_params(cfg))
+    compare_fp64(g, o)
+    assert st["force_pairs"] == int(o["nneigh_force"].sum())
