@@ -224,14 +224,17 @@ def main():
     tim, st = main_run["timings"], main_run["stats"]
     tag = "mixed" if prec == sph.SPH_PREC_MIXED else "fp64"
     fpl, dpl = st["force_pairs_per_launch"], st["density_pair_sums_per_launch"]
-    force = roofline(f"k_force<{tag}>", FORCE_FLOPS_PER_PAIR * fpl, tim["force"],
+    lists = tim.get("lists", 0.0) > 0.0  # neighbour-list path (groups of 4 or 8)
+    fname = "k_force_lists" if lists else "k_force"
+    dname = "k_density_lists" if lists else "k_density"
+    force = roofline(f"{fname}<{tag}>", FORCE_FLOPS_PER_PAIR * fpl, tim["force"],
                      {"force_pairs": fpl}, FORCE_FLOPS_PER_PAIR,
-                     traffic_record("k_force", cfg, tag))
-    dens = roofline(f"k_density<{tag}>", DENSITY_FLOPS_PER_PAIR_SUM * dpl,
+                     traffic_record(fname, cfg, tag))
+    dens = roofline(f"{dname}<{tag}>", DENSITY_FLOPS_PER_PAIR_SUM * dpl,
                     tim["density"], {"density_pair_sums": dpl},
-                    DENSITY_FLOPS_PER_PAIR_SUM, traffic_record("k_density", cfg, tag))
+                    DENSITY_FLOPS_PER_PAIR_SUM, traffic_record(dname, cfg, tag))
     kernels = [(tim["density"], dens), (tim["force"], force)]
-    if tim.get("lists", 0.0) > 0.0:
+    if lists:
         lpl = st["list_candidates_per_launch"]
         kernels.append((tim["lists"], roofline(
             f"k_lists<{tag}>", LIST_FLOPS_PER_CANDIDATE * lpl, tim["lists"],
