@@ -63,6 +63,7 @@ class Params(ctypes.Structure):
         ("n_group", ctypes.c_int),
         ("h_tol", ctypes.c_double),
         ("max_h_iter", ctypes.c_int),
+        ("kernel", ctypes.c_int),
     ]
 
 
@@ -84,6 +85,7 @@ def make_params(cfg: dict) -> Params:
     p.n_group = int(cfg["n_group"])
     p.h_tol = float(cfg.get("h_tol_oracle", 1e-10))
     p.max_h_iter = int(cfg.get("max_h_iter", 30))
+    p.kernel = int(cfg.get("kernel", 0))
     return p
 
 
@@ -103,6 +105,9 @@ def _load():
             build(force=False)
         lib = ctypes.CDLL(_SO)
         lib.orc_kernel_m4.argtypes = [ctypes.c_int64, _D, _D, _D, _D, _D]
+        lib.orc_kernel.argtypes = [ctypes.c_int, ctypes.c_int64, _D, _D, _D, _D, _D]
+        lib.orc_kernel_support.argtypes = [ctypes.c_int]
+        lib.orc_kernel_support.restype = ctypes.c_double
         lib.orc_keys.argtypes = [ctypes.c_int64, _D, _D, _D, _P, _U64]
         lib.orc_sort.argtypes = [ctypes.c_int64, _U64, _I64]
         lib.orc_tree.argtypes = [ctypes.c_int64, _U64, ctypes.c_int, ctypes.c_int64,
@@ -158,6 +163,24 @@ def kernel_m4(r, h):
     w, F, dh = np.empty_like(r), np.empty_like(r), np.empty_like(r)
     _load().orc_kernel_m4(r.size, _dptr(r), _dptr(h), _dptr(w), _dptr(F), _dptr(dh))
     return w, F, dh
+
+
+M4, M6, WENDLAND_C6 = 0, 1, 2
+
+
+def kernel(kind: int, r, h):
+    """W(r,h), F(r,h)=dW/dr and dW/dh of kernel ``kind`` (M4, M6 or
+    WENDLAND_C6), elementwise."""
+    r = _f64(r).ravel()
+    h = _f64(np.broadcast_to(h, r.shape)).copy()
+    w, F, dh = np.empty_like(r), np.empty_like(r), np.empty_like(r)
+    _load().orc_kernel(int(kind), r.size, _dptr(r), _dptr(h), _dptr(w), _dptr(F), _dptr(dh))
+    return w, F, dh
+
+
+def kernel_support(kind: int) -> float:
+    """Support radius of kernel ``kind`` in units of h."""
+    return float(_load().orc_kernel_support(int(kind)))
 
 
 def keys(x, y, z, params: Params) -> np.ndarray:

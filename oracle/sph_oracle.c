@@ -17,8 +17,10 @@
  *   density sum .................... Sect. 2.2, density equation
  *   h <-> rho relation ............. Sect. 2.2, smoothing-length equation
  *   Omega (grad-h term) ............ Sect. 2.2, Omega definition
- *   M4 cubic spline ................ Sect. 2.3 (kernel list); polynomial is the
- *                                    standard Monaghan M4, support 2h, 1/pi
+ *   smoothing kernels .............. Sect. 2.3 (kernel list: M4 cubic, M6
+ *                                    quintic, Wendland C6); the polynomials,
+ *                                    supports and 3D normalisations are the
+ *                                    standard ones (not printed in the paper)
  *   leapfrog predict / correct ..... Sect. 2.4, eq:predict_pos, eq:predict_vel,
  *                                    eq:correct_vel
  *   Courant step ................... Sect. 2.4, eq:timestep
@@ -67,56 +69,103 @@ typedef struct {
   int n_group;
   double h_tol;   /* NR stop: |dh| <= h_tol*h.  h_tol < 0: three fixed NR passes */
   int max_h_iter; /* NR iterations before the bracketing fallback */
+  int kernel;     /* 0: M4 cubic spline, 1: M6 quintic spline, 2: Wendland C6 */
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
-/* M4 cubic spline in 3D, support 2h, normalisation 1/pi (Sect. 2.3).        */
-/*   f(q)  = 1 - 3/2 q^2 + 3/4 q^3      0 <= q < 1                           */
-/*         = 1/4 (2 - q)^3              1 <= q < 2                           */
-/*         = 0                          q >= 2                               */
-/*   W(r,h) = f(q) / (pi h^3), q = r/h                                       */
-/*   F(r,h) = dW/dr = f'(q) / (pi h^4)          (the F_ij of Sect. 2.6)       */
-/*   dW/dh  = -(3 f(q) + q f'(q)) / (pi h^4)                                  */
+/* Smoothing kernels in 3D (Sect. 2.3 names them; the forms below are the    */
+/* standard ones).  W(r,h) = C f(q) / h^3 with q = r/h and support S h:       */
+/*                                                                          */
+/* M4 cubic spline, S = 2, C = 1/pi:                                         */
+/*   f(q) = 1 - 3/2 q^2 + 3/4 q^3       0 <= q < 1                           */
+/*        = 1/4 (2 - q)^3               1 <= q < 2                           */
+/* M6 quintic spline, S = 3, C = 1/(120 pi):                                 */
+/*   f(q) = (3-q)^5 - 6 (2-q)^5 + 15 (1-q)^5    0 <= q < 1                   */
+/*        = (3-q)^5 - 6 (2-q)^5                 1 <= q < 2                   */
+/*        = (3-q)^5                             2 <= q < 3                   */
+/* Wendland C6 with compact support H = 2h, S = 2, C = 1365/(512 pi):        */
+/*   f(q) = (1 - q/2)^8 (4 q^3 + 25/4 q^2 + 4 q + 1)    0 <= q < 2           */
+/* (the 3D C6 function (1-x)^8 (32 x^3 + 25 x^2 + 8 x + 1) of x = r/H).      */
+/* f = 0 beyond the support.  Derived quantities:                           */
+/*   F(r,h) = dW/dr = C f'(q) / h^4          (the F_ij of Sect. 2.6)          */
+/*   dW/dh  = -C (3 f(q) + q f'(q)) / h^4                                    */
 /* ------------------------------------------------------------------------ */
-static double m4_f(double q) {
+static double ipow(double t, int k) {
+  double r = 1.0;
+  for (int i = 0; i < k; ++i) r *= t;
+  return r;
+}
+
+double orc_kernel_support(int kind) { return kind == 1 ? 3.0 : 2.0; }
+
+static double kern_norm(int kind) {
+  if (kind == 1) return 1.0 / (120.0 * M_PI);
+  if (kind == 2) return 1365.0 / (512.0 * M_PI);
+  return 1.0 / M_PI;
+}
+
+static double kern_f(int kind, double q) {
+  if (kind == 1) {
+    if (q >= 3.0) return 0.0;
+    double f = ipow(3.0 - q, 5);
+    if (q < 2.0) f -= 6.0 * ipow(2.0 - q, 5);
+    if (q < 1.0) f += 15.0 * ipow(1.0 - q, 5);
+    return f;
+  }
+  if (kind == 2) {
+    if (q >= 2.0) return 0.0;
+    return ipow(1.0 - 0.5 * q, 8) * (((4.0 * q + 6.25) * q + 4.0) * q + 1.0);
+  }
   if (q < 1.0) return 1.0 - 1.5 * q * q + 0.75 * q * q * q;
-  if (q < 2.0) {
-    double t = 2.0 - q;
-    return 0.25 * t * t * t;
-  }
+  if (q < 2.0) return 0.25 * ipow(2.0 - q, 3);
   return 0.0;
 }
 
-static double m4_df(double q) {
+static double kern_df(int kind, double q) {
+  if (kind == 1) {
+    if (q >= 3.0) return 0.0;
+    double d = -5.0 * ipow(3.0 - q, 4);
+    if (q < 2.0) d += 30.0 * ipow(2.0 - q, 4);
+    if (q < 1.0) d -= 75.0 * ipow(1.0 - q, 4);
+    return d;
+  }
+  if (kind == 2) {
+    /* d/dq of (1 - q/2)^8 g(q): (1 - q/2)^7 [-4 g(q) + (1 - q/2) g'(q)],
+       which collapses to -(11/4) q (8 q^2 + 7 q + 2) (1 - q/2)^7 */
+    if (q >= 2.0) return 0.0;
+    return -2.75 * q * ((8.0 * q + 7.0) * q + 2.0) * ipow(1.0 - 0.5 * q, 7);
+  }
   if (q < 1.0) return -3.0 * q + 2.25 * q * q;
-  if (q < 2.0) {
-    double t = 2.0 - q;
-    return -0.75 * t * t;
-  }
+  if (q < 2.0) return -0.75 * ipow(2.0 - q, 2);
   return 0.0;
 }
 
-static double kern_w(double r, double h) {
-  return m4_f(r / h) / (M_PI * h * h * h);
+static double kern_w(int kind, double r, double h) {
+  return kern_norm(kind) * kern_f(kind, r / h) / (h * h * h);
 }
 
-static double kern_F(double r, double h) {
-  return m4_df(r / h) / (M_PI * h * h * h * h);
+static double kern_F(int kind, double r, double h) {
+  return kern_norm(kind) * kern_df(kind, r / h) / (h * h * h * h);
 }
 
-static double kern_dwdh(double r, double h) {
+static double kern_dwdh(int kind, double r, double h) {
   double q = r / h;
-  return -(3.0 * m4_f(q) + q * m4_df(q)) / (M_PI * h * h * h * h);
+  return -kern_norm(kind) * (3.0 * kern_f(kind, q) + q * kern_df(kind, q)) / (h * h * h * h);
 }
 
-/* Vectorised access to the kernel for the self-tests. */
-void orc_kernel_m4(int64_t n, const double* r, const double* h, double* w,
-                   double* F, double* dwdh) {
+/* Vectorised access to the kernels for the self-tests. */
+void orc_kernel(int kind, int64_t n, const double* r, const double* h, double* w, double* F,
+                double* dwdh) {
   for (int64_t i = 0; i < n; ++i) {
-    w[i] = kern_w(r[i], h[i]);
-    F[i] = kern_F(r[i], h[i]);
-    dwdh[i] = kern_dwdh(r[i], h[i]);
+    w[i] = kern_w(kind, r[i], h[i]);
+    F[i] = kern_F(kind, r[i], h[i]);
+    dwdh[i] = kern_dwdh(kind, r[i], h[i]);
   }
+}
+
+void orc_kernel_m4(int64_t n, const double* r, const double* h, double* w, double* F,
+                   double* dwdh) {
+  orc_kernel(0, n, r, h, w, F, dwdh);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -307,14 +356,14 @@ static double pair_r2(const double* x, const double* y, const double* z,
   return fma(az, az, fma(ay, ay, ax * ax));
 }
 
-/* density criterion: j within 2 h_i (self included)                         */
-static int in_density(double r2, double hi) {
-  double s = 2.0 * hi;
+/* density criterion: j within the support S h_i (self included)            */
+static int in_density(double r2, double hi, double S) {
+  double s = S * hi;
   return r2 < s * s;
 }
-/* force criterion: j != i within 2 max(h_i, h_j)                            */
-static int in_force(double r2, double hi, double hj) {
-  double s = 2.0 * (hi > hj ? hi : hj);
+/* force criterion: j != i within the support of the larger of h_i, h_j     */
+static int in_force(double r2, double hi, double hj, double S) {
+  double s = S * (hi > hj ? hi : hj);
   return r2 < s * s;
 }
 
@@ -470,15 +519,16 @@ static void stree_query(const orc_stree* t, int64_t k, int64_t i, double hi,
                         orc_list* out, int* err) {
   if (*err) return;
   double c[3] = {x[i], y[i], z[i]};
-  double reach = 2.0 * ((mode == 1 && t->hmax[k] > hi) ? t->hmax[k] : hi);
+  double reach = orc_kernel_support(p->kernel) * ((mode == 1 && t->hmax[k] > hi) ? t->hmax[k] : hi);
   double d2 = point_box_d2(t, k, c, p);
   if (!(d2 <= reach * reach * (1.0 + 1e-9))) return;
   if (t->child_first[k] < 0) {
     for (int64_t s = t->first[k]; s < t->first[k] + t->count[k]; ++s) {
       int64_t j = t->perm[s];
       double r2 = pair_r2(x, y, z, i, j, p, NULL, NULL, NULL);
-      int take = (mode == 0) ? in_density(r2, hi)
-                             : (j != i && in_force(r2, hi, h[j]));
+      const double S = orc_kernel_support(p->kernel);
+      int take = (mode == 0) ? in_density(r2, hi, S)
+                             : (j != i && in_force(r2, hi, h[j], S));
       if (take && list_push(out, j) != ORC_OK) {
         *err = ORC_E_NOMEM;
         return;
@@ -514,6 +564,7 @@ int64_t orc_neighbours_sel(int64_t n, const double* x, const double* y,
                            int64_t* offsets, int64_t* idx, int64_t cap) {
   if (n <= 0) return ORC_E_ARG;
   if (!sel) nsel = n;
+  const double S = orc_kernel_support(p->kernel);
   int64_t* cnt = (int64_t*)calloc((size_t)(nsel > 0 ? nsel : 1), sizeof(int64_t));
   if (!cnt) return ORC_E_NOMEM;
   orc_stree t;
@@ -536,7 +587,7 @@ int64_t orc_neighbours_sel(int64_t n, const double* x, const double* y,
         int64_t c = 0;
         for (int64_t j = 0; j < n; ++j) {
           double r2 = pair_r2(x, y, z, i, j, p, NULL, NULL, NULL);
-          if (mode == 0 ? in_density(r2, h[i]) : (j != i && in_force(r2, h[i], h[j]))) ++c;
+          if (mode == 0 ? in_density(r2, h[i], S) : (j != i && in_force(r2, h[i], h[j], S))) ++c;
         }
         cnt[k] = c;
       } else {
@@ -563,7 +614,7 @@ int64_t orc_neighbours_sel(int64_t n, const double* x, const double* y,
         if (brute) {
           for (int64_t j = 0; j < n; ++j) {
             double r2 = pair_r2(x, y, z, i, j, p, NULL, NULL, NULL);
-            if (mode == 0 ? in_density(r2, h[i]) : (j != i && in_force(r2, h[i], h[j]))) idx[o++] = j;
+            if (mode == 0 ? in_density(r2, h[i], S) : (j != i && in_force(r2, h[i], h[j], S))) idx[o++] = j;
           }
         } else {
           if (neighbours_of(&t, i, h[i], mode, x, y, z, h, p, &l) != ORC_OK) {
@@ -617,8 +668,8 @@ static int dens_sums(const dens_ctx* c, int64_t i, double h, double* S0,
   for (int64_t k = 0; k < c->l->n; ++k) {
     int64_t j = c->l->idx[k];
     double r = sqrt(pair_r2(c->x, c->y, c->z, i, j, c->p, NULL, NULL, NULL));
-    s0 += c->m[j] * kern_w(r, h);
-    s1 += c->m[j] * kern_dwdh(r, h);
+    s0 += c->m[j] * kern_w(c->p->kernel, r, h);
+    s1 += c->m[j] * kern_dwdh(c->p->kernel, r, h);
   }
   *S0 = s0;
   *S1 = s1;
@@ -846,8 +897,8 @@ int orc_force_sel(int64_t n, const double* x, const double* y, const double* z,
         double ex = dx / r, ey = dy / r, ez = dz / r;
         double w = (vx[i] - vx[j]) * ex + (vy[i] - vy[j]) * ey +
                    (vz[i] - vz[j]) * ez;
-        double Fi = kern_F(r, h[i]);
-        double Fj = kern_F(r, h[j]);
+        double Fi = kern_F(p->kernel, r, h[i]);
+        double Fj = kern_F(p->kernel, r, h[j]);
         double qi = 0.0, qj = 0.0, vsi = 0.0;
         if (w < 0.0) {
           vsi = al * cs[i] + be * fabs(w);

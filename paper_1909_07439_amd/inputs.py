@@ -37,7 +37,28 @@ DEFAULTS = dict(
     c_cour=0.3,
     n_leaf=16,  # the paper's timing runs (Sect. 4.6)
     n_group=8,
+    kernel=0,  # M4 cubic spline
 )
+
+# Smoothing kernels of Sect. 2.3 and the h_fact each is run with (the paper
+# gives none): M4 with support 2h at 1.2 (about 58 neighbours), the M6 quintic
+# with support 3h at 1.0 (about 113) and Wendland C6 with support 2h at 1.6
+# (about 137).
+KERNELS = {"m4": 0, "m6": 1, "wc6": 2}
+KERNEL_HFACT = {0: 1.2, 1: 1.0, 2: 1.6}
+
+
+def with_kernel(cfg: dict, kernel) -> dict:
+    """A copy of workload ``cfg`` run with another smoothing kernel: the
+    kernel's h_fact, and start values of h scaled by the h_fact ratio."""
+    kind = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    out = dict(cfg)
+    hf = KERNEL_HFACT[kind]
+    out["h"] = np.ascontiguousarray(cfg["h"] * (hf / cfg["hfact"]))
+    out["hfact"] = hf
+    out["kernel"] = kind
+    out["workload"] = cfg["workload"] + ("" if kind == 0 else {1: "_m6", 2: "_wc6"}[kind])
+    return out
 
 
 def _rng(workload: int, variant: int = 0) -> np.random.Generator:

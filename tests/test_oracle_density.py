@@ -97,3 +97,47 @@ def test_sod_interiors_keep_lattice_ratio():
     np.testing.assert_allclose(rl, rl[0], rtol=1e-12)
     np.testing.assert_allclose(rr, rl[0], rtol=1e-12)
     np.testing.assert_allclose(o["h"][right], 2 * o["h"][left][0], rtol=1e-12)
+
+
+# ---- the other kernels of Sect. 2.3 on a perfect lattice ----
+B5 = BSpline.basis_element([-3.0, -2.0, -1.0, 0.0, 1.0, 2.0, 3.0], extrapolate=False)
+
+
+def w_m6(r, h):
+    return np.nan_to_num(B5(np.asarray(r) / h), nan=0.0) / (np.pi * h ** 3)  # 120 B5 / (120 pi)
+
+
+def w_wc6(r, h):
+    """Wendland C6 (3D, k = 3) built by the dimension walk I^3 (1 - x)^5 on
+    x = r / (2h), normalised here by a radial quadrature."""
+    P = np.polynomial.Polynomial
+    g, t = P([1.0, -1.0]) ** 5, P([0.0, 1.0])
+    for _ in range(3):
+        a = (t * g).integ()
+        g = a(1.0) - a
+    xs = np.linspace(0.0, 1.0, 200001)
+    norm = 1.0 / np.trapezoid(4.0 * np.pi * (2.0 * xs) ** 2 * g(xs), 2.0 * xs)
+    x = np.minimum(np.asarray(r) / (2.0 * h), 1.0)
+    return norm * g(x) / h ** 3
+
+
+@pytest.mark.parametrize("kind,wfun,nn_expect", [(oracle.M6, w_m6, 112),
+                                                 (oracle.WENDLAND_C6, w_wc6, 136)])
+def test_perfect_lattice_root_other_kernels(kind, wfun, nn_expect):
+    c = inputs.with_kernel(inputs.lattice(16, jitter=0.0), kind)
+    dx, m, hf = c["dx"], c["m"][0], c["hfact"]
+    S = oracle.kernel_support(kind)
+    g = np.arange(-5, 6)
+    I, J, K = np.meshgrid(g, g, g, indexing="ij")
+    r = dx * np.sqrt(I ** 2 + J ** 2 + K ** 2).ravel()
+    f = lambda h: m * wfun(r, h).sum() - m * (hf / h) ** 3
+    hs = brentq(f, 0.7 * hf * dx, 1.4 * hf * dx, xtol=1e-16, rtol=1e-15)
+    rho = m * wfun(r, hs).sum()
+    o = oracle.density(c["x"], c["y"], c["z"], c["m"], c["h"], oracle.make_params(c))
+    # the C6 reference carries the quadrature error of its normalisation
+    tol = 1e-12 if kind == oracle.M6 else 1e-9
+    np.testing.assert_allclose(o["h"], hs, rtol=tol)
+    np.testing.assert_allclose(o["rho"], rho, rtol=tol)
+    assert np.all(o["nneigh"] == int(np.sum(r < S * hs)))
+    assert abs(int(np.sum(r < S * hs)) - nn_expect) <= 12
+    assert abs(o["rho"].mean() - 1.0) < 3e-3  # each kernel's lattice-sum bias

@@ -1,4 +1,5 @@
-"""Pins of the oracle's hydrodynamic force (Sect. 2.4-2.6).
+"""Pins of the oracle's hydrodynamic force (Sect. 2.4-2.6), for the M4, M6
+and Wendland C6 kernels of Sect. 2.3 where marked.
 
 * The pressure part of a_i is the gradient of the thermal energy at fixed
   entropy (the variable-h SPH Lagrangian): a finite difference of
@@ -49,8 +50,12 @@ def wrap01(v):
     return np.mod(v, 1.0)
 
 
-def test_pressure_force_is_thermal_energy_gradient():
-    c = no_dissipation(state_with_u())
+KINDS = [oracle.M4, oracle.M6, oracle.WENDLAND_C6]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_pressure_force_is_thermal_energy_gradient(kind):
+    c = no_dissipation(inputs.with_kernel(state_with_u(), kind))
     o, p = solved(c)
     g1 = c["gamma_minus_1"]
     K = g1 * c["u"] / o["rho"] ** g1  # entropy function, frozen
@@ -73,8 +78,9 @@ def test_pressure_force_is_thermal_energy_gradient():
             assert abs(got - fd) < 2e-6 * scale, (i, key, got, fd)
 
 
-def test_adiabatic_dudt_is_pdv_work():
-    c = no_dissipation(state_with_u(vel=0.3, seed=9))
+@pytest.mark.parametrize("kind", KINDS)
+def test_adiabatic_dudt_is_pdv_work(kind):
+    c = no_dissipation(inputs.with_kernel(state_with_u(vel=0.3, seed=9), kind))
     o, p = solved(c)
     eps = 1e-6
     dp = oracle.density(wrap01(c["x"] + eps * c["vx"]), wrap01(c["y"] + eps * c["vy"]),
@@ -87,8 +93,9 @@ def test_adiabatic_dudt_is_pdv_work():
     np.testing.assert_allclose(o["dudt"], expect, atol=1e-6 * scale)
 
 
-def test_conservation_with_viscosity_and_conductivity():
-    c = inputs.lattice(12, jitter=0.3, velocities=True)
+@pytest.mark.parametrize("kind", KINDS)
+def test_conservation_with_viscosity_and_conductivity(kind):
+    c = inputs.with_kernel(inputs.lattice(12, jitter=0.3, velocities=True), kind)
     o, _ = solved(c)
     m = c["m"]
     red = oracle.reduce(o)
