@@ -30,13 +30,15 @@ if ROOT not in sys.path:
 METRIC = "particle-updates/s (density+force, ~58 nbrs): mixed FP32/FP64 vs FP64"
 
 # Algorithmic floating-point operations per unit of work, counted from the
-# pair functions (an FMA counts 2, sqrt / rsqrt / rcp count 1):
-#   force pair (r < 2 max(h_i,h_j)): geometry 9, r and rhat 5, v.rhat 8, two
-#   kernel gradients 16, viscosity terms 14, acceleration 10, energy terms 24
-FORCE_FLOPS_PER_PAIR = 85
-#   density pair term per smoothing-length pass: q 1, M4 f and f' 14,
-#   two accumulations 7
-DENSITY_FLOPS_PER_PAIR_SUM = 22
+# pair functions (an FMA counts 2, sqrt / rsqrt / rcp count 1), per smoothing
+# kernel (M4, M6, Wendland C6):
+#   force pair (r < S max(h_i,h_j)): geometry 9, r and rhat 5, v.rhat 8, two
+#   kernel gradients (M4 16, M6 34, C6 28), viscosity terms 14,
+#   acceleration 10, energy terms 24
+FORCE_FLOPS_PER_PAIR = {0: 85, 1: 103, 2: 97}
+#   density pair term per smoothing-length pass: q 1, f and f' (M4 14, M6 25,
+#   C6 22), two accumulations 7
+DENSITY_FLOPS_PER_PAIR_SUM = {0: 22, 1: 33, 2: 30}
 #   candidate test of the neighbour-list kernel: separation 3, r^2 5, list
 #   radius 2 max(hl_i, h_margin h_j) 3, its square with the FP32 guard 2,
 #   compare 1
@@ -191,6 +193,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-group", type=int, default=None, help="particles per walk group")
     ap.add_argument("--n-leaf", type=int, default=None, help="particles per tree leaf")
+    ap.add_argument("--kernel", default="m4", choices=["m4", "m6", "wc6"],
+                    help="smoothing kernel (M4 cubic, M6 quintic, Wendland C6)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run a plain streaming kernel over MIB MiB "
                          "(scale for PMC byte counters)")
@@ -206,6 +210,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     cfg = workload(args.workload)
+    if args.kernel != "m4":
+        from paper_1909_07439_amd import inputs
+
+        cfg = inputs.with_kernel(cfg, args.kernel)
     if args.n_group:
         cfg["n_group"] = args.n_group
     if args.n_leaf:
@@ -224,15 +232,15 @@ def main():
     tim, st = main_run["timings"], main_run["stats"]
     tag = "mixed" if prec == sph.SPH_PREC_MIXED else "fp64"
     fpl, dpl = st["force_pairs_per_launch"], st["density_pair_sums_per_launch"]
+    kk = int(cfg.get("kernel", 0))
+    ffl, dfl = FORCE_FLOPS_PER_PAIR[kk], DENSITY_FLOPS_PER_PAIR_SUM[kk]
     lists = tim.get("lists", 0.0) > 0.0  # neighbour-list path (groups of 4 or 8)
     fname = "k_force_lists" if lists else "k_force"
     dname = "k_density_lists" if lists else "k_density"
-    force = roofline(f"{fname}<{tag}>", FORCE_FLOPS_PER_PAIR * fpl, tim["force"],
-                     {"force_pairs": fpl}, FORCE_FLOPS_PER_PAIR,
-                     traffic_record(fname, cfg, tag))
-    dens = roofline(f"{dname}<{tag}>", DENSITY_FLOPS_PER_PAIR_SUM * dpl,
-                    tim["density"], {"density_pair_sums": dpl},
-                    DENSITY_FLOPS_PER_PAIR_SUM, traffic_record(dname, cfg, tag))
+    force = roofline(f"{fname}<{tag}>", ffl * fpl, tim["force"],
+                     {"force_pairs": fpl}, ffl, traffic_record(fname, cfg, tag))
+    dens = roofline(f"{dname}<{tag}>", dfl * dpl, tim["density"],
+                    {"density_pair_sums": dpl}, dfl, traffic_record(dname, cfg, tag))
     kernels = [(tim["density"], dens), (tim["force"], force)]
     if lists:
         lpl = st["list_candidates_per_launch"]
@@ -259,7 +267,9 @@ def main():
         "dtype": "f32+f64" if prec == sph.SPH_PREC_MIXED else "f64",
         "data": "synthetic",
         "config": {"workload": cfg["workload"], "n_particles": cfg["n"],
-                   "precision": args.precision, "kernel": "M4", "hfact": cfg["hfact"],
+                   "precision": args.precision,
+                   "kernel": {"m4": "M4", "m6": "M6", "wc6": "Wendland C6"}[args.kernel],
+                   "hfact": cfg["hfact"],
                    "n_leaf": cfg["n_leaf"], "n_group": cfg["n_group"]},
         "roofline": roof,
         "other_kernel_rooflines": others,

@@ -45,7 +45,7 @@ typedef enum {
   SPH_E_HIP = -3,       /* a HIP runtime call failed */
   SPH_E_NOCONV = -4,    /* smoothing-length iteration did not converge */
   SPH_E_OVERFLOW = -5,  /* a fixed-capacity list (tree nodes, walk lists) overflowed */
-  SPH_E_DOMAIN = -6,    /* 2h reaches half a periodic box length (minimum image ambiguous) */
+  SPH_E_DOMAIN = -6,    /* the kernel support S h reaches half a periodic box length */
   SPH_E_NONFINITE = -7  /* a NaN/Inf appeared in an input or a result */
 } sph_status;
 
@@ -63,7 +63,8 @@ typedef struct {
   double beta_av;       /* artificial viscosity beta; 2 */
   double alpha_u;       /* artificial conductivity alpha_u (Sect. 2.6); 1 */
   double c_cour;        /* Courant factor (eq:timestep); 0.3 */
-  int32_t kernel;       /* smoothing kernel: 0 = M4 cubic spline (support 2h) */
+  int32_t kernel;       /* smoothing kernel (Sect. 2.3): 0 = M4 cubic spline (support 2h),
+                           1 = M6 quintic spline (support 3h), 2 = Wendland C6 (support 2h) */
   int32_t n_leaf;       /* max particles per tree leaf (Sect. 3.1); 1..64 */
   int32_t n_group;      /* max particles per walk group (Sect. 3.1); one of 4,8,16,32 */
   int32_t precision;    /* sph_precision: pair arithmetic in FP64 or FP32 */
@@ -72,7 +73,8 @@ typedef struct {
                            default (1e-14 FP64, 2e-7 mixed); < 0: three fixed passes */
   int32_t max_h_iter;   /* iteration limit before SPH_E_NOCONV (default 30 if <= 0) */
   int32_t reserved0;
-  double h_margin;      /* pair lists cover r < 2 h h_margin so h may grow by that
+  double h_margin;      /* neighbour lists cover r < S h h_margin (S the kernel support in
+                           units of h) so h may grow by that
                            factor without a new walk (default 1.1 if <= 1) */
 } sph_params;
 
@@ -116,7 +118,8 @@ sph_status sph_build_tree(sph_ctx* ctx, sph_particles* p);
 
 /* Density (Sect. 2.2, Sect. 3.2.1) on the tree of the last sph_build_tree:
    for every particle the smoothing length is iterated to the root of
-   sum_j m_j W(r_ij, h) = m (hfact/h)^3 (j within 2h, self included), with a
+   sum_j m_j W(r_ij, h) = m (hfact/h)^3 (j within the support S h: S = 2
+   for M4 and Wendland C6, 3 for M6; self included), with a
    wavefront-wide convergence vote per group; then rho, Omega = 1 + h S1/(3
    rho), P = (gamma-1) rho u and cs = sqrt(gamma (gamma-1) u) are written.
    iters_out (may be NULL; if given, the call synchronises): the largest
@@ -124,7 +127,7 @@ sph_status sph_build_tree(sph_ctx* ctx, sph_particles* p);
    Errors: SPH_E_NOCONV, SPH_E_OVERFLOW, SPH_E_DOMAIN, SPH_E_NONFINITE. */
 sph_status sph_density(sph_ctx* ctx, sph_particles* p, int32_t* iters_out);
 
-/* Hydrodynamic force (Sect. 2.4-2.6): for every pair with r < 2 max(h_i,h_j)
+/* Hydrodynamic force (Sect. 2.4-2.6): for every pair with r < S max(h_i,h_j)
    the pressure, artificial-viscosity and conductivity terms; writes ax, ay,
    az, dudt and vsig_dt.  Needs rho, omega, P, cs from sph_density on the
    same tree.  dt_next_out (may be NULL; if given the call synchronises):
@@ -168,8 +171,8 @@ sph_status sph_get_tree(sph_ctx* ctx, int64_t* n_nodes, int32_t* level, uint64_t
 sph_status sph_get_groups(sph_ctx* ctx, int64_t* n_groups, int64_t* first, int64_t* count);
 
 /* Neighbour sets found by the group tree walk, as CSR over the current
-   particle order with ascending indices: mode 0 = density set (r < 2 h_i,
-   self included), mode 1 = force set (j != i, r < 2 max(h_i, h_j)), using
+   particle order with ascending indices: mode 0 = density set (r < S h_i,
+   self included), mode 1 = force set (j != i, r < S max(h_i, h_j)), using
    the h currently in p->h and the FP64 predicate of both precision modes.
    offsets: host array of n+1 entries (always filled); idx: host array of
    cap entries (may be NULL to query the total in offsets[n]).
@@ -188,7 +191,7 @@ sph_status sph_timings(sph_ctx* ctx, double out[12]);
 
 /* Counters of the work done (for throughput accounting).  out[0..9] refer
    to the last sph_build_tree / sph_step: {tree nodes, groups, most density
-   sums any group needed, true density neighbours (r < 2h, self included) at
+   sums any group needed, true density neighbours (r < S h, self included) at
    the converged h, force pairs, density pair terms summed over all passes,
    density candidate tests, force candidate tests, walks done by the density
    pass, device error word}.  out[10..13] are running totals since

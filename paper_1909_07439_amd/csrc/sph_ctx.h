@@ -11,7 +11,7 @@ constexpr int kSortTile = 2048;  // keys per radix-sort block (256 threads x 8)
 constexpr int kTreeTile = 256;   // particles per tree block
 constexpr int kScanTile = 2048;  // elements per scan block
 constexpr int kChunk = 256;     // particles per chunk box of the node-box reduction
-constexpr int kNLCap = 128;     // entries per neighbour-list row
+constexpr int kNLCapMax = 256;  // largest neighbour-list row (entries)
 constexpr int kSpill = 4096;    // walk frontier entries per level beyond LDS, per wavefront
 
 // Per-particle data the force loop reads for a neighbour j (written by the
@@ -82,8 +82,8 @@ struct sph_ctx {
   int64_t pool_cap = 0;
   int32_t* gl_off = nullptr;   // per group: first pool entry
   int32_t* gl_cnt = nullptr;   // per group: entries, -1 if not stored
-  int32_t* nl_idx = nullptr;   // neighbour-list rows, kNLCap per particle
-  int32_t* nl_len = nullptr;   // entries found per particle (may exceed kNLCap)
+  int32_t* nl_idx = nullptr;   // neighbour-list rows, kp.nl_cap entries per particle
+  int32_t* nl_len = nullptr;   // entries found per particle (may exceed kp.nl_cap)
   int32_t* gflag = nullptr;    // per group: 0 lists complete, 1 row overflow, 2 h outgrew rows
   int32_t* flag_list = nullptr;  // indices of the flagged groups (DevState::n_flagged of them)
   int32_t* walk_spill = nullptr; // 2 * kSpill frontier entries per walk wavefront

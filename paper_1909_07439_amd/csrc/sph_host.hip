@@ -154,7 +154,7 @@ sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ct
     return reject("hfact, gamma, gamma_minus_1 and c_cour must be > 0");
   if (P.alpha_av < 0 || P.beta_av < 0 || P.alpha_u < 0)
     return reject("alpha_av, beta_av and alpha_u must be >= 0");
-  if (P.kernel != 0) return reject("unknown kernel");
+  if (P.kernel < 0 || P.kernel > 2) return reject("unknown kernel (0 M4, 1 M6, 2 Wendland C6)");
   if (P.n_leaf < 1 || P.n_leaf > 64) return reject("n_leaf outside [1, 64]");
   if (!(P.n_group == 4 || P.n_group == 8 || P.n_group == 16 || P.n_group == 32))
     return reject("n_group must be 4, 8, 16 or 32");
@@ -195,6 +195,18 @@ sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ct
   k.n_leaf = P.n_leaf;
   k.n_group = P.n_group;
   k.precision = P.precision;
+  // smoothing kernel of Sect. 2.3: support in units of h and 3D normalisation
+  k.kernel = P.kernel;
+  k.support = (P.kernel == 1) ? 3.0 : 2.0;
+  k.knorm = (P.kernel == 1) ? 1.0 / (120.0 * M_PI)
+                            : (P.kernel == 2 ? 1365.0 / (512.0 * M_PI) : 1.0 / M_PI);
+  // list rows: entries within support * h_margin * h of a uniform density
+  // (4/3 pi (support hfact margin)^3 particles) with 40% room; 128 or 256
+  {
+    const double reach = k.support * P.hfact * k.h_margin;
+    const double expect = 4.0 / 3.0 * M_PI * reach * reach * reach;
+    k.nl_cap = (1.4 * expect <= 128.0) ? 128 : sph::kNLCapMax;
+  }
 
   auto bail = [&](hipError_t e, const char* where) {
     sph_status st = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? SPH_E_NOMEM
@@ -254,7 +266,7 @@ sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ct
   ALLOC(c->leaf_pool, c->pool_cap);
   ALLOC(c->gl_off, N);
   ALLOC(c->gl_cnt, N);
-  ALLOC(c->nl_idx, (int64_t)sph::kNLCap * N);
+  ALLOC(c->nl_idx, (int64_t)k.nl_cap * N);
   ALLOC(c->nl_len, N);
   ALLOC(c->gflag, N);
   ALLOC(c->flag_list, N);
@@ -417,7 +429,7 @@ sph_status sph_force(sph_ctx* c, sph_particles* p, double* dt_next_out) {
   sph_status st = check_parts(c, p, true, true);
   if (st != SPH_OK) return st;
   if (p->n != c->n) return fail(c, SPH_E_ARG, "n differs from the last sph_build_tree");
-  HIPCHK(c, sph::launch_node_h(c, p));
+  HIPCHK(c, sph::launch_node_h(c, p, false));
   HIPCHK(c, sph::launch_force_reset(c));
   st = run_force(c, p, false);
   if (st != SPH_OK) return st;
@@ -442,7 +454,7 @@ sph_status sph_step(sph_ctx* c, sph_particles* p, double dt, double* dt_next_out
   HIPCHK(c, sph::launch_leaf_state(c, 1));
   st = run_density(c, p);
   if (st != SPH_OK) return st;
-  HIPCHK(c, sph::launch_node_h(c, p));
+  HIPCHK(c, sph::launch_node_h(c, p, false));
   HIPCHK(c, sph::launch_force_reset(c));
   st = run_force(c, p, true);
   if (st != SPH_OK) return st;
@@ -553,7 +565,7 @@ sph_status sph_neighbours(sph_ctx* c, const sph_particles* p, int32_t mode, int6
   sph_status st = check_parts(c, p, false, false);
   if (st != SPH_OK) return st;
   if (p->n != c->n) return fail(c, SPH_E_ARG, "n differs from the last sph_build_tree");
-  HIPCHK(c, sph::launch_node_h(c, p));
+  HIPCHK(c, sph::launch_node_h(c, p, true));  // the current h, whatever the force used
   HIPCHK(c, sph::launch_neighbours(c, p, mode, c->nb_cnt, nullptr, nullptr));
   std::vector<int32_t> cnt(c->n);
   HIPCHK(c, hipMemcpyAsync(cnt.data(), c->nb_cnt, 4 * (size_t)c->n, hipMemcpyDeviceToHost,

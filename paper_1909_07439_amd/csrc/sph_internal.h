@@ -90,6 +90,10 @@ struct KParams {
   int32_t n_leaf;
   int32_t n_group;
   int32_t precision;
+  int32_t kernel;   // 0 M4 cubic, 1 M6 quintic, 2 Wendland C6
+  double support;   // kernel support in units of h (2, 3, 2)
+  double knorm;     // 3D normalisation C of W = C f(r/h) / h^3
+  int32_t nl_cap;   // entries per neighbour-list row (128 or 256)
 };
 
 // ---- small device helpers ---------------------------------------------------
@@ -123,7 +127,7 @@ hipError_t launch_predict_keys(sph_ctx* c, const sph_particles* p, bool predict,
 hipError_t launch_sort(sph_ctx* c);
 hipError_t launch_permute(sph_ctx* c, const sph_particles* p, bool outputs_too);
 hipError_t launch_tree(sph_ctx* c);
-hipError_t launch_node_h(sph_ctx* c, const sph_particles* p);
+hipError_t launch_node_h(sph_ctx* c, const sph_particles* p, bool always);
 bool lists_mode(const sph_ctx* c);
 hipError_t launch_lists(sph_ctx* c, const sph_particles* p);
 hipError_t launch_density_lists(sph_ctx* c, const sph_particles* p);

@@ -602,11 +602,12 @@ __global__ void k_tree_guard(DevState* ds, int64_t node_cap) {
 // chunk boxes.  No atomics; min/max are exact, so the boxes are exactly the
 // tight boxes of the particles.
 //
-// do_bb == 0 is the h-only refresh after the density; it is skipped (the
-// kernels return at once) while the force will replay the stored leaf lists,
-// which need neither node nor group h_max.
-__device__ __forceinline__ bool h_refresh_needed(const DevState* ds, int do_bb) {
-  return do_bb || ds->leaf_state != 1 || ds->lists_missing != 0;
+// mode 1: boxes and h_max; mode 0: the h-only refresh after the density,
+// skipped (the kernels return at once) while the force will use complete
+// neighbour lists or replay stored leaf lists, which need neither node nor
+// group h_max; mode 2: the h-only refresh, always.
+__device__ __forceinline__ bool h_refresh_needed(const DevState* ds, int mode) {
+  return mode != 0 || ds->leaf_state != 1 || ds->lists_missing != 0;
 }
 
 struct Box7 {
@@ -656,8 +657,9 @@ __global__ __launch_bounds__(256) void k_chunk_boxes(const double* __restrict__ 
                                                       const double* __restrict__ z,
                                                       const double* __restrict__ h, int n,
                                                       double* __restrict__ cb,
-                                                      const DevState* __restrict__ ds, int do_bb) {
-  if (!h_refresh_needed(ds, do_bb)) return;
+                                                      const DevState* __restrict__ ds, int mode) {
+  if (!h_refresh_needed(ds, mode)) return;
+  const int do_bb = mode == 1 ? 1 : 0;
   const int nch = (n + kChunk - 1) / kChunk;
   const int wpb = blockDim.x / kWave;
   for (int c = blockIdx.x * wpb + (int)(threadIdx.x / kWave); c < nch; c += gridDim.x * wpb) {
@@ -732,8 +734,9 @@ __global__ __launch_bounds__(256) void k_range_boxes(
     const int32_t* __restrict__ nparent, const int32_t* __restrict__ nchild,
     const int32_t* __restrict__ nnchild, WalkNode* __restrict__ wn,
     const int32_t* __restrict__ gfirst, const int32_t* __restrict__ gcount,
-    GroupInfo* __restrict__ gi, const DevState* __restrict__ ds, int do_bb, int nb_small) {
-  if (!h_refresh_needed(ds, do_bb)) return;
+    GroupInfo* __restrict__ gi, const DevState* __restrict__ ds, int mode, int nb_small) {
+  if (!h_refresh_needed(ds, mode)) return;
+  const int do_bb = mode == 1 ? 1 : 0;
   const int nn = ds->n_nodes, ng = ds->n_groups;
   if ((int)blockIdx.x < nb_small) {
     for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < nn + ng;
@@ -1109,25 +1112,54 @@ __device__ __forceinline__ void load_leaves(WalkLds& L, const int2* __restrict__
   __syncthreads();
 }
 
-// ---- M4 cubic spline (3D, support 2h, 1/pi): f(q) and f'(q) -------------
+// ---- smoothing kernels of Sect. 2.3: W = C f(q) / h^3, q = r / h ----------
+// M4 cubic spline (support 2, C = 1/pi), M6 quintic spline (support 3,
+// C = 1/(120 pi)), Wendland C6 on the support H = 2h (C = 1365/(512 pi)).
+// f(q) and f'(q); the kind is uniform over a launch.
 template <typename T>
-__device__ __forceinline__ void m4_f_df(T q, T& f, T& df) {
-  const T one = T(1), two = T(2);
-  const T t = two - q;
-  const T tp = t > T(0) ? t : T(0);
-  // inner branch (q < 1): 1 - 1.5 q^2 + 0.75 q^3 and -3q + 2.25 q^2
-  const T fi = one + q * q * (T(0.75) * q - T(1.5));
-  const T dfi = q * (T(2.25) * q - T(3));
-  // outer branch (1 <= q < 2): 0.25 (2-q)^3 and -0.75 (2-q)^2
-  const T fo = T(0.25) * tp * tp * tp;
-  const T dfo = T(-0.75) * tp * tp;
-  const bool in = q < one;
-  f = in ? fi : fo;
-  df = in ? dfi : dfo;
+__device__ __forceinline__ void kern_f_df(int kind, T q, T& f, T& df) {
+  if (kind == 1) {
+    const T a = T(3) - q, b = T(2) - q, c = T(1) - q;
+    const T t3 = a > T(0) ? a : T(0), t2 = b > T(0) ? b : T(0), t1 = c > T(0) ? c : T(0);
+    const T s3 = t3 * t3, s2 = t2 * t2, s1 = t1 * t1;
+    const T q3 = s3 * s3, q2 = s2 * s2, q1 = s1 * s1;  // fourth powers
+    f = q3 * t3 - T(6) * q2 * t2 + T(15) * q1 * t1;
+    df = T(-5) * q3 + T(30) * q2 - T(75) * q1;
+  } else if (kind == 2) {
+    const T u = T(1) - T(0.5) * q;
+    const T s = u > T(0) ? u : T(0);
+    const T s2 = s * s, s4 = s2 * s2, s7 = s4 * s2 * s;
+    f = s7 * s * (((T(4) * q + T(6.25)) * q + T(4)) * q + T(1));
+    df = T(-2.75) * q * ((T(8) * q + T(7)) * q + T(2)) * s7;
+  } else {
+    const T t = T(2) - q;
+    const T tp = t > T(0) ? t : T(0);
+    // inner branch (q < 1): 1 - 1.5 q^2 + 0.75 q^3 and -3q + 2.25 q^2
+    const T fi = T(1) + q * q * (T(0.75) * q - T(1.5));
+    const T dfi = q * (T(2.25) * q - T(3));
+    // outer branch (1 <= q < 2): 0.25 (2-q)^3 and -0.75 (2-q)^2
+    const T fo = T(0.25) * tp * tp * tp;
+    const T dfo = T(-0.75) * tp * tp;
+    const bool in = q < T(1);
+    f = in ? fi : fo;
+    df = in ? dfi : dfo;
+  }
 }
 
 template <typename T>
-__device__ __forceinline__ T m4_df(T q) {
+__device__ __forceinline__ T kern_df(int kind, T q) {
+  if (kind == 1) {
+    const T a = T(3) - q, b = T(2) - q, c = T(1) - q;
+    const T t3 = a > T(0) ? a : T(0), t2 = b > T(0) ? b : T(0), t1 = c > T(0) ? c : T(0);
+    const T s3 = t3 * t3, s2 = t2 * t2, s1 = t1 * t1;
+    return T(-5) * s3 * s3 + T(30) * s2 * s2 - T(75) * s1 * s1;
+  }
+  if (kind == 2) {
+    const T u = T(1) - T(0.5) * q;
+    const T s = u > T(0) ? u : T(0);
+    const T s2 = s * s, s4 = s2 * s2;
+    return T(-2.75) * q * ((T(8) * q + T(7)) * q + T(2)) * (s4 * s2 * s);
+  }
   const T t = T(2) - q;
   const T tp = t > T(0) ? t : T(0);
   const T dfi = q * (T(2.25) * q - T(3));
@@ -1149,7 +1181,6 @@ __device__ __forceinline__ float fast_rcp(float v) { return __builtin_amdgcn_rcp
 // The first walk opens nodes with the force criterion widened by the margin
 // and stores the group's leaf list, so that the force pass can replay it.
 // ============================================================================
-constexpr double kInvPi = 0.318309886183790671537767526745;
 
 // Global Courant minimum: the atomic is skipped when the stored value is
 // already smaller (most wavefronts once the first ones have finished).
@@ -1175,7 +1206,7 @@ __device__ __forceinline__ void density_outputs(const KParams& kp, const Parts& 
   const double P = kp.gm1 * rho * u;
   const double cs = sqrt(kp.gamma * kp.gm1 * u);
   if (!(isfinite(rho) && isfinite(omega) && isfinite(P) && isfinite(cs))) err |= kErrNonFinite;
-  if (2.0 * h >= minhalf) err |= kErrDomain;
+  if (kp.support * h >= minhalf) err |= kErrDomain;
   if (!write) return;
   p.h[i] = h;
   p.rho[i] = rho;
@@ -1185,7 +1216,7 @@ __device__ __forceinline__ void density_outputs(const KParams& kp, const Parts& 
   const double hinv = 1.0 / h;
   const double g = P / (rho * rho * omega);
   const double kk = 1.0 / (rho * omega);
-  const double hinv4pi = hinv * hinv * hinv * hinv * kInvPi;
+  const double hinv4pi = hinv * hinv * hinv * hinv * kp.knorm;
   if constexpr (MIXED) {
     FRec32 r;
     r.x = xi;
@@ -1305,7 +1336,7 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
    {
      const double hs = margin * SG.hmax;
      auto sradius = [&](const WalkNode& nd) {
-       return 2.0 * fmax(hs, margin * (double)nd.hmax) * (1.0 + 4e-9);
+       return kp.support * fmax(hs, margin * (double)nd.hmax) * (1.0 + 4e-9);
      };
      auto sflush = [&](int nleaf) {
        if (nsl + nleaf <= kSLCap) {
@@ -1358,12 +1389,12 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
       if (!stream && ballot64(act && need) != 0ull) {
         // ---- walk and fill the pair lists (r < 2 hlim_i)
         const double hm = wave_max_f64(act ? hlim : 0.0);
-        const double rl = 2.0 * hlim, rl2 = rl * rl;
+        const double rl = kp.support * hlim, rl2 = rl * rl;
         const float rl2f = (float)rl2 * 1.00001f;
         npair = 0;
         auto radius = [&](const WalkNode& nd) {
           const double r = store ? fmax(hm, margin * (double)nd.hmax) : hm;
-          return 2.0 * r * (1.0 + 4e-9);
+          return kp.support * r * (1.0 + 4e-9);
         };
         auto flush = [&](int nleaf) {
           const int total = leaf_offsets(L, nleaf);
@@ -1439,8 +1470,8 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
       uint32_t cnt = 0;
       if (stream) {
         // walk at the current h and accumulate the candidates directly
-        const double Rg = 2.0 * wave_max_f64(act ? h : 0.0) * (1.0 + 4e-9);
-        const double twoh = 2.0 * h, rl2 = twoh * twoh;
+        const double Rg = kp.support * wave_max_f64(act ? h : 0.0) * (1.0 + 4e-9);
+        const double twoh = kp.support * h, rl2 = twoh * twoh;
         const float rl2f = (float)rl2;
         const float hinvf = (float)hinv;
         auto radius = [&](const WalkNode&) { return Rg; };
@@ -1456,7 +1487,7 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
                   const float m = T.a[c];
                   const float q = fast_sqrt(r2) * hinvf;
                   float f, df;
-                  m4_f_df<float>(q, f, df);
+                  kern_f_df<float>(kp.kernel, q, f, df);
                   a0 += (double)(m * f);
                   a1 += (double)(m * (3.0f * f + q * df));
                   ++cnt;
@@ -1470,7 +1501,7 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
                   const double mj = T.a[c];
                   const double q = sqrt(r2) * hinv;
                   double f, df;
-                  m4_f_df<double>(q, f, df);
+                  kern_f_df<double>(kp.kernel, q, f, df);
                   a0 += mj * f;
                   a1 += mj * (3.0 * f + q * df);
                   ++cnt;
@@ -1492,13 +1523,13 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
       } else if (MIXED) {
         // each lane sums its few terms in FP32; lanes are combined in FP64
         const float hinvf = (float)hinv;
-        const float twohf = (float)(2.0 * h);
+        const float twohf = (float)(kp.support * h);
         float s0 = 0.f, s1 = 0.f;
         for (int k = sub; k < npair; k += LPI) {
           const float r = (float)s_r[k * GS + slot], m = (float)s_m[k * GS + slot];
           const float q = r * hinvf;
           float f, df;
-          m4_f_df<float>(q, f, df);
+          kern_f_df<float>(kp.kernel, q, f, df);
           s0 = fmaf(m, f, s0);
           s1 = fmaf(m, fmaf(q, df, 3.0f * f), s1);
           cnt += (r < twohf) ? 1u : 0u;
@@ -1506,12 +1537,12 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
         a0 = (double)s0;
         a1 = (double)s1;
       } else {
-        const double twoh = 2.0 * h;
+        const double twoh = kp.support * h;
         for (int k = sub; k < npair; k += LPI) {
           const double r = (double)s_r[k * GS + slot], m = (double)s_m[k * GS + slot];
           const double q = r * hinv;
           double f, df;
-          m4_f_df<double>(q, f, df);
+          kern_f_df<double>(kp.kernel, q, f, df);
           a0 += m * f;
           a1 += m * (3.0 * f + q * df);
           cnt += (r < twoh) ? 1u : 0u;
@@ -1521,8 +1552,8 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
       a1 = seg_sum<LPI>(a1);
       cnt = seg_sum_u32<LPI>(cnt);
       const double h3 = hinv * hinv * hinv;
-      S0 = a0 * h3 * kInvPi;
-      S1 = -a1 * h3 * hinv * kInvPi;
+      S0 = a0 * h3 * kp.knorm;
+      S1 = -a1 * h3 * hinv * kp.knorm;
       nnb = cnt;
       sums += (act && sub == 0) ? (unsigned long long)cnt : 0ull;
       // ---- decide: a slot is done when the h-rho relation holds at its
@@ -1707,8 +1738,8 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
           const float r = r2 * rinv;
           const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
           const float w = fmaf(vzi - rj.vz, ez, fmaf(vyi - rj.vy, ey, (vxi - rj.vx) * ex));
-          const float Fi = m4_df<float>(r * hinvi) * h4i;
-          const float Fj = m4_df<float>(r * rj.hinv) * rj.hinv4pi;
+          const float Fi = kern_df<float>(kp.kernel, r * hinvi) * h4i;
+          const float Fj = kern_df<float>(kp.kernel, r * rj.hinv) * rj.hinv4pi;
           const float aw = fabsf(w);
           const bool app = w < 0.0f;
           const float vsi = fmaf(be, aw, al * ci);
@@ -1752,8 +1783,8 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
           const double rinv = 1.0 / r;
           const double ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
           const double w = fma(vzi - rj.vz, ez, fma(vyi - rj.vy, ey, (vxi - rj.vx) * ex));
-          const double Fi = m4_df<double>(r * hinvi) * h4i;
-          const double Fj = m4_df<double>(r * rj.hinv) * rj.hinv4pi;
+          const double Fi = kern_df<double>(kp.kernel, r * hinvi) * h4i;
+          const double Fj = kern_df<double>(kp.kernel, r * rj.hinv) * rj.hinv4pi;
           const double aw = fabs(w);
           const bool app = w < 0.0;
           const double vsi = fma(be, aw, al * ci);
@@ -1788,7 +1819,7 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
     };
     const double hg = G.hmax;
     auto radius = [&](const WalkNode& nd) {
-      return 2.0 * fmax(hg, (double)nd.hmax) * (1.0 + 4e-9);
+      return kp.support * fmax(hg, (double)nd.hmax) * (1.0 + 4e-9);
     };
     auto flush = [&](int nleaf) {
       const int total = leaf_offsets(L, nleaf);
@@ -1809,7 +1840,7 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
             const float dx = xr - T.x[c], dy = yr - T.y[c], dz = zr - T.z[c];
             const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
             const float hj = T.a[c];
-            const float sr = 2.0f * fmaxf(hif, hj);
+            const float sr = (float)kp.support * fmaxf(hif, hj);
             pred = r2 < sr * sr * 1.00001f;
           } else {
             const double dx = fold(xi - T.x[c], kp.len[0], kp.half[0], kp.periodic[0]);
@@ -1817,7 +1848,7 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
             const double dz = fold(zi - T.z[c], kp.len[2], kp.half[2], kp.periodic[2]);
             const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
             const double hj = T.a[c];
-            const double sr = 2.0 * (hi > hj ? hi : hj);
+            const double sr = kp.support * (hi > hj ? hi : hj);
             pred = r2 < sr * sr;
           }
         }
@@ -1952,7 +1983,7 @@ __global__ __launch_bounds__(64) void k_lists(KParams kp, Parts p,
     {
       const double hs = margin * SG.hmax;
       auto sradius = [&](const WalkNode& nd) {
-        return 2.0 * fmax(hs, margin * (double)nd.hmax) * (1.0 + 4e-9);
+        return kp.support * fmax(hs, margin * (double)nd.hmax) * (1.0 + 4e-9);
       };
       auto sflush = [&](int nleaf) {
         if (nsl + nleaf <= kSLCap) {
@@ -1983,10 +2014,10 @@ __global__ __launch_bounds__(64) void k_lists(KParams kp, Parts p,
         }
         const float hlf = (float)hl, marginf = (float)margin;
         const double hm = wave_max_f64(act ? hl : 0.0);
-        int32_t* __restrict__ row = nl_idx + (int64_t)i * kNLCap;
+        int32_t* __restrict__ row = nl_idx + (int64_t)i * kp.nl_cap;
         int npair = 0;
         auto radius = [&](const WalkNode& nd) {
-          return 2.0 * fmax(hm, margin * (double)nd.hmax) * (1.0 + 4e-9);
+          return kp.support * fmax(hm, margin * (double)nd.hmax) * (1.0 + 4e-9);
         };
         auto flush = [&](int nleaf) {
           const int total = leaf_offsets(L, nleaf);
@@ -1999,21 +2030,21 @@ __global__ __launch_bounds__(64) void k_lists(KParams kp, Parts p,
               if constexpr (MIXED) {
                 const float dx = xr - T.x[c], dy = yr - T.y[c], dz = zr - T.z[c];
                 const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                const float sr = 2.0f * fmaxf(hlf, marginf * T.a[c]);
+                const float sr = (float)kp.support * fmaxf(hlf, marginf * T.a[c]);
                 pred = r2 < sr * sr * 1.00001f;
               } else {
                 const double dx = fold(xi - T.x[c], kp.len[0], kp.half[0], kp.periodic[0]);
                 const double dy = fold(yi - T.y[c], kp.len[1], kp.half[1], kp.periodic[1]);
                 const double dz = fold(zi - T.z[c], kp.len[2], kp.half[2], kp.periodic[2]);
                 const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                const double sr = 2.0 * fmax(hl, margin * T.a[c]);
+                const double sr = kp.support * fmax(hl, margin * T.a[c]);
                 pred = r2 < sr * sr;
               }
             }
             const uint64_t b = ballot64(pred);
             const uint32_t seg = (uint32_t)((b >> (slot * LPI)) & ((LPI == 64) ? ~0ull : ((1ull << LPI) - 1ull)));
             const int pos = npair + __popc(seg & ((1u << sub) - 1u));
-            if (pred && pos < kNLCap) row[pos] = j;
+            if (pred && pos < kp.nl_cap) row[pos] = j;
             npair += __popc(seg);
           });
           __syncthreads();
@@ -2044,7 +2075,7 @@ __global__ __launch_bounds__(64) void k_lists(KParams kp, Parts p,
           nl_len[i] = npair;
           grp_of[i] = g;
         }
-        return !gok || ballot64(act && npair > kNLCap) != 0ull;
+        return !gok || ballot64(act && npair > kp.nl_cap) != 0ull;
       };
       const bool bad = unit(G);
       if (lane == 0) {
@@ -2090,7 +2121,7 @@ __device__ __forceinline__ GroupRange xcd_groups(int ng) {
 // neighbours) is flagged (gflag = 2) for the walking kernel, and the force
 // pass then walks for every group (leaf_state 2).
 // ============================================================================
-template <bool MIXED, int LPI>
+template <bool MIXED, int LPI, int CAP>
 __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
                                                       const GroupInfo* __restrict__ groups,
                                                       const int32_t* __restrict__ nl_idx,
@@ -2101,10 +2132,10 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
                                                       void* __restrict__ frec_out,
                                                       DevState* __restrict__ ds) {
   using R = typename std::conditional<MIXED, float, double>::type;
-  constexpr int E = kNLCap / LPI;  // row entries per lane
+  constexpr int E = CAP / LPI;  // row entries per lane (CAP = kp.nl_cap)
   constexpr int GS = kWave / LPI;
-  __shared__ R s_r[kNLCap * GS];  // separation and mass of row entry k of slot s at [k * GS + s]
-  __shared__ R s_m[kNLCap * GS];
+  __shared__ R s_r[CAP * GS];  // separation and mass of row entry k of slot s at [k * GS + s]
+  __shared__ R s_m[CAP * GS];
   const int lane = threadIdx.x;
   const int slot = lane / LPI, sub = lane % LPI;
   constexpr int CS = kWave / LPI;  // particles per chunk
@@ -2136,7 +2167,7 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
     }
     const double hl = margin * h;
     const int len = act ? nl_len[i] : 0;
-    const int32_t* __restrict__ row = nl_idx + (int64_t)i * kNLCap;
+    const int32_t* __restrict__ row = nl_idx + (int64_t)i * CAP;
     int lmax = len;
     for (int d = 32; d > 0; d >>= 1) lmax = max(lmax, __shfl_xor(lmax, d, kWave));
     // ---- gather: separation and mass of every row entry into LDS, four
@@ -2188,13 +2219,13 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
       uint32_t cnt = 0;
       if constexpr (MIXED) {
         // each lane sums its few terms in FP32; lanes are combined in FP64
-        const float hinvf = (float)hinv, twohf = (float)(2.0 * h);
+        const float hinvf = (float)hinv, twohf = (float)(kp.support * h);
         float s0 = 0.f, s1 = 0.f;
         for (int k = sub; k < len; k += LPI) {
           const float r = s_r[k * GS + slot], m = s_m[k * GS + slot];
           const float q = r * hinvf;
           float f, df;
-          m4_f_df<float>(q, f, df);
+          kern_f_df<float>(kp.kernel, q, f, df);
           s0 = fmaf(m, f, s0);
           s1 = fmaf(m, fmaf(q, df, 3.0f * f), s1);
           cnt += (r < twohf) ? 1u : 0u;
@@ -2202,12 +2233,12 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
         a0 = (double)s0;
         a1 = (double)s1;
       } else {
-        const double twoh = 2.0 * h;
+        const double twoh = kp.support * h;
         for (int k = sub; k < len; k += LPI) {
           const double r = s_r[k * GS + slot], m = s_m[k * GS + slot];
           const double q = r * hinv;
           double f, df;
-          m4_f_df<double>(q, f, df);
+          kern_f_df<double>(kp.kernel, q, f, df);
           a0 += m * f;
           a1 += m * (3.0 * f + q * df);
           cnt += (r < twoh) ? 1u : 0u;
@@ -2217,8 +2248,8 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
       a1 = seg_sum<LPI>(a1);
       cnt = seg_sum_u32<LPI>(cnt);
       const double h3 = hinv * hinv * hinv;
-      S0 = a0 * h3 * kInvPi;
-      S1 = -a1 * h3 * hinv * kInvPi;
+      S0 = a0 * h3 * kp.knorm;
+      S1 = -a1 * h3 * hinv * kp.knorm;
       nnb = cnt;
       sums += (act && sub == 0) ? (unsigned long long)cnt : 0ull;
       bool moved = false;
@@ -2354,7 +2385,7 @@ void k_force_lists(KParams kp, Parts p,
     const double xi = p.x[i], yi = p.y[i], zi = p.z[i], hi = p.h[i];
     const Rec ri = rec[i];
     const int len = act ? nl_len[i] : 0;
-    const int32_t* __restrict__ row = nl_idx + (int64_t)i * kNLCap;
+    const int32_t* __restrict__ row = nl_idx + (int64_t)i * kp.nl_cap;
     int lmax = len;
     for (int d = 32; d > 0; d >>= 1) lmax = max(lmax, __shfl_xor(lmax, d, kWave));
     cands += (act && sub == 0) ? (unsigned long long)len : 0ull;
@@ -2369,15 +2400,15 @@ void k_force_lists(KParams kp, Parts p,
         const float dy = (float)fold(yi - rj.y, kp.len[1], kp.half[1], kp.periodic[1]);
         const float dz = (float)fold(zi - rj.z, kp.len[2], kp.half[2], kp.periodic[2]);
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        const float sr = 2.0f * fmaxf(hif, rj.h);
+        const float sr = (float)kp.support * fmaxf(hif, rj.h);
         if (!(r2 < sr * sr * 1.00001f)) return;
         ++pairs;
         const float rinv = __builtin_amdgcn_rsqf(r2);
         const float r = r2 * rinv;
         const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
         const float w = fmaf(vzi - rj.vz, ez, fmaf(vyi - rj.vy, ey, (vxi - rj.vx) * ex));
-        const float Fi = m4_df<float>(r * hinvi) * h4i;
-        const float Fj = m4_df<float>(r * rj.hinv) * rj.hinv4pi;
+        const float Fi = kern_df<float>(kp.kernel, r * hinvi) * h4i;
+        const float Fj = kern_df<float>(kp.kernel, r * rj.hinv) * rj.hinv4pi;
         const float aw = fabsf(w);
         const bool app = w < 0.0f;
         const float vsi = fmaf(be, aw, al * ci);
@@ -2423,15 +2454,15 @@ void k_force_lists(KParams kp, Parts p,
         const double dy = fold(yi - rj.y, kp.len[1], kp.half[1], kp.periodic[1]);
         const double dz = fold(zi - rj.z, kp.len[2], kp.half[2], kp.periodic[2]);
         const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-        const double sr = 2.0 * (hi > rj.h ? hi : rj.h);
+        const double sr = kp.support * (hi > rj.h ? hi : rj.h);
         if (!(r2 < sr * sr)) return;
         ++pairs;
         const double r = sqrt(r2);
         const double rinv = 1.0 / r;
         const double ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
         const double w = fma(vzi - rj.vz, ez, fma(vyi - rj.vy, ey, (vxi - rj.vx) * ex));
-        const double Fi = m4_df<double>(r * hinvi) * h4i;
-        const double Fj = m4_df<double>(r * rj.hinv) * rj.hinv4pi;
+        const double Fi = kern_df<double>(kp.kernel, r * hinvi) * h4i;
+        const double Fj = kern_df<double>(kp.kernel, r * rj.hinv) * rj.hinv4pi;
         const double aw = fabs(w);
         const bool app = w < 0.0;
         const double vsi = fma(be, aw, al * ci);
@@ -2527,7 +2558,7 @@ __global__ __launch_bounds__(64) void k_neighbours(KParams kp, Parts p, int mode
     int cnt = 0;
     const double hg = G.hmax;
     auto radius = [&](const WalkNode& nd) {
-      return 2.0 * (mode == 1 ? fmax(hg, (double)nd.hmax) : hg) * (1.0 + 4e-9);
+      return kp.support * (mode == 1 ? fmax(hg, (double)nd.hmax) : hg) * (1.0 + 4e-9);
     };
     auto flush = [&](int nleaf) {
       const int total = leaf_offsets(L, nleaf);
@@ -2541,11 +2572,11 @@ __global__ __launch_bounds__(64) void k_neighbours(KParams kp, Parts p, int mode
           const double dz = fold(zi - T.z[c], kp.len[2], kp.half[2], kp.periodic[2]);
           const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
           if (mode == 0) {
-            const double s = 2.0 * hi;
+            const double s = kp.support * hi;
             pred = r2 < s * s;
           } else {
             const double hj = T.a[c];
-            const double s = 2.0 * (hi > hj ? hi : hj);
+            const double s = kp.support * (hi > hj ? hi : hj);
             pred = (j != i) && r2 < s * s;
           }
         }
@@ -2772,10 +2803,10 @@ hipError_t launch_tree(sph_ctx* c) {
 
 // Node boxes (positions) and largest h; group boxes.  The positions are the
 // current (sorted) ones; h may be the start value or the converged one.
-static hipError_t node_props(sph_ctx* c, const sph_particles* s, bool do_bb) {
+static hipError_t node_props(sph_ctx* c, const sph_particles* s, int mode) {
   const int n = c->n;
   const int nch = (n + kChunk - 1) / kChunk;
-  const int flag = do_bb ? 1 : 0;
+  const int flag = mode;
   hipLaunchKernelGGL(k_chunk_boxes, dim3((nch + 3) / 4), dim3(256), 0, c->stream, s->x, s->y,
                      s->z, s->h, n, c->chunk_box, c->ds, flag);
   // leaves and groups: about one per thread; inner nodes (about a seventh of
@@ -2790,8 +2821,10 @@ static hipError_t node_props(sph_ctx* c, const sph_particles* s, bool do_bb) {
   return hipGetLastError();
 }
 
-hipError_t launch_node_h(sph_ctx* c, const sph_particles* s) { return node_props(c, s, false); }
-hipError_t launch_node_boxes(sph_ctx* c, const sph_particles* s) { return node_props(c, s, true); }
+hipError_t launch_node_h(sph_ctx* c, const sph_particles* s, bool always) {
+  return node_props(c, s, always ? 2 : 0);
+}
+hipError_t launch_node_boxes(sph_ctx* c, const sph_particles* s) { return node_props(c, s, 1); }
 
 // Density and force of groups of 4 or 8 particles go through the neighbour
 // lists; larger groups (and flagged groups) through the walking kernels.
@@ -2867,20 +2900,29 @@ hipError_t launch_lists(sph_ctx* c, const sph_particles* s) {
   return hipGetLastError();
 }
 
+template <bool MIXED, int CAP>
+static void density_lists_dispatch(sph_ctx* c, const Parts& p) {
+  const dim3 grid(c->walk_blocks), block(64);
+  SPH_LPI_SWITCH_LISTS(c->kp.n_group,
+                       hipLaunchKernelGGL((k_density_lists<MIXED, LPI, CAP>), grid, block, 0,
+                                          c->stream, c->kp, p, c->ginfo, c->nl_idx, c->nl_len,
+                                          c->gflag, c->flag_list, c->grp_of, c->frec, c->ds));
+}
+
 hipError_t launch_density_lists(sph_ctx* c, const sph_particles* s) {
   c->kp.n = c->n;
   const Parts p = parts_of(s);
-  const dim3 grid(c->walk_blocks), block(64);
+  const bool wide = c->kp.nl_cap > 128;
   if (c->kp.precision == SPH_PREC_MIXED) {
-    SPH_LPI_SWITCH_LISTS(c->kp.n_group,
-                         hipLaunchKernelGGL((k_density_lists<true, LPI>), grid, block, 0,
-                                            c->stream, c->kp, p, c->ginfo, c->nl_idx, c->nl_len,
-                                            c->gflag, c->flag_list, c->grp_of, c->frec, c->ds));
+    if (wide)
+      density_lists_dispatch<true, 256>(c, p);
+    else
+      density_lists_dispatch<true, 128>(c, p);
   } else {
-    SPH_LPI_SWITCH_LISTS(c->kp.n_group,
-                         hipLaunchKernelGGL((k_density_lists<false, LPI>), grid, block, 0,
-                                            c->stream, c->kp, p, c->ginfo, c->nl_idx, c->nl_len,
-                                            c->gflag, c->flag_list, c->grp_of, c->frec, c->ds));
+    if (wide)
+      density_lists_dispatch<false, 256>(c, p);
+    else
+      density_lists_dispatch<false, 128>(c, p);
   }
   return hipGetLastError();
 }

@@ -130,7 +130,7 @@ def make_params(cfg: dict, precision: int = SPH_PREC_FP64, **over) -> sph_params
     p.beta_av = float(c["beta_av"])
     p.alpha_u = float(c["alpha_u"])
     p.c_cour = float(c["c_cour"])
-    p.kernel = 0
+    p.kernel = int(c.get("kernel", 0))
     p.n_leaf = int(c["n_leaf"])
     p.n_group = int(c["n_group"])
     p.precision = int(c.get("precision", precision))

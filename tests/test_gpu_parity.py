@@ -351,3 +351,83 @@ def test_list_rows_overflow_fall_back_per_group():
     o = oracle.evaluate(cfg, oracle.make_params(cfg))
     compare_fp64(g, o)
     assert st["force_pairs"] == int(o["nneigh_force"].sum())
+
+
+# ---- the other kernels of Sect. 2.3 (M6 quintic, Wendland C6) ----
+KERNEL_CASES = [(k, w) for k in (oracle.M6, oracle.WENDLAND_C6) for w in ("lattice", "sod")]
+
+
+def kernel_workload(kind, name):
+    if name == "lattice":
+        base = inputs.lattice(14, jitter=0.3, velocities=True)
+    else:
+        base = inputs.sod(dx_left=1.0 / 64, width=0.25)
+    return inputs.with_kernel(base, kind)
+
+
+@pytest.mark.parametrize("kind,name", KERNEL_CASES)
+def test_other_kernels_fp64_parity(kind, name):
+    cfg = kernel_workload(kind, name)
+    g, ctx, parts, info = gpu_eval(cfg)
+    o = oracle.evaluate(cfg, oracle.make_params(cfg))
+    compare_fp64(g, o)
+    assert info["stats"]["density_pairs"] == int(o["nneigh"].sum())
+    assert info["stats"]["force_pairs"] == int(o["nneigh_force"].sum())
+    assert abs(info["dt"] - o["dt_next"]) <= FP64_TOL * o["dt_next"]
+
+
+@pytest.mark.parametrize("kind,name", KERNEL_CASES)
+def test_other_kernels_mixed_bounds(kind, name):
+    cfg = kernel_workload(kind, name)
+    g, ctx, parts, info = gpu_eval(cfg, sph.SPH_PREC_MIXED)
+    o = oracle.evaluate(cfg, oracle.make_params(cfg))
+    eh = rel_err(g["h"], o["h"]).max()
+    er = rel_err(g["rho"], o["rho"]).max()
+    ea = max((np.abs(g[k] - o[k]) / o["anorm"]).max() for k in ("ax", "ay", "az"))
+    eu = (np.abs(g["dudt"] - o["dudt"]) / np.maximum(o["unorm"], 1e-300)).max()
+    say(f"  kernel {kind} {name} mixed: h {eh:.2e} rho {er:.2e} a {ea:.2e} du {eu:.2e}")
+    assert eh < 2e-6 and er < 1e-5 and ea < 2e-5 and eu < 2e-5
+
+
+@pytest.mark.parametrize("kind", [oracle.M6, oracle.WENDLAND_C6])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_other_kernels_neighbour_sets(kind, mode):
+    cfg = kernel_workload(kind, "lattice")
+    g, ctx, parts, info = gpu_eval(cfg)
+    s = parts.numpy()
+    off, idx = sph.sph_neighbours(ctx, parts, mode)
+    c = dict(cfg)
+    ooff, oidx = oracle.neighbours(s["x"], s["y"], s["z"], s["h"], oracle.make_params(c),
+                                   mode=mode)
+    np.testing.assert_array_equal(off, ooff)
+    np.testing.assert_array_equal(idx, oidx)
+
+
+@pytest.mark.parametrize("kind", [oracle.M6, oracle.WENDLAND_C6])
+def test_other_kernels_walking_path(kind):
+    """Groups of 16 particles: the walking kernels for every group."""
+    cfg = kernel_workload(kind, "lattice")
+    cfg["n_group"] = 16
+    g, ctx, parts, info = gpu_eval(cfg)
+    o = oracle.evaluate(cfg, oracle.make_params(cfg))
+    compare_fp64(g, o)
+
+
+def test_m6_steps_fp64_match_oracle():
+    cfg = inputs.with_kernel(inputs.sod(dx_left=1.0 / 64, width=0.25), oracle.M6)
+    op = oracle.make_params(cfg)
+    s = oracle.evaluate(cfg, op)
+    state = dict(cfg)
+    for k in ("ax", "ay", "az", "dudt", "h"):
+        state[k] = s[k]
+    parts = sph.Particles(state)
+    ctx = sph.Context(sph.make_params(cfg, sph.SPH_PREC_FP64), cfg["n"])
+    dt = s["dt_next"]
+    for _ in range(4):
+        s = oracle.step(s, dt, op)
+        dtg = sph.sph_step(ctx, parts, dt, want_dt=True)
+        assert abs(dtg - s["dt_next"]) <= 1e-11 * s["dt_next"]
+        dt = s["dt_next"]
+    g = to_orig(parts.numpy())
+    for k in ("x", "vx", "u", "rho", "h"):
+        assert np.abs(g[k] - s[k]).max() <= 1e-10 * max(np.abs(s[k]).max(), 1e-300), k

@@ -75,7 +75,8 @@ def _params(**kw):
 
 @pytest.mark.parametrize("bad", [dict(n_group=6), dict(n_leaf=0), dict(n_leaf=65),
                                  dict(box_len=(1, 0, 1)), dict(hfact=0.0),
-                                 dict(gamma_minus_1=0.0), dict(precision=3)])
+                                 dict(gamma_minus_1=0.0), dict(precision=3), dict(kernel=3),
+                                 dict(kernel=-1)])
 def test_create_rejects_bad_parameters(lib, bad):
     p = _params(**bad)
     h = ctypes.c_void_p()
