@@ -184,7 +184,8 @@ sph_status sph_neighbours(sph_ctx* ctx, const sph_particles* p, int32_t mode, in
    milliseconds, from HIP events recorded on the library stream around each
    phase (at most 1024 launches per phase are kept): out[0..11] = {keys+sort,
    permute, tree, density, force, integrate, total step, neighbour lists,
-   density of flagged groups, force of flagged groups, reserved, reserved}.
+   density of flagged groups, force of flagged groups, adjoint kernels of
+   sph_eval_adjoint / sph_step_adjoint, reserved}.
    The density, force, integrate, neighbour-list and flagged-group phases each
    bracket exactly one kernel.  Clears the kept events.  Synchronises. */
 sph_status sph_timings(sph_ctx* ctx, double out[12]);
@@ -203,6 +204,55 @@ sph_status sph_timings(sph_ctx* ctx, double out[12]);
    {candidate tests of the neighbour-list kernel, its launches}.
    Synchronises. */
 sph_status sph_stats(sph_ctx* ctx, int64_t out[18]);
+
+/* ---- adjoint (reverse-mode derivative) ---------------------------------
+
+   The derivative of the equations of Sect. 2.2-2.6 (density sums, the root
+   h of sum_j m_j W(r_ij, h) = m (hfact/h)^3, Omega, P, cs, the momentum and
+   energy equations with viscosity and conductivity) and of the leapfrog
+   (Sect. 2.4), with three things held fixed: the neighbour sets of the
+   forward evaluation, the viscosity switches (approaching pairs) and dt.
+   The root h enters through its implicit derivative -(dS0/dx)/(dS0/dh -
+   d[m (hfact/h)^3]/dh).  The conductivity's signal speed sqrt|P_i - P_j| has
+   no derivative where P_i = P_j; its derivative there is taken as zero.
+
+   Cotangent arrays: eleven caller-owned DEVICE float64 arrays of n entries,
+   indexed by the particle's id, not by its current position: the particles'
+   order changes with every tree build, the cotangents keep theirs.  p->id
+   must be non-NULL and hold a permutation of 0..n-1. */
+typedef struct {
+  double *x, *y, *z;     /* positions */
+  double *vx, *vy, *vz;  /* velocities */
+  double* u;             /* specific internal energy */
+  double *ax, *ay, *az;  /* accelerations */
+  double* dudt;          /* du/dt */
+} sph_cotangents;
+
+/* Adjoint of the evaluation last done by sph_density + sph_force on p (no
+   sph_build_tree or sph_step in between; p unchanged).  Reads g->ax, ay, az,
+   dudt (the cotangents of that evaluation's outputs) and ADDS the cotangents
+   of its inputs x, y, z, vx, vy, vz, u to g->x ... g->u; g->ax ... g->dudt
+   are left unchanged.  Asynchronous unless the neighbour rows of the forward
+   pass were incomplete (a group overflowed its row or some h outgrew it):
+   then the call synchronises and rebuilds the rows at the current h.
+   Needs n_group 4 or 8 and the iterated density (h_tol >= 0).  The first
+   adjoint call on a context allocates its adjoint workspace (about 150 bytes
+   per particle of n_max); later calls allocate nothing.
+   Errors: SPH_E_ARG, SPH_E_NOMEM (workspace), SPH_E_OVERFLOW (a neighbour row
+   cannot hold all neighbours), SPH_E_HIP. */
+sph_status sph_eval_adjoint(sph_ctx* ctx, const sph_particles* p, sph_cotangents* g);
+
+/* Adjoint of one leapfrog step.  p must hold the state at the START of the
+   step being differentiated, exactly as it was passed to sph_step (x, v, u,
+   the previous a and dudt, h, m, id; any order).  The call performs that
+   step (p ends as sph_step would leave it; dt > 0 is required, the step is
+   frozen at that value), then replaces the cotangents of the step's outputs
+   held in g (x, v, u, a, dudt at the step's end) by those of its inputs
+   (x, v, u, a, dudt at its start).  Chaining K calls backwards over saved
+   step-start states, then one sph_eval_adjoint of the initial evaluation,
+   gives the gradient of a K-step rollout.  Synchronises like
+   sph_eval_adjoint.  Errors as sph_step and sph_eval_adjoint. */
+sph_status sph_step_adjoint(sph_ctx* ctx, sph_particles* p, double dt, sph_cotangents* g);
 
 /* Human-readable description of the last failure of this context; with
    ctx == NULL, of the last failed sph_create on the calling thread. */

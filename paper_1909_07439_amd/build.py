@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsph.so")
 BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["sph_kernels.hip", "sph_host.hip"]
+SOURCES = ["sph_kernels.hip", "sph_host.hip", "sph_adjoint.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

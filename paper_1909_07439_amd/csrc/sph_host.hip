@@ -31,6 +31,7 @@ enum Phase {
   kPhLists,
   kPhDensityFb,
   kPhForceFb,
+  kPhAdjoint,
   kNPh
 };
 
@@ -109,7 +110,9 @@ sph_status status_of_err(sph_ctx* c, uint32_t e) {
   if (e & kErrFrontier) s += " walk frontier capacity exceeded (density);";
   if (e & kErrFrontierForce) s += " walk frontier capacity exceeded (force);";
   if (e & kErrPairs) s += " pair list capacity exceeded;";
+  if (e & kErrIds) s += " particle id outside [0, n) in the adjoint;";
   c->err = s;
+  if (e & kErrIds) return SPH_E_ARG;
   if (e & kErrNonFinite) return SPH_E_NONFINITE;
   if (e & kErrDomain) return SPH_E_DOMAIN;
   if (e & kErrNoConv) return SPH_E_NOCONV;
@@ -334,7 +337,8 @@ void sph_destroy(sph_ctx* c) {
                   c->grp_count, c->ginfo,       c->frec,         c->a1,          c->nb_cnt,
                   c->nb_off,    c->red_part,    c->red_out,      c->ds,
                   c->leaf_pool, c->gl_off,      c->gl_cnt,       c->nl_idx,      c->nl_len,
-                  c->gflag,     c->flag_list,   c->walk_spill,   c->grp_of};
+                  c->gflag,     c->flag_list,   c->walk_spill,   c->grp_of,
+                  c->adj_abar,  c->adj_raw,     c->adj_ab};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->hs) (void)hipHostFree(c->hs);
@@ -470,6 +474,99 @@ sph_status sph_step(sph_ctx* c, sph_particles* p, double dt, double* dt_next_out
   return SPH_OK;
 }
 
+// ---- adjoint ----------------------------------------------------------------
+
+static sph_status adj_check(sph_ctx* c, const sph_particles* p, const sph_cotangents* g) {
+  sph_status st = check_parts(c, p, true, true);
+  if (st != SPH_OK) return st;
+  if (!p->id) return fail(c, SPH_E_ARG, "the adjoint needs particle ids (p->id)");
+  if (!g || !g->x || !g->y || !g->z || !g->vx || !g->vy || !g->vz || !g->u || !g->ax || !g->ay ||
+      !g->az || !g->dudt)
+    return fail(c, SPH_E_ARG, "every cotangent array is required");
+  if (!sph::lists_mode(c)) return fail(c, SPH_E_ARG, "the adjoint needs n_group 4 or 8");
+  if (c->kp.fixed_passes)
+    return fail(c, SPH_E_ARG, "the adjoint differentiates the iterated density (h_tol >= 0)");
+  if (!c->adj_raw) {
+    const int64_t N = c->n_max;
+    hipError_t e = hipMalloc(&c->adj_abar, 32 * (size_t)N);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->adj_raw, 13 * sizeof(double) * (size_t)N);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->adj_ab, sizeof(double2) * (size_t)N);
+    if (e != hipSuccess) {
+      (void)hipFree(c->adj_abar);
+      (void)hipFree(c->adj_raw);
+      (void)hipFree(c->adj_ab);
+      c->adj_abar = nullptr;
+      c->adj_raw = nullptr;
+      c->adj_ab = nullptr;
+      return hip_fail(c, e, "adjoint workspace");
+    }
+  }
+  return SPH_OK;
+}
+
+// The adjoint kernels read the neighbour-list rows of the forward pass.  They
+// hold every density and force pair unless a group was flagged (its row
+// overflowed or some h outgrew it); then the rows are rebuilt at the current
+// h and must be complete.
+static sph_status adj_rows(sph_ctx* c, const sph_particles* p) {
+  sph_status st = sync_state(c, true);
+  if (st != SPH_OK) return st;
+  if (c->hs->n_flagged == 0) return SPH_OK;
+  HIPCHK(c, sph::launch_node_h(c, p, true));
+  HIPCHK(c, sph::launch_leaf_state(c, 1));
+  HIPCHK(c, sph::launch_lists(c, p));
+  ++c->lists_launches;
+  st = sync_state(c, true);
+  if (st != SPH_OK) return st;
+  if (c->hs->n_flagged != 0)
+    return fail(c, SPH_E_OVERFLOW, "adjoint: a neighbour-list row cannot hold all neighbours");
+  return SPH_OK;
+}
+
+sph_status sph_eval_adjoint(sph_ctx* c, const sph_particles* p, sph_cotangents* g) {
+  if (!c) return SPH_E_ARG;
+  sph_status st = adj_check(c, p, g);
+  if (st != SPH_OK) return st;
+  if (p->n != c->n) return fail(c, SPH_E_ARG, "n differs from the last sph_build_tree");
+  st = adj_rows(c, p);
+  if (st != SPH_OK) return st;
+  ph_begin(c, kPhAdjoint);
+  HIPCHK(c, sph::launch_adjoint(c, p, g, 0.0, false));
+  ph_end(c, kPhAdjoint);
+  return SPH_OK;
+}
+
+sph_status sph_step_adjoint(sph_ctx* c, sph_particles* p, double dt, sph_cotangents* g) {
+  if (!c) return SPH_E_ARG;
+  sph_status st = adj_check(c, p, g);
+  if (st != SPH_OK) return st;
+  if (!(dt > 0.0) || !isfinite(dt)) return fail(c, SPH_E_ARG, "the step adjoint needs dt > 0");
+  // the forward step up to the corrector (as sph_step)
+  ph_begin(c, kPhStep);
+  HIPCHK(c, sph::launch_reset_counters(c));
+  HIPCHK(c, sph::launch_set_dt(c, dt));
+  st = do_build(c, p, false, true);
+  if (st != SPH_OK) return st;
+  HIPCHK(c, sph::launch_leaf_state(c, 1));
+  st = run_density(c, p);
+  if (st != SPH_OK) return st;
+  HIPCHK(c, sph::launch_node_h(c, p, false));
+  HIPCHK(c, sph::launch_force_reset(c));
+  st = run_force(c, p, true);
+  if (st != SPH_OK) return st;
+  ph_end(c, kPhStep);
+  // reverse sweep at the predicted state (x1, v_p, u_p, new a in scratch)
+  st = adj_rows(c, p);
+  if (st != SPH_OK) return st;
+  ph_begin(c, kPhAdjoint);
+  HIPCHK(c, sph::launch_adjoint(c, p, g, dt, true));
+  ph_end(c, kPhAdjoint);
+  ph_begin(c, kPhIntegrate);
+  HIPCHK(c, sph::launch_correct(c, p));
+  ph_end(c, kPhIntegrate);
+  return SPH_OK;
+}
+
 sph_status sph_reduce(sph_ctx* c, const sph_particles* p, double out[12]) {
   if (!c || !out) return SPH_E_ARG;
   sph_status st = check_parts(c, p, true, false);
@@ -597,7 +694,7 @@ sph_status sph_timings(sph_ctx* c, double out[12]) {
   for (int k = 0; k < 12; ++k) out[k] = 0.0;
   sph_timing* x = c->tm;
   if (!x || !x->ready) return SPH_OK;
-  const int map[kNPh] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9};
+  const int map[kNPh] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10};
   for (int ph = 0; ph < kNPh; ++ph) {
     double s = 0.0;
     const int n = x->count[ph];

@@ -23,6 +23,7 @@ enum : uint32_t {
   kErrNonFinite = 32u,
   kErrLeaves = 64u,
   kErrFrontierForce = 128u,  // walk frontier capacity in the force pass
+  kErrIds = 256u,            // a particle id outside [0, n) (adjoint cotangent index)
 };
 
 // Device-resident scalars of one context.
@@ -139,4 +140,7 @@ hipError_t launch_set_dt(sph_ctx* c, double dt_host);
 hipError_t launch_reduce(sph_ctx* c, const sph_particles* p, double* dev_out);
 hipError_t launch_neighbours(sph_ctx* c, const sph_particles* p, int mode, int32_t* counts,
                              const int64_t* offsets, int32_t* idx);
+// implemented in sph_adjoint.hip
+hipError_t launch_adjoint(sph_ctx* c, const sph_particles* p, const sph_cotangents* g, double dt,
+                          bool step_mode);
 }  // namespace sph

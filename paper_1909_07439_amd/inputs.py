@@ -121,6 +121,20 @@ def lattice(n_side: int = 32, jitter: float = 0.05, velocities: bool = False,
     return _finish(cfg, arrays)
 
 
+def adjoint_lattice(n_side: int = 64) -> dict:
+    """Workload of the rollout gradient: the jittered lattice (+-0.05
+    spacings) with seeded velocities (each component uniform in +-0.1 of the
+    sound speed) and u on two levels, 1 and 1.2, at random.  At v = 0 every
+    pair would sit on the viscosity switch (w = 0), where the loss has no
+    derivative in v; with u on two levels the conductivity's sqrt|P_i - P_j|
+    is far from its kink wherever u_i != u_j."""
+    cfg = lattice(n_side, jitter=0.05, velocities=True)
+    rng = _rng(4, 0)
+    cfg["u"] = np.where(rng.random(cfg["n"]) < 0.5, 1.0, 1.2)
+    cfg["workload"] = f"adjoint_lattice{n_side}"
+    return cfg
+
+
 def sod(dx_left: float = 1.0 / 512, width: float = 1.0 / 16, gamma: float = 5.0 / 3.0) -> dict:
     """Shock tube on [-1/2,1/2] x [-w/2,w/2]^2, periodic on all axes.
 

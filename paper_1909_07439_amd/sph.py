@@ -69,6 +69,13 @@ class sph_particles(ctypes.Structure):
         [(f, ctypes.c_void_p) for f in FIELDS]
 
 
+COT_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "u", "ax", "ay", "az", "dudt")
+
+
+class sph_cotangents(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in COT_FIELDS]
+
+
 _lock = threading.Lock()
 _lib = None
 
@@ -104,11 +111,14 @@ def load() -> ctypes.CDLL:
         lib.sph_neighbours.argtypes = [vp, P(sph_particles), i32, vp, vp, i64]
         lib.sph_timings.argtypes = [vp, P(d)]
         lib.sph_stats.argtypes = [vp, P(i64)]
+        lib.sph_eval_adjoint.argtypes = [vp, P(sph_particles), P(sph_cotangents)]
+        lib.sph_step_adjoint.argtypes = [vp, P(sph_particles), d, P(sph_cotangents)]
         lib.sph_last_error.argtypes = [vp]
         lib.sph_last_error.restype = ctypes.c_char_p
         for name in ("sph_create", "sph_build_tree", "sph_density", "sph_force", "sph_step",
                      "sph_reduce", "sph_check", "sph_get_keys", "sph_get_tree",
-                     "sph_get_groups", "sph_neighbours", "sph_timings", "sph_stats"):
+                     "sph_get_groups", "sph_neighbours", "sph_timings", "sph_stats",
+                     "sph_eval_adjoint", "sph_step_adjoint"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
         return lib
@@ -168,6 +178,31 @@ class Particles:
         self.c.id = self.t["id"].data_ptr()
         for f in FIELDS:
             setattr(self.c, f, self.t[f].data_ptr())
+
+    @classmethod
+    def from_tensors(cls, tensors: dict) -> "Particles":
+        """A particle set holding copies of the given device tensors (missing
+        fields are zero; missing ids are 0..n-1)."""
+        import torch
+
+        self = cls.__new__(cls)
+        ref = tensors["x"]
+        n = int(ref.shape[0])
+        self.n = n
+        self.t = {}
+        for f in FIELDS:
+            src = tensors.get(f)
+            self.t[f] = (torch.zeros(n, dtype=torch.float64, device=ref.device) if src is None
+                         else src.detach().to(torch.float64).contiguous().clone())
+        ids = tensors.get("id")
+        self.t["id"] = (torch.arange(n, dtype=torch.int64, device=ref.device) if ids is None
+                        else ids.detach().to(torch.int64).contiguous().clone())
+        self.c = sph_particles()
+        self.c.n = n
+        self.c.id = self.t["id"].data_ptr()
+        for f in FIELDS:
+            setattr(self.c, f, self.t[f].data_ptr())
+        return self
 
     def numpy(self, *names) -> dict:
         names = names or (FIELDS + ("id",))
@@ -290,8 +325,120 @@ def sph_neighbours(ctx: Context, p: Particles, mode: int):
     return off, idx[:total]
 
 
+class Cotangents:
+    """The eleven cotangent arrays of the adjoint (device float64 tensors of
+    n entries, indexed by particle id), and their C view."""
+
+    def __init__(self, n: int, device="cuda", tensors: dict | None = None):
+        import torch
+
+        self.t = {}
+        for f in COT_FIELDS:
+            src = None if tensors is None else tensors.get(f)
+            self.t[f] = (torch.zeros(n, dtype=torch.float64, device=device) if src is None
+                         else src.detach().to(torch.float64).contiguous().clone())
+        self.c = sph_cotangents()
+        for f in COT_FIELDS:
+            setattr(self.c, f, self.t[f].data_ptr())
+
+
+def sph_eval_adjoint(ctx: Context, p: Particles, g: Cotangents) -> None:
+    _check(ctx.h, ctx.lib.sph_eval_adjoint(ctx.h, ctypes.byref(p.c), ctypes.byref(g.c)),
+           "sph_eval_adjoint")
+
+
+def sph_step_adjoint(ctx: Context, p: Particles, dt: float, g: Cotangents) -> None:
+    _check(ctx.h, ctx.lib.sph_step_adjoint(ctx.h, ctypes.byref(p.c), float(dt),
+                                           ctypes.byref(g.c)), "sph_step_adjoint")
+
+
+STEP_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "m", "u", "h", "ax", "ay", "az", "dudt")
+ROLLOUT_IN = ("x", "y", "z", "vx", "vy", "vz", "u")
+ROLLOUT_OUT = COT_FIELDS
+
+
+def _original_order(p: Particles, names):
+    """Fields of p scattered back to the callers' order (by id)."""
+    import torch
+
+    ids = p.t["id"]
+    out = []
+    for k in names:
+        o = torch.empty_like(p.t[k])
+        o[ids] = p.t[k]
+        out.append(o)
+    return out
+
+
+def _rollout_autograd():
+    import torch
+
+    class Rollout(torch.autograd.Function):
+        """Initial evaluation and K leapfrog steps of fixed dt as one
+        differentiable function of the initial x, y, z, vx, vy, vz, u (device
+        float64 tensors in the callers' order).  Returns the final x, y, z,
+        vx, vy, vz, u, ax, ay, az, dudt in the same order.  The forward keeps
+        the state at the start of every step (checkpoints); the backward
+        replays each step in reverse through sph_step_adjoint and ends with
+        sph_eval_adjoint of the initial evaluation."""
+
+        @staticmethod
+        def forward(fctx, spec, *inp):
+            ctx, m, h0, dt, K = spec
+            state = dict(zip(ROLLOUT_IN, inp))
+            state.update(m=m, h=h0)
+            p = Particles.from_tensors(state)
+            sph_build_tree(ctx, p)
+            sph_density(ctx, p)
+            sph_force(ctx, p)
+            ckpt = []
+            for _ in range(K):
+                ckpt.append({k: p.t[k].clone() for k in STEP_FIELDS + ("id",)})
+                sph_step(ctx, p, dt)
+            fctx.spec = spec
+            fctx.ckpt = ckpt
+            fctx.save_for_backward(*inp)
+            return tuple(_original_order(p, ROLLOUT_OUT))
+
+        @staticmethod
+        def backward(fctx, *gout):
+            ctx, m, h0, dt, K = fctx.spec
+            inp = fctx.saved_tensors
+            n = inp[0].shape[0]
+            g = Cotangents(n, device=inp[0].device,
+                           tensors={k: v for k, v in zip(ROLLOUT_OUT, gout) if v is not None})
+            for s in reversed(range(K)):
+                p = Particles.from_tensors(fctx.ckpt[s])
+                sph_step_adjoint(ctx, p, dt, g)
+            state = dict(zip(ROLLOUT_IN, inp))
+            state.update(m=m, h=h0)
+            p = Particles.from_tensors(state)
+            sph_build_tree(ctx, p)
+            sph_density(ctx, p)
+            sph_force(ctx, p)
+            sph_eval_adjoint(ctx, p, g)
+            return (None,) + tuple(g.t[k] for k in ROLLOUT_IN)
+
+    return Rollout
+
+
+_ROLLOUT = None
+
+
+def rollout(ctx: Context, state: dict, dt: float, K: int) -> dict:
+    """Differentiable K-step rollout (see Rollout).  ``state`` holds device
+    float64 tensors x, y, z, vx, vy, vz, u (may require grad), m and h (the
+    smoothing-length start values)."""
+    global _ROLLOUT
+    if _ROLLOUT is None:
+        _ROLLOUT = _rollout_autograd()
+    spec = (ctx, state["m"], state["h"], float(dt), int(K))
+    out = _ROLLOUT.apply(spec, *[state[k] for k in ROLLOUT_IN])
+    return dict(zip(ROLLOUT_OUT, out))
+
+
 PHASES = ("keys_sort", "permute", "tree", "density", "force", "integrate", "step",
-          "lists", "density_fallback", "force_fallback")
+          "lists", "density_fallback", "force_fallback", "adjoint")
 
 
 def sph_timings(ctx: Context) -> dict:

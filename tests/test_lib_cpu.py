@@ -47,6 +47,8 @@ int main(void) {
          offsetof(sph_params, kernel), offsetof(sph_params, h_tol),
          offsetof(sph_params, h_margin), sizeof(sph_particles));
   printf("%zu %zu\n", offsetof(sph_particles, x), offsetof(sph_particles, vsig_dt));
+  printf("%zu %zu %zu\n", sizeof(sph_cotangents), offsetof(sph_cotangents, u),
+         offsetof(sph_cotangents, dudt));
   return 0;
 }
 ''')
@@ -63,6 +65,10 @@ int main(void) {
     assert int(out[5]) == ctypes.sizeof(Q)
     assert int(out[6]) == Q.x.offset
     assert int(out[7]) == Q.vsig_dt.offset
+    G = sph.sph_cotangents
+    assert int(out[8]) == ctypes.sizeof(G)
+    assert int(out[9]) == G.u.offset
+    assert int(out[10]) == G.dudt.offset
 
 
 def _params(**kw):
@@ -98,5 +104,7 @@ def test_create_rejects_bad_sizes(lib):
 def test_null_context_is_an_argument_error(lib):
     assert lib.sph_build_tree(None, None) == sph.SPH_E_ARG
     assert lib.sph_check(None) == sph.SPH_E_ARG
+    assert lib.sph_eval_adjoint(None, None, None) == sph.SPH_E_ARG
+    assert lib.sph_step_adjoint(None, None, 1.0, None) == sph.SPH_E_ARG
     assert isinstance(lib.sph_last_error(None), bytes)
     lib.sph_destroy(None)
