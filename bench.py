@@ -43,6 +43,12 @@ DENSITY_FLOPS_PER_PAIR_SUM = {0: 22, 1: 33, 2: 30}
 #   radius 2 max(hl_i, h_margin h_j) 3, its square with the FP32 guard 2,
 #   compare 1
 LIST_FLOPS_PER_CANDIDATE = 14
+#   adjoint force pair (k_adj_force, per ordered pair (k, j), both the term of
+#   a_k and the mirror term of a_j): geometry and predicate 17, r and e 5,
+#   w 8, F, F_r, F_h at h_k and h_j 47, viscosity speeds and T, dT/dw 24,
+#   conductivity speed and its derivatives 13, brackets 9, projections 14,
+#   term of k 125, mirror term 110
+ADJ_FORCE_FLOPS_PER_PAIR = {0: 372, 1: 396, 2: 388}
 # Vector ALU peak of the 256 CUs at 2.4 GHz for non-packed FP32 (and FP64)
 # FMA: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz.  The published FP32
 # figure of 157.3 TFLOP/s needs packed FP32 instructions, which this build
@@ -166,6 +172,83 @@ def roofline(kernel, flops, launch_ms, units, flops_per_unit, traffic):
             "flops_per_unit": flops_per_unit}
 
 
+def adjoint_cost(precision, n_side=64, K=8, reps=3):
+    """Cost of the gradient of a K-step rollout against the rollout itself on
+    the adjoint workload: forward = initial evaluation + K steps, keeping the
+    state at the start of every step; backward = K sph_step_adjoint calls
+    (each replays its step, then runs the adjoint kernels) + the initial
+    evaluation and its sph_eval_adjoint.  Median of ``reps`` repetitions."""
+    import numpy as np
+    import torch
+
+    from paper_1909_07439_amd import inputs, sph
+
+    cfg = inputs.adjoint_lattice(n_side)
+    p = sph.make_params(cfg, precision)
+    ctx = sph.Context(p, cfg["n"])
+    base = sph.Particles(cfg)
+    sph.sph_build_tree(ctx, base)
+    sph.sph_density(ctx, base)
+    dt = sph.sph_force(ctx, base, want_dt=True)
+    start = {k: torch.as_tensor(np.ascontiguousarray(cfg[k], dtype=np.float64)).cuda()
+             for k in ("x", "y", "z", "vx", "vy", "vz", "m", "u", "h")}
+    fw, bw = [], []
+    tim = {}
+    st0 = sph.sph_stats(ctx)
+    for rep in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pp = sph.Particles.from_tensors(start)
+        sph.sph_build_tree(ctx, pp)
+        sph.sph_density(ctx, pp)
+        sph.sph_force(ctx, pp)
+        ckpt = []
+        for _ in range(K):
+            ckpt.append({k: pp.t[k].clone() for k in sph.STEP_FIELDS + ("id",)})
+            sph.sph_step(ctx, pp, dt)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g = sph.Cotangents(cfg["n"])
+        g.t["ax"].fill_(1.0)
+        g.t["vx"].fill_(1.0)
+        if rep == 1:
+            sph.sph_timings(ctx)
+            st0 = sph.sph_stats(ctx)
+        for s in reversed(range(K)):
+            q = sph.Particles.from_tensors(ckpt[s])
+            sph.sph_step_adjoint(ctx, q, dt, g)
+        q = sph.Particles.from_tensors(start)
+        sph.sph_build_tree(ctx, q)
+        sph.sph_density(ctx, q)
+        sph.sph_force(ctx, q)
+        sph.sph_eval_adjoint(ctx, q, g)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        sph.sph_check(ctx)
+        if rep > 0:
+            fw.append(t1 - t0)
+            bw.append(t2 - t1)
+    tim = sph.sph_timings(ctx)
+    st = sph.sph_stats(ctx)
+    ctx.close()
+    f, b = float(np.median(fw)), float(np.median(bw))
+    # ordered force pairs per adjoint launch: force pairs of the force launches
+    # in the timed backward passes (one force launch per adjoint launch)
+    nf = st["force_launches"] - st0["force_launches"]
+    fpl = (st["total_force_pairs"] - st0["total_force_pairs"]) / max(nf, 1)
+    kk = int(cfg.get("kernel", 0))
+    tag = "mixed" if precision == sph.SPH_PREC_MIXED else "fp64"
+    return {"workload": cfg["workload"], "n_particles": cfg["n"], "steps": K,
+            "precision": tag, "dt": dt, "forward_ms": round(1e3 * f, 3),
+            "backward_ms": round(1e3 * b, 3), "backward_over_forward": round(b / f, 3),
+            "adjoint_kernels_ms_per_launch": round(tim["adjoint"], 5),
+            "step_forward_part_ms": round(tim["step"], 5),
+            "roofline": roofline(f"k_adj_force<{tag}>", ADJ_FORCE_FLOPS_PER_PAIR[kk] * fpl,
+                                 tim["adjoint_force"], {"force_pairs": fpl},
+                                 ADJ_FORCE_FLOPS_PER_PAIR[kk], None)
+            if tim.get("adjoint_force", 0.0) > 0 else None}
+
+
 def cpu_baseline(cfg, budget_s=12.0):
     import oracle
 
@@ -195,6 +278,8 @@ def main():
     ap.add_argument("--n-leaf", type=int, default=None, help="particles per tree leaf")
     ap.add_argument("--kernel", default="m4", choices=["m4", "m6", "wc6"],
                     help="smoothing kernel (M4 cubic, M6 quintic, Wendland C6)")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the rollout-gradient cost on the adjoint workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run a plain streaming kernel over MIB MiB "
                          "(scale for PMC byte counters)")
@@ -297,6 +382,9 @@ def main():
             "a_max_over_rms_a": float(max(np.max(np.abs(a[k] - b[k])) for k in ("ax", "ay", "az"))
                                       / scale),
         }
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_cost(prec)
+        print(f"[bench] adjoint: {out['adjoint']}", flush=True)
     if args.copy_calibration > 0:
         copy_calibration(args.copy_calibration)
     if not args.no_cpu_baseline:

@@ -185,9 +185,10 @@ sph_status sph_neighbours(sph_ctx* ctx, const sph_particles* p, int32_t mode, in
    phase (at most 1024 launches per phase are kept): out[0..11] = {keys+sort,
    permute, tree, density, force, integrate, total step, neighbour lists,
    density of flagged groups, force of flagged groups, adjoint kernels of
-   sph_eval_adjoint / sph_step_adjoint, reserved}.
-   The density, force, integrate, neighbour-list and flagged-group phases each
-   bracket exactly one kernel.  Clears the kept events.  Synchronises. */
+   sph_eval_adjoint / sph_step_adjoint, the force-adjoint kernel alone}.
+   The density, force, integrate, neighbour-list, flagged-group and
+   force-adjoint phases each bracket exactly one kernel.  Clears the kept
+   events.  Synchronises. */
 sph_status sph_timings(sph_ctx* ctx, double out[12]);
 
 /* Counters of the work done (for throughput accounting).  out[0..9] refer

@@ -532,39 +532,41 @@ static Cot cot_of(const sph_cotangents* g) {
   return Cot{g->x, g->y, g->z, g->vx, g->vy, g->vz, g->u, g->ax, g->ay, g->az, g->dudt};
 }
 
+// Three launches: the seed, the force adjoint (the dominant kernel, timed on
+// its own by the host) and the two density passes with the final combination.
 hipError_t launch_adjoint(sph_ctx* c, const sph_particles* s, const sph_cotangents* gc, double dt,
-                          bool step_mode) {
+                          bool step_mode, int part) {
   c->kp.n = c->n;
   const Parts p = adj_parts(s);
   const Cot g = cot_of(gc);
   const int n = c->n;
   const int64_t ns = c->n_max;
   const bool mixed = c->kp.precision == SPH_PREC_MIXED;
-  const int sblocks = (int)std::min<int64_t>((n + 255) / 256, 8 * (int64_t)c->n_cu);
   const dim3 grid(c->walk_blocks), block(64);
-  if (mixed)
-    hipLaunchKernelGGL(k_adj_seed<true>, dim3(sblocks), dim3(256), 0, c->stream, n, p.id, g,
-                       0.5 * dt, step_mode ? 1 : 0, c->adj_abar, &c->ds->err);
-  else
-    hipLaunchKernelGGL(k_adj_seed<false>, dim3(sblocks), dim3(256), 0, c->stream, n, p.id, g,
-                       0.5 * dt, step_mode ? 1 : 0, c->adj_abar, &c->ds->err);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   constexpr int LPI = 8;
-  if (mixed)
-    hipLaunchKernelGGL((k_adj_force<true, LPI>), grid, block, 0, c->stream, c->kp, p, c->frec,
-                       c->adj_abar, c->nl_idx, c->nl_len, c->adj_raw, ns);
-  else
-    hipLaunchKernelGGL((k_adj_force<false, LPI>), grid, block, 0, c->stream, c->kp, p, c->frec,
-                       c->adj_abar, c->nl_idx, c->nl_len, c->adj_raw, ns);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_adj_dens1<LPI>), grid, block, 0, c->stream, c->kp, p, c->nl_idx,
-                     c->nl_len, c->adj_raw, ns, c->adj_ab);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_adj_dens2<LPI>), grid, block, 0, c->stream, c->kp, p, c->nl_idx,
-                     c->nl_len, c->adj_raw, ns, c->adj_ab, g, dt, step_mode ? 1 : 0);
+  if (part == 0) {
+    const int sblocks = (int)std::min<int64_t>((n + 255) / 256, 8 * (int64_t)c->n_cu);
+    if (mixed)
+      hipLaunchKernelGGL(k_adj_seed<true>, dim3(sblocks), dim3(256), 0, c->stream, n, p.id, g,
+                         0.5 * dt, step_mode ? 1 : 0, c->adj_abar, &c->ds->err);
+    else
+      hipLaunchKernelGGL(k_adj_seed<false>, dim3(sblocks), dim3(256), 0, c->stream, n, p.id, g,
+                         0.5 * dt, step_mode ? 1 : 0, c->adj_abar, &c->ds->err);
+  } else if (part == 1) {
+    if (mixed)
+      hipLaunchKernelGGL((k_adj_force<true, LPI>), grid, block, 0, c->stream, c->kp, p, c->frec,
+                         c->adj_abar, c->nl_idx, c->nl_len, c->adj_raw, ns);
+    else
+      hipLaunchKernelGGL((k_adj_force<false, LPI>), grid, block, 0, c->stream, c->kp, p, c->frec,
+                         c->adj_abar, c->nl_idx, c->nl_len, c->adj_raw, ns);
+  } else {
+    hipLaunchKernelGGL((k_adj_dens1<LPI>), grid, block, 0, c->stream, c->kp, p, c->nl_idx,
+                       c->nl_len, c->adj_raw, ns, c->adj_ab);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_adj_dens2<LPI>), grid, block, 0, c->stream, c->kp, p, c->nl_idx,
+                       c->nl_len, c->adj_raw, ns, c->adj_ab, g, dt, step_mode ? 1 : 0);
+  }
   return hipGetLastError();
 }
 

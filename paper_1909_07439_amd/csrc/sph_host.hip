@@ -32,6 +32,7 @@ enum Phase {
   kPhDensityFb,
   kPhForceFb,
   kPhAdjoint,
+  kPhAdjForce,
   kNPh
 };
 
@@ -508,6 +509,18 @@ static sph_status adj_check(sph_ctx* c, const sph_particles* p, const sph_cotang
 // hold every density and force pair unless a group was flagged (its row
 // overflowed or some h outgrew it); then the rows are rebuilt at the current
 // h and must be complete.
+static sph_status adj_launch(sph_ctx* c, const sph_particles* p, sph_cotangents* g, double dt,
+                             bool step_mode) {
+  ph_begin(c, kPhAdjoint);
+  HIPCHK(c, sph::launch_adjoint(c, p, g, dt, step_mode, 0));
+  ph_begin(c, kPhAdjForce);
+  HIPCHK(c, sph::launch_adjoint(c, p, g, dt, step_mode, 1));
+  ph_end(c, kPhAdjForce);
+  HIPCHK(c, sph::launch_adjoint(c, p, g, dt, step_mode, 2));
+  ph_end(c, kPhAdjoint);
+  return SPH_OK;
+}
+
 static sph_status adj_rows(sph_ctx* c, const sph_particles* p) {
   sph_status st = sync_state(c, true);
   if (st != SPH_OK) return st;
@@ -530,10 +543,7 @@ sph_status sph_eval_adjoint(sph_ctx* c, const sph_particles* p, sph_cotangents* 
   if (p->n != c->n) return fail(c, SPH_E_ARG, "n differs from the last sph_build_tree");
   st = adj_rows(c, p);
   if (st != SPH_OK) return st;
-  ph_begin(c, kPhAdjoint);
-  HIPCHK(c, sph::launch_adjoint(c, p, g, 0.0, false));
-  ph_end(c, kPhAdjoint);
-  return SPH_OK;
+  return adj_launch(c, p, g, 0.0, false);
 }
 
 sph_status sph_step_adjoint(sph_ctx* c, sph_particles* p, double dt, sph_cotangents* g) {
@@ -558,9 +568,8 @@ sph_status sph_step_adjoint(sph_ctx* c, sph_particles* p, double dt, sph_cotange
   // reverse sweep at the predicted state (x1, v_p, u_p, new a in scratch)
   st = adj_rows(c, p);
   if (st != SPH_OK) return st;
-  ph_begin(c, kPhAdjoint);
-  HIPCHK(c, sph::launch_adjoint(c, p, g, dt, true));
-  ph_end(c, kPhAdjoint);
+  st = adj_launch(c, p, g, dt, true);
+  if (st != SPH_OK) return st;
   ph_begin(c, kPhIntegrate);
   HIPCHK(c, sph::launch_correct(c, p));
   ph_end(c, kPhIntegrate);
@@ -694,7 +703,7 @@ sph_status sph_timings(sph_ctx* c, double out[12]) {
   for (int k = 0; k < 12; ++k) out[k] = 0.0;
   sph_timing* x = c->tm;
   if (!x || !x->ready) return SPH_OK;
-  const int map[kNPh] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10};
+  const int map[kNPh] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11};
   for (int ph = 0; ph < kNPh; ++ph) {
     double s = 0.0;
     const int n = x->count[ph];

@@ -141,6 +141,7 @@ hipError_t launch_reduce(sph_ctx* c, const sph_particles* p, double* dev_out);
 hipError_t launch_neighbours(sph_ctx* c, const sph_particles* p, int mode, int32_t* counts,
                              const int64_t* offsets, int32_t* idx);
 // implemented in sph_adjoint.hip
+// part 0: seed, 1: force adjoint, 2: density adjoint and final combination
 hipError_t launch_adjoint(sph_ctx* c, const sph_particles* p, const sph_cotangents* g, double dt,
-                          bool step_mode);
+                          bool step_mode, int part);
 }  // namespace sph

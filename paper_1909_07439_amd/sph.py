@@ -438,7 +438,7 @@ def rollout(ctx: Context, state: dict, dt: float, K: int) -> dict:
 
 
 PHASES = ("keys_sort", "permute", "tree", "density", "force", "integrate", "step",
-          "lists", "density_fallback", "force_fallback", "adjoint")
+          "lists", "density_fallback", "force_fallback", "adjoint", "adjoint_force")
 
 
 def sph_timings(ctx: Context) -> dict:
