@@ -68,6 +68,8 @@ def workload(name: str):
         return inputs.kelvin_helmholtz(100)
     if name == "turb":
         return inputs.turbulent_box(256)
+    if name == "blast":
+        return inputs.blast_wave()
     if name == "sod_small":
         return inputs.sod(dx_left=1.0 / 128, width=1.0 / 8)
     raise SystemExit(f"unknown workload {name}")
@@ -172,18 +174,20 @@ def roofline(kernel, flops, launch_ms, units, flops_per_unit, traffic):
             "flops_per_unit": flops_per_unit}
 
 
-def adjoint_cost(precision, n_side=64, K=8, reps=3):
+def adjoint_cost(precision, cfg=None, K=8, reps=3):
     """Cost of the gradient of a K-step rollout against the rollout itself on
-    the adjoint workload: forward = initial evaluation + K steps, keeping the
-    state at the start of every step; backward = K sph_step_adjoint calls
-    (each replays its step, then runs the adjoint kernels) + the initial
-    evaluation and its sph_eval_adjoint.  Median of ``reps`` repetitions."""
+    the adjoint workload (default: the 64^3 adjoint lattice): forward =
+    initial evaluation + K steps, keeping the state at the start of every
+    step; backward = K sph_step_adjoint calls (each replays its step, then
+    runs the adjoint kernels) + the initial evaluation and its
+    sph_eval_adjoint.  Median of ``reps`` repetitions."""
     import numpy as np
     import torch
 
     from paper_1909_07439_amd import inputs, sph
 
-    cfg = inputs.adjoint_lattice(n_side)
+    if cfg is None:
+        cfg = inputs.adjoint_lattice(64)
     p = sph.make_params(cfg, precision)
     ctx = sph.Context(p, cfg["n"])
     base = sph.Particles(cfg)
@@ -280,6 +284,10 @@ def main():
                     help="smoothing kernel (M4 cubic, M6 quintic, Wendland C6)")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the rollout-gradient cost on the adjoint workload")
+    ap.add_argument("--adjoint-on-workload", action="store_true",
+                    help="measure the gradient cost of ONE step of the bench workload itself "
+                         "(e.g. the final step of the turbulent box) instead of the 8-step "
+                         "adjoint lattice")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run a plain streaming kernel over MIB MiB "
                          "(scale for PMC byte counters)")
@@ -383,7 +391,10 @@ def main():
                                       / scale),
         }
     if not args.no_adjoint:
-        out["adjoint"] = adjoint_cost(prec)
+        if args.adjoint_on_workload:
+            out["adjoint"] = adjoint_cost(prec, cfg=cfg, K=1, reps=2)
+        else:
+            out["adjoint"] = adjoint_cost(prec)
         print(f"[bench] adjoint: {out['adjoint']}", flush=True)
     if args.copy_calibration > 0:
         copy_calibration(args.copy_calibration)

@@ -165,6 +165,38 @@ def sod(dx_left: float = 1.0 / 512, width: float = 1.0 / 16, gamma: float = 5.0 
     return _finish(cfg, arrays)
 
 
+def blast_wave(dx: float = 1.0 / 800, half_length: float = 1.0, n_cross: int = 12,
+               gamma: float = 1.4) -> dict:
+    """Blast-wave tube (Sect. 4.2): [rho, P] = [1, 1000] for x <= 0 and
+    [1, 0.1] for x > 0, gamma = 7/5, both states on one cubic lattice of
+    spacing dx (equal densities), n_cross x n_cross particles across.
+
+    The box is [-half_length, half_length] x [-w/2, w/2]^2 (w = n_cross dx),
+    periodic on all axes: the periodic copy of the interface at x = +-half_length
+    starts a mirrored Riemann problem whose waves, with the default
+    half_length = 1, stay clear of |x| < 0.5 until after t = 0.01 (the
+    rarefaction heads move at c_L = 37.4).  With the defaults: 1600 x 12 x 12
+    = 230,400 particles, 400 per unit length as in the paper.
+    """
+    gm1 = gamma - 1.0
+    nx = int(round(2.0 * half_length / dx))
+    i, j, k = _grid(nx, n_cross, n_cross)
+    w = n_cross * dx
+    x = -half_length + (i + 0.5) * dx
+    y = -0.5 * w + (j + 0.5) * dx
+    z = -0.5 * w + (k + 0.5) * dx
+    n = x.size
+    left = x <= 0.0
+    u = np.where(left, 1000.0 / gm1, 0.1 / gm1)
+    cfg = dict(box_lo=(-half_length, -0.5 * w, -0.5 * w), box_len=(2.0 * half_length, w, w),
+               periodic=(1, 1, 1), gamma=gamma, gamma_minus_1=gm1,
+               workload=f"blast_dx{int(round(1 / dx))}",
+               left=(1.0, 0.0, 1000.0), right=(1.0, 0.0, 0.1), dx=dx)
+    arrays = dict(x=x, y=y, z=z, vx=np.zeros(n), vy=np.zeros(n), vz=np.zeros(n),
+                  m=np.full(n, dx ** 3), u=u, h=np.full(n, DEFAULTS["hfact"] * dx))
+    return _finish(cfg, arrays)
+
+
 def kelvin_helmholtz(n_side: int = 100, jitter: float = 0.02) -> dict:
     """Shear layer in the periodic unit cube.
 
