@@ -70,6 +70,8 @@ def workload(name: str):
         return inputs.turbulent_box(256)
     if name == "blast":
         return inputs.blast_wave()
+    if name == "sedov":
+        return inputs.sedov()
     if name == "sod_small":
         return inputs.sod(dx_left=1.0 / 128, width=1.0 / 8)
     raise SystemExit(f"unknown workload {name}")

@@ -197,6 +197,33 @@ def blast_wave(dx: float = 1.0 / 800, half_length: float = 1.0, n_cross: int = 1
     return _finish(cfg, arrays)
 
 
+def sedov(n_side: int = 100, energy: float = 1.0, r_inject: float = 2.0,
+          u_ambient: float = 1e-6, gamma: float = 5.0 / 3.0) -> dict:
+    """Sedov-Taylor blast (Sect. 4.3): a uniform periodic unit cube (rho = 1)
+    on an n_side^3 cubic lattice, at rest, with the energy ``energy`` shared
+    equally (as u) by the particles within r_inject lattice spacings of the
+    centre; every other particle has u = u_ambient (a pressure 10^-6 of the
+    post-shock pressure at t = 0.1, so the shock stays strong).  With the
+    defaults the shock reaches R = 1.1517 (E t^2)^(1/5) = 0.458 at t = 0.1,
+    inside the box."""
+    gm1 = gamma - 1.0
+    dx = 1.0 / n_side
+    i, j, k = _grid(n_side, n_side, n_side)
+    x, y, z = (i + 0.5) * dx, (j + 0.5) * dx, (k + 0.5) * dx
+    n = x.size
+    m = np.full(n, dx ** 3)
+    r = np.sqrt((x - 0.5) ** 2 + (y - 0.5) ** 2 + (z - 0.5) ** 2)
+    hot = r < r_inject * dx
+    u = np.full(n, u_ambient)
+    u[hot] = energy / (m[hot].sum())
+    cfg = dict(box_lo=(0.0, 0.0, 0.0), box_len=(1.0, 1.0, 1.0), periodic=(1, 1, 1),
+               gamma=gamma, gamma_minus_1=gm1, workload=f"sedov{n_side}", dx=dx,
+               energy=energy, centre=(0.5, 0.5, 0.5), n_hot=int(hot.sum()))
+    arrays = dict(x=x, y=y, z=z, vx=np.zeros(n), vy=np.zeros(n), vz=np.zeros(n), m=m, u=u,
+                  h=np.full(n, DEFAULTS["hfact"] * dx))
+    return _finish(cfg, arrays)
+
+
 def kelvin_helmholtz(n_side: int = 100, jitter: float = 0.02) -> dict:
     """Shear layer in the periodic unit cube.
 
