@@ -237,7 +237,7 @@ typedef struct {
    pass were incomplete (a group overflowed its row or some h outgrew it):
    then the call synchronises and rebuilds the rows at the current h.
    Needs n_group 4 or 8 and the iterated density (h_tol >= 0).  The first
-   adjoint call on a context allocates its adjoint workspace (about 150 bytes
+   adjoint call on a context allocates its adjoint workspace (about 100 bytes
    per particle of n_max); later calls allocate nothing.
    Errors: SPH_E_ARG, SPH_E_NOMEM (workspace), SPH_E_OVERFLOW (a neighbour row
    cannot hold all neighbours), SPH_E_HIP. */

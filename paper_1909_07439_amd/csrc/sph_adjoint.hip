@@ -15,9 +15,9 @@
 //   k_adj_seed   cotangents of a and du/dt in key order (AoS records)
 //   k_adj_force  for particle k, both pair terms a_k(j) and a_j(k): the
 //                cotangent of x_k, v_k and of k's own h, g = P/(rho^2 Omega),
-//                kk = 1/(rho Omega), c, P, rho, u
-//   k_adj_dens1  S1, S2 = sum m_j d2W/dh2 over k's density set; the chain
-//                through P, c, g, kk, Omega and the root h gives the
+//                kk = 1/(rho Omega), c, P, rho, u; in the same pair loop
+//                S1, S2 = sum m_j d2W/dh2 over k's density set; then the
+//                chain through P, c, g, kk, Omega and the root h gives the
 //                coefficients alpha_k, beta_k of dS0_k/dx and dS1_k/dx
 //   k_adj_dens2  x-cotangent through the density sums, from both directions
 //                of each pair, and the final combination with the leapfrog
@@ -178,8 +178,7 @@ __global__ __launch_bounds__(256) void k_adj_seed(int n, const int64_t* __restri
 //   m_j [ g_k w F_k - kk_k vs_k w^2 F_k / 2 + alpha_u v^u (u_k - u_j)(F_k kk_k + F_j kk_j)/2 ].
 // Particle k differentiates its own term (cotangents abar_k) and the mirror
 // term of a_j, du_j (cotangents abar_j), with respect to x_k, v_k and k's own
-// per-particle quantities.  raw (SoA, stride ns): xb yb zb vxb vyb vzb hb gb
-// kb cb pb rb ub.
+// per-particle quantities.
 // ---------------------------------------------------------------------------
 template <bool MIXED, int LPI>
 __global__ __launch_bounds__(64) void k_adj_force(KParams kp, Parts p,
@@ -187,7 +186,8 @@ __global__ __launch_bounds__(64) void k_adj_force(KParams kp, Parts p,
                                                   const void* __restrict__ abar_in,
                                                   const int32_t* __restrict__ nl_idx,
                                                   const int32_t* __restrict__ nl_len,
-                                                  double* __restrict__ raw, int64_t ns) {
+                                                  double* __restrict__ raw, int64_t ns,
+                                                  double2* __restrict__ ab) {
   using Rec = typename ARecOf<MIXED>::T;
   using CT = typename ARecOf<MIXED>::C;
   using R = typename std::conditional<MIXED, float, double>::type;
@@ -210,6 +210,8 @@ __global__ __launch_bounds__(64) void k_adj_force(KParams kp, Parts p,
     const CT ak = abar[k];
     const double xk = rk.x, yk = rk.y, zk = rk.z;
     const R hk = (R)rk.h, hinvk = R(1) / hk, mk = (R)rk.m;
+    const R h4k = C * hinvk * hinvk * hinvk * hinvk, h5k = h4k * hinvk;
+    const R srk = S * hk, srk2 = srk * srk;
     const R vxk = (R)rk.vx, vyk = (R)rk.vy, vzk = (R)rk.vz, uk = (R)rk.u;
     const R gk = (R)rk.g, kk = (R)rk.k, ck = (R)rk.c, Pk = (R)rk.P, rhok = (R)rk.rho;
     const R Axk = (R)ak.x, Ayk = (R)ak.y, Azk = (R)ak.z, Dk = (R)ak.w;
@@ -217,6 +219,7 @@ __global__ __launch_bounds__(64) void k_adj_force(KParams kp, Parts p,
     const int32_t* __restrict__ row = nl_idx + (int64_t)k * kp.nl_cap;
     R bx = 0, by = 0, bz = 0, bvx = 0, bvy = 0, bvz = 0;
     R bh = 0, bg = 0, bk = 0, bc = 0, bp = 0, br = 0, bu = 0;
+    R s1 = 0, s2 = 0;  // density sums of dW/dh and d2W/dh2 (without C / h^4, C / h^5)
     for (int t = sub; t < len; t += LPI) {
       const int j = row[t];
       if (j == k) continue;
@@ -234,7 +237,19 @@ __global__ __launch_bounds__(64) void k_adj_force(KParams kp, Parts p,
       const R vx = vxk - (R)rj.vx, vy = vyk - (R)rj.vy, vz = vzk - (R)rj.vz;
       const R w = fma(vz, ez, fma(vy, ey, vx * ex));
       R Fk, Frk, Fhk, Fj, Frj, Fhj;
-      kern_F3<R>(kind, C, r, hinvk, Fk, Frk, Fhk);
+      {
+        const R q = r * hinvk;
+        R f, d1, d2;
+        kern3<R>(kind, q, f, d1, d2);
+        Fk = d1 * h4k;
+        Frk = d2 * h5k;
+        Fhk = -(R(4) * d1 + q * d2) * h5k;
+        if (r2 < srk2) {  // k's density set
+          const R mjd = (R)rj.m;
+          s1 += mjd * (R(3) * f + q * d1);
+          s2 += mjd * ((R(12) * f + R(8) * q * d1) + q * q * d2);
+        }
+      }
       kern_F3<R>(kind, C, r, R(1) / hj, Fj, Frj, Fhj);
       const R mj = (R)rj.m, gj = (R)rj.g, kj = (R)rj.k, cj = (R)rj.c;
       const bool chi = w < R(0);
@@ -306,98 +321,60 @@ __global__ __launch_bounds__(64) void k_adj_force(KParams kp, Parts p,
         bu += -Dj * mk * au * vu * Kb;
       }
     }
-    double o[13] = {(double)bx, (double)by, (double)bz, (double)bvx, (double)bvy, (double)bvz,
+    double o[15] = {(double)bx, (double)by, (double)bz, (double)bvx, (double)bvy, (double)bvz,
                     (double)bh, (double)bg, (double)bk, (double)bc, (double)bp, (double)br,
-                    (double)bu};
+                    (double)bu, (double)s1, (double)s2};
 #pragma unroll
-    for (int q = 0; q < 13; ++q) o[q] = seg_sum_d<LPI>(o[q]);
+    for (int q = 0; q < 15; ++q) o[q] = seg_sum_d<LPI>(o[q]);
     if (act && sub == 0) {
+      // the chain through g, kk, P, c, Omega and the root h (see below)
+      const double hd = p.h[k], hinv = 1.0 / hd;
+      double f0, d10, d20;
+      kern3<double>(kind, 0.0, f0, d10, d20);  // the self term (r = 0, f'(0) = 0)
+      const double md = p.m[k];
+      const double h4 = kp.knorm * hinv * hinv * hinv * hinv;
+      const double S1 = -(o[13] + 3.0 * md * f0) * h4;
+      const double S2 = (o[14] + 12.0 * md * f0) * h4 * hinv;
+      const double rho = p.rho[k], om = p.omega[k], P = p.P[k], u = p.u[k], c = p.cs[k];
+      const double gb = o[7], kb = o[8], cb = o[9], pb = o[10], rb = o[11], ub = o[12];
+      const double r2o = rho * rho * om;
+      const double Ptot = pb + gb / r2o;
+      double rtot = rb - 2.0 * gb * P / (r2o * rho) - kb / (om * rho * rho);
+      const double Ob = -gb * P / (r2o * om) - kb / (om * om * rho);
+      rtot += Ptot * kp.gm1 * u;
+      const double utot =
+          ub + Ptot * kp.gm1 * rho + (c > 0.0 ? cb * kp.gamma * kp.gm1 / (2.0 * c) : 0.0);
+      const double S1b = Ob * hd / (3.0 * rho);
+      rtot -= Ob * hd * S1 / (3.0 * rho * rho);
+      const double hb = o[6] + Ob * S1 / (3.0 * rho);
+      const double S0b = rtot;
+      const double H = hb + S0b * S1 + S1b * S2;
+      const double hr = kp.hfact * hinv;
+      const double rho_h = md * hr * hr * hr;
+      const double fp = S1 + 3.0 * rho_h * hinv;
+      const double lam = -H / fp;
+      ab[k] = make_double2(S0b + lam, S1b);
 #pragma unroll
-      for (int q = 0; q < 13; ++q) raw[q * ns + k] = o[q];
+      for (int q = 0; q < 6; ++q) raw[q * ns + k] = o[q];
+      raw[6 * ns + k] = utot;
     }
   }
 }
 
-// ---------------------------------------------------------------------------
-// Density adjoint, pass 1: S1 = sum m_j dW/dh and S2 = sum m_j d2W/dh2 over
-// k's density set (self included), then the chain of per-particle relations
+// The density adjoint's first half -- S1, S2 = sum m_j d2W/dh2 over k's
+// density set (self included) and the chain of per-particle relations
 //   g = P/(rho^2 Omega), kk = 1/(rho Omega), P = (gamma-1) rho u,
 //   c = sqrt(gamma (gamma-1) u), Omega = 1 + h S1/(3 rho), rho = S0,
 // and the root h (f(h) = S0 - m (hfact/h)^3 = 0):
 //   H = hbar + S0bar S1 + S1bar S2,  lambda = -H / (S1 + 3 m (hfact/h)^3 / h),
 //   alpha = S0bar + lambda,  beta = S1bar,
 // so that the x-cotangent through the density is alpha_k dS0_k/dx +
-// beta_k dS1_k/dx summed over k.  Writes ab[k] = (alpha, beta) and the final
-// u-cotangent of the evaluation into raw row 12.
-// ---------------------------------------------------------------------------
-template <int LPI>
-__global__ __launch_bounds__(64) void k_adj_dens1(KParams kp, Parts p,
-                                                  const int32_t* __restrict__ nl_idx,
-                                                  const int32_t* __restrict__ nl_len,
-                                                  double* __restrict__ raw, int64_t ns,
-                                                  double2* __restrict__ ab) {
-  const int lane = threadIdx.x;
-  const int slot = lane / LPI, sub = lane % LPI;
-  constexpr int CS = kWave / LPI;
-  const int nch = (kp.n + CS - 1) / CS;
-  const ChunkRange cr = xcd_chunks(nch);
-  const double C = kp.knorm, S = kp.support;
-  for (int ch = cr.beg; ch < cr.end; ch += cr.step) {
-    const int first = ch * CS, count = min(CS, kp.n - first);
-    const bool act = slot < count;
-    const int k = first + (act ? slot : 0);
-    const double xk = p.x[k], yk = p.y[k], zk = p.z[k], hk = p.h[k];
-    const double hinv = 1.0 / hk, sr = S * hk, sr2 = sr * sr;
-    const int len = act ? min(nl_len[k], kp.nl_cap) : 0;
-    const int32_t* __restrict__ row = nl_idx + (int64_t)k * kp.nl_cap;
-    double s1 = 0.0, s2 = 0.0;
-    for (int t = sub; t < len; t += LPI) {
-      const int j = row[t];
-      const double dx = afold(xk - p.x[j], kp.len[0], kp.half[0], kp.periodic[0]);
-      const double dy = afold(yk - p.y[j], kp.len[1], kp.half[1], kp.periodic[1]);
-      const double dz = afold(zk - p.z[j], kp.len[2], kp.half[2], kp.periodic[2]);
-      const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-      if (!(r2 < sr2)) continue;
-      const double q = sqrt(r2) * hinv;
-      double f, d1, d2;
-      kern3<double>(kp.kernel, q, f, d1, d2);
-      const double mj = p.m[j];
-      s1 += mj * (3.0 * f + q * d1);
-      s2 += mj * ((12.0 * f + 8.0 * q * d1) + q * q * d2);
-    }
-    s1 = seg_sum_d<LPI>(s1);
-    s2 = seg_sum_d<LPI>(s2);
-    if (act && sub == 0) {
-      const double h4 = C * hinv * hinv * hinv * hinv;
-      const double S1 = -s1 * h4, S2 = s2 * h4 * hinv;
-      const double rho = p.rho[k], om = p.omega[k], P = p.P[k], u = p.u[k], c = p.cs[k];
-      const double m = p.m[k];
-      const double hb0 = raw[6 * ns + k], gb = raw[7 * ns + k], kb = raw[8 * ns + k];
-      const double cb = raw[9 * ns + k], pb = raw[10 * ns + k], rb = raw[11 * ns + k];
-      const double ub = raw[12 * ns + k];
-      const double r2o = rho * rho * om;
-      const double Ptot = pb + gb / r2o;
-      double rtot = rb - 2.0 * gb * P / (r2o * rho) - kb / (om * rho * rho);
-      const double Ob = -gb * P / (r2o * om) - kb / (om * om * rho);
-      rtot += Ptot * kp.gm1 * u;
-      const double utot = ub + Ptot * kp.gm1 * rho + (c > 0.0 ? cb * kp.gamma * kp.gm1 / (2.0 * c) : 0.0);
-      const double S1b = Ob * hk / (3.0 * rho);
-      rtot -= Ob * hk * S1 / (3.0 * rho * rho);
-      const double hb = hb0 + Ob * S1 / (3.0 * rho);
-      const double S0b = rtot;
-      const double H = hb + S0b * S1 + S1b * S2;
-      const double hr = kp.hfact * hinv;
-      const double rho_h = m * hr * hr * hr;
-      const double fp = S1 + 3.0 * rho_h * hinv;
-      const double lam = -H / fp;
-      ab[k] = make_double2(S0b + lam, S1b);
-      raw[12 * ns + k] = utot;
-    }
-  }
-}
+// beta_k dS1_k/dx summed over k -- runs at the end of k_adj_force, whose
+// pair loop visits every density pair of k (the force set holds it).
+// raw rows: xb yb zb vxb vyb vzb and the evaluation's final u-cotangent.
 
 // ---------------------------------------------------------------------------
-// Density adjoint, pass 2: for particle k over its row (j != k),
+// Density adjoint, second half: for particle k over its row (j != k),
 //   xbar_k += m_j [alpha_k F(r, h_k) + beta_k F_h(r, h_k)] e    (r < S h_k)
 //           + m_k [alpha_j F(r, h_j) + beta_j F_h(r, h_j)] e    (r < S h_j)
 // with e = (x_k - x_j)/r, F = dW/dr, F_h = d2W/dr dh; then the evaluation's
@@ -409,13 +386,17 @@ __global__ __launch_bounds__(64) void k_adj_dens1(KParams kp, Parts p,
 //     X0 = Xt, V0 = dt Xt + Vp, U0 = Up,
 //     A0 = -dt/2 V1 + dt^2/2 Xt + dt Vp,  D0 = -dt/2 U1 + dt Up.
 // ---------------------------------------------------------------------------
-template <int LPI>
+template <bool MIXED, int LPI>
 __global__ __launch_bounds__(64) void k_adj_dens2(KParams kp, Parts p,
+                                                  const void* __restrict__ frec_in,
                                                   const int32_t* __restrict__ nl_idx,
                                                   const int32_t* __restrict__ nl_len,
                                                   const double* __restrict__ raw, int64_t ns,
                                                   const double2* __restrict__ ab, Cot g,
                                                   double dt, int step_mode) {
+  using Rec = typename ARecOf<MIXED>::T;
+  using R = typename std::conditional<MIXED, float, double>::type;
+  const Rec* __restrict__ rec = reinterpret_cast<const Rec*>(frec_in);
   const int lane = threadIdx.x;
   const int slot = lane / LPI, sub = lane % LPI;
   constexpr int CS = kWave / LPI;
@@ -426,48 +407,54 @@ __global__ __launch_bounds__(64) void k_adj_dens2(KParams kp, Parts p,
     const int first = ch * CS, count = min(CS, kp.n - first);
     const bool act = slot < count;
     const int k = first + (act ? slot : 0);
-    const double xk = p.x[k], yk = p.y[k], zk = p.z[k], hk = p.h[k], mk = p.m[k];
-    const double hinvk = 1.0 / hk, srk = S * hk, srk2 = srk * srk;
+    const double xk = p.x[k], yk = p.y[k], zk = p.z[k];
+    const R hk = (R)p.h[k], mk = (R)p.m[k], Cr = (R)C;
+    const R hinvk = R(1) / hk, srk = (R)S * hk, srk2 = srk * srk;
     const double2 abk = ab[k];
+    const R ak = (R)abk.x, bk = (R)abk.y;
     const int len = act ? min(nl_len[k], kp.nl_cap) : 0;
     const int32_t* __restrict__ row = nl_idx + (int64_t)k * kp.nl_cap;
-    double bx = 0.0, by = 0.0, bz = 0.0;
+    R sx = 0, sy = 0, sz = 0;
+    // row index one iteration ahead
+    int jn = (sub < len) ? row[sub] : k;
     for (int t = sub; t < len; t += LPI) {
-      const int j = row[t];
+      const int j = jn;
+      jn = (t + LPI < len) ? row[t + LPI] : k;
       if (j == k) continue;
-      const double dx = afold(xk - p.x[j], kp.len[0], kp.half[0], kp.periodic[0]);
-      const double dy = afold(yk - p.y[j], kp.len[1], kp.half[1], kp.periodic[1]);
-      const double dz = afold(zk - p.z[j], kp.len[2], kp.half[2], kp.periodic[2]);
-      const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-      const double hj = p.h[j];
-      const double srj = S * hj;
+      const Rec& rj = rec[j];
+      const R dx = (R)afold(xk - rj.x, kp.len[0], kp.half[0], kp.periodic[0]);
+      const R dy = (R)afold(yk - rj.y, kp.len[1], kp.half[1], kp.periodic[1]);
+      const R dz = (R)afold(zk - rj.z, kp.len[2], kp.half[2], kp.periodic[2]);
+      const R r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+      const R hj = (R)rj.h;
+      const R srj = (R)S * hj;
       const bool ink = r2 < srk2, inj = r2 < srj * srj;
       if (!(ink || inj)) continue;
-      const double r = sqrt(r2);
-      double coef = 0.0;
+      const R r = sqrt(r2);
+      R coef = 0;
       if (ink) {
-        double F, Fr, Fh;
-        kern_F3<double>(kp.kernel, C, r, hinvk, F, Fr, Fh);
-        coef += p.m[j] * (abk.x * F + abk.y * Fh);
+        R F, Fr, Fh;
+        kern_F3<R>(kp.kernel, Cr, r, hinvk, F, Fr, Fh);
+        coef += (R)rj.m * (ak * F + bk * Fh);
       }
       if (inj) {
         const double2 abj = ab[j];
-        double F, Fr, Fh;
-        kern_F3<double>(kp.kernel, C, r, 1.0 / hj, F, Fr, Fh);
-        coef += mk * (abj.x * F + abj.y * Fh);
+        R F, Fr, Fh;
+        kern_F3<R>(kp.kernel, Cr, r, R(1) / hj, F, Fr, Fh);
+        coef += mk * ((R)abj.x * F + (R)abj.y * Fh);
       }
       coef /= r;
-      bx += coef * dx;
-      by += coef * dy;
-      bz += coef * dz;
+      sx += coef * dx;
+      sy += coef * dy;
+      sz += coef * dz;
     }
-    bx = seg_sum_d<LPI>(bx);
-    by = seg_sum_d<LPI>(by);
-    bz = seg_sum_d<LPI>(bz);
+    const double bx = seg_sum_d<LPI>((double)sx);
+    const double by = seg_sum_d<LPI>((double)sy);
+    const double bz = seg_sum_d<LPI>((double)sz);
     if (act && sub == 0) {
       const double ex = bx + raw[k], ey = by + raw[ns + k], ez = bz + raw[2 * ns + k];
       const double evx = raw[3 * ns + k], evy = raw[4 * ns + k], evz = raw[5 * ns + k];
-      const double eu = raw[12 * ns + k];
+      const double eu = raw[6 * ns + k];
       const int64_t o = p.id[k];
       if ((uint64_t)o >= (uint64_t)kp.n) {
         // reported by the seed kernel
@@ -543,6 +530,9 @@ hipError_t launch_adjoint(sph_ctx* c, const sph_particles* s, const sph_cotangen
   const int64_t ns = c->n_max;
   const bool mixed = c->kp.precision == SPH_PREC_MIXED;
   const dim3 grid(c->walk_blocks), block(64);
+  // the density pass has little arithmetic per gathered neighbour: more
+  // wavefronts in flight hide the gathers' latency
+  const dim3 dgrid(4 * c->walk_blocks);
   constexpr int LPI = 8;
   if (part == 0) {
     const int sblocks = (int)std::min<int64_t>((n + 255) / 256, 8 * (int64_t)c->n_cu);
@@ -555,17 +545,18 @@ hipError_t launch_adjoint(sph_ctx* c, const sph_particles* s, const sph_cotangen
   } else if (part == 1) {
     if (mixed)
       hipLaunchKernelGGL((k_adj_force<true, LPI>), grid, block, 0, c->stream, c->kp, p, c->frec,
-                         c->adj_abar, c->nl_idx, c->nl_len, c->adj_raw, ns);
+                         c->adj_abar, c->nl_idx, c->nl_len, c->adj_raw, ns, c->adj_ab);
     else
       hipLaunchKernelGGL((k_adj_force<false, LPI>), grid, block, 0, c->stream, c->kp, p, c->frec,
-                         c->adj_abar, c->nl_idx, c->nl_len, c->adj_raw, ns);
+                         c->adj_abar, c->nl_idx, c->nl_len, c->adj_raw, ns, c->adj_ab);
+  } else if (mixed) {
+    hipLaunchKernelGGL((k_adj_dens2<true, LPI>), dgrid, block, 0, c->stream, c->kp, p, c->frec,
+                       c->nl_idx, c->nl_len, c->adj_raw, ns, c->adj_ab, g, dt,
+                       step_mode ? 1 : 0);
   } else {
-    hipLaunchKernelGGL((k_adj_dens1<LPI>), grid, block, 0, c->stream, c->kp, p, c->nl_idx,
-                       c->nl_len, c->adj_raw, ns, c->adj_ab);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_adj_dens2<LPI>), grid, block, 0, c->stream, c->kp, p, c->nl_idx,
-                       c->nl_len, c->adj_raw, ns, c->adj_ab, g, dt, step_mode ? 1 : 0);
+    hipLaunchKernelGGL((k_adj_dens2<false, LPI>), dgrid, block, 0, c->stream, c->kp, p, c->frec,
+                       c->nl_idx, c->nl_len, c->adj_raw, ns, c->adj_ab, g, dt,
+                       step_mode ? 1 : 0);
   }
   return hipGetLastError();
 }

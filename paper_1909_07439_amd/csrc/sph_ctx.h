@@ -93,7 +93,7 @@ struct sph_ctx {
   double* a1 = nullptr;        // 4 * n_max: new ax, ay, az, dudt inside sph_step
   // adjoint workspace (allocated by the first adjoint call)
   void* adj_abar = nullptr;    // cotangents of a, du/dt in key order (double4 or float4)
-  double* adj_raw = nullptr;   // 13 * n_max: per-particle cotangents of the force adjoint
+  double* adj_raw = nullptr;   // 7 * n_max: cotangents of x, v and u from the force adjoint
   double2* adj_ab = nullptr;   // alpha, beta of the density adjoint
   int32_t* nb_cnt = nullptr;   // neighbour-export counts
   int64_t* nb_off = nullptr;   // neighbour-export offsets (device)

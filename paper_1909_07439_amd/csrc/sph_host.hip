@@ -490,7 +490,7 @@ static sph_status adj_check(sph_ctx* c, const sph_particles* p, const sph_cotang
   if (!c->adj_raw) {
     const int64_t N = c->n_max;
     hipError_t e = hipMalloc(&c->adj_abar, 32 * (size_t)N);
-    if (e == hipSuccess) e = hipMalloc((void**)&c->adj_raw, 13 * sizeof(double) * (size_t)N);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->adj_raw, 7 * sizeof(double) * (size_t)N);
     if (e == hipSuccess) e = hipMalloc((void**)&c->adj_ab, sizeof(double2) * (size_t)N);
     if (e != hipSuccess) {
       (void)hipFree(c->adj_abar);
