@@ -53,7 +53,8 @@ struct sph_ctx {
   // sort
   uint64_t* keys[2] = {nullptr, nullptr};
   uint32_t* vals[2] = {nullptr, nullptr};
-  uint32_t* radix_cnt = nullptr;  // 256 * blocks
+  uint32_t* radix_cnt = nullptr;  // look-back status (8 passes x 256 x blocks), histograms, tickets
+  int64_t n_max_sort_blocks = 0;
   uint32_t* scan_part = nullptr;  // block partials of the scans
   uint32_t* scan_total = nullptr; // scratch totals (several slots)
   // permute

@@ -112,6 +112,7 @@ sph_status status_of_err(sph_ctx* c, uint32_t e) {
   if (e & kErrFrontierForce) s += " walk frontier capacity exceeded (force);";
   if (e & kErrPairs) s += " pair list capacity exceeded;";
   if (e & kErrIds) s += " particle id outside [0, n) in the adjoint;";
+  if (e & kErrSort) s += " radix-sort look-back did not complete;";
   c->err = s;
   if (e & kErrIds) return SPH_E_ARG;
   if (e & kErrNonFinite) return SPH_E_NONFINITE;
@@ -243,7 +244,8 @@ sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ct
   ALLOC(c->keys[1], N);
   ALLOC(c->vals[0], N);
   ALLOC(c->vals[1], N);
-  ALLOC(c->radix_cnt, 256 * nblk_sort);
+  c->n_max_sort_blocks = nblk_sort;
+  ALLOC(c->radix_cnt, 8 * 256 * nblk_sort + 8 * 256 + 64);
   ALLOC(c->scan_part, scan_max / sph::kScanTile + 16);
   ALLOC(c->scan_total, 16);
   ALLOC(c->gtmp, (int64_t)sph::kMaxFields * N);

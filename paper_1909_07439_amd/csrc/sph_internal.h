@@ -24,6 +24,7 @@ enum : uint32_t {
   kErrLeaves = 64u,
   kErrFrontierForce = 128u,  // walk frontier capacity in the force pass
   kErrIds = 256u,            // a particle id outside [0, n) (adjoint cotangent index)
+  kErrSort = 512u,           // a radix-sort look-back wait ran out (should not happen)
 };
 
 // Device-resident scalars of one context.

@@ -310,61 +310,154 @@ __device__ __forceinline__ uint64_t match_digit8(uint32_t d, uint64_t active) {
   return m;
 }
 
-__global__ __launch_bounds__(256) void k_radix_hist(const uint64_t* __restrict__ keys, int n,
-                                                     int shift, uint32_t* __restrict__ cnt,
-                                                     int nblk) {
-  __shared__ uint32_t hist[256];
-  hist[threadIdx.x] = 0;
-  __syncthreads();
-  const int base = blockIdx.x * kSortTile;
-#pragma unroll
-  for (int k = 0; k < kSortTile / 256; ++k) {
-    const int i = base + k * 256 + threadIdx.x;
-    const bool valid = i < n;
-    const uint32_t d = valid ? (uint32_t)((keys[i] >> shift) & 255ull) : 0u;
-    const uint64_t act = ballot64(valid);
-    const uint64_t m = match_digit8(d, act);
-    if (valid && (m & lanemask_lt()) == 0) atomicAdd(&hist[d], (uint32_t)popc64(m));
+// Wave-aggregated increment of an LDS digit counter: when every active lane
+// of the wavefront holds the same digit (the high digits of a curve-ordered
+// tile) one lane adds the whole count.
+__device__ __forceinline__ void lds_count_digit(uint32_t* cnt, uint32_t d, bool valid) {
+  const uint64_t act = ballot64(valid);
+  if (act == 0ull) return;
+  const int lead = __builtin_ctzll(act);
+  const uint32_t d0 = (uint32_t)__shfl((int)d, lead, kWave);
+  const uint64_t same = ballot64(valid && d == d0);
+  if (same == act) {
+    if (lane_id() == lead) atomicAdd(&cnt[d0], (uint32_t)popc64(act));
+  } else if (valid) {
+    atomicAdd(&cnt[d], 1u);
   }
-  __syncthreads();
-  cnt[threadIdx.x * nblk + blockIdx.x] = hist[threadIdx.x];
 }
 
-__global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t* __restrict__ kin,
-                                                        const uint32_t* __restrict__ vin,
-                                                        uint64_t* __restrict__ kout,
-                                                        uint32_t* __restrict__ vout, int n,
-                                                        int shift,
-                                                        const uint32_t* __restrict__ off,
-                                                        int nblk, int fused) {
+// One-sweep radix sort.  k_radix_prep counts the digits of all eight passes
+// in one read of the keys (global histograms) and clears the look-back
+// status of every pass; k_radix_pass then sorts one 8-bit digit per launch:
+// each block takes the next tile (an atomic ticket, so every earlier tile
+// belongs to a block that already runs), publishes its digit counts, and
+// looks back over the earlier tiles' published counts or inclusive prefixes
+// for its exclusive prefix (decoupled look-back), then scatters stably.
+// Status words: flag in the top two bits (1 count only, 2 inclusive prefix),
+// the count in the low 30 (n < 2^30).  A word carries nothing but itself, so
+// relaxed device-scope atomics suffice (no acquire/release cache maintenance).
+constexpr uint32_t kStAgg = 1u << 30, kStPre = 2u << 30, kStMask = (1u << 30) - 1u;
+constexpr int kLookbackSpin = 1 << 22;  // bounded wait; the predecessors always publish
+constexpr int kLookW = 16;               // earlier tiles read per look-back round
+
+__global__ void k_radix_init(uint32_t* __restrict__ ghist, uint32_t* __restrict__ tickets) {
+  for (int k = threadIdx.x; k < 8 * 256; k += blockDim.x) ghist[k] = 0u;
+  if (threadIdx.x < 8) tickets[threadIdx.x] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_radix_prep(const uint64_t* __restrict__ keys, int n,
+                                                     int nblk, uint32_t* __restrict__ status,
+                                                     uint32_t* __restrict__ ghist) {
+  __shared__ uint32_t h[8][256];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int p = 0; p < 8; ++p) h[p][tid] = 0u;
+  __syncthreads();
+  for (int t = blockIdx.x; t < nblk; t += gridDim.x) {
+#pragma unroll
+    for (int p = 0; p < 8; ++p) status[((int64_t)p * nblk + t) * 256 + tid] = 0u;
+    const int base = t * kSortTile;
+#pragma unroll
+    for (int k = 0; k < kSortTile / 256; ++k) {
+      const int i = base + k * 256 + tid;
+      const bool valid = i < n;
+      const uint64_t key = valid ? keys[i] : 0ull;
+#pragma unroll
+      for (int p = 0; p < 8; ++p) lds_count_digit(h[p], (uint32_t)((key >> (8 * p)) & 255ull), valid);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < 8; ++p)
+    if (h[p][tid]) atomicAdd(&ghist[p * 256 + tid], h[p][tid]);
+}
+
+__global__ __launch_bounds__(256) void k_radix_pass(const uint64_t* __restrict__ kin,
+                                                     const uint32_t* __restrict__ vin,
+                                                     uint64_t* __restrict__ kout,
+                                                     uint32_t* __restrict__ vout, int n,
+                                                     int pass, int nblk,
+                                                     uint32_t* __restrict__ status,
+                                                     const uint32_t* __restrict__ ghist,
+                                                     uint32_t* __restrict__ tickets,
+                                                     uint32_t* __restrict__ err) {
+  constexpr int PER = kSortTile / 256;
+  __shared__ uint32_t cnt[256];
   __shared__ uint32_t run[256];
   __shared__ uint32_t wc[4][256];
   __shared__ uint32_t lds4[4];
+  __shared__ int s_tile;
   const int tid = threadIdx.x, w = tid >> 6;
-  if (fused) {
-    // `off` holds the raw per-block digit counts: this block's start for
-    // digit d = (all keys with a smaller digit) + (digit d in earlier blocks)
-    uint32_t tot = 0, pre = 0;
-    const uint32_t* row = off + (int64_t)tid * nblk;
-    for (int b = 0; b < nblk; ++b) {
-      const uint32_t v = row[b];
-      tot += v;
-      pre += (b < (int)blockIdx.x) ? v : 0u;
-    }
-    uint32_t all;
-    run[tid] = block256_excl_scan(tot, lds4, &all) + pre;
-  } else {
-    run[tid] = off[tid * nblk + blockIdx.x];
-  }
-  wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0;
+  const int shift = 8 * pass;
+  cnt[tid] = 0u;
+  if (tid == 0) s_tile = (int)atomicAdd(&tickets[pass], 1u);
   __syncthreads();
-  const int base = blockIdx.x * kSortTile;
-  for (int k = 0; k < kSortTile / 256; ++k) {
+  const int tile = s_tile;
+  const int base = tile * kSortTile;
+  uint64_t key[PER];
+  uint32_t val[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = base + k * 256 + tid;
+    key[k] = i < n ? kin[i] : 0ull;
+    val[k] = i < n ? vin[i] : 0u;
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    lds_count_digit(cnt, (uint32_t)((key[k] >> shift) & 255ull), base + k * 256 + tid < n);
+  __syncthreads();
+  // publish this tile's counts, then the exclusive prefix over earlier tiles
+  uint32_t* st = status + (int64_t)pass * nblk * 256;
+  const uint32_t mine = cnt[tid];
+  uint32_t excl = 0u;
+  if (tile == 0) {
+    __hip_atomic_store(&st[tid], kStPre | mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    __hip_atomic_store(&st[(int64_t)tile * 256 + tid], kStAgg | mine, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    // a window of kLookW earlier tiles per round: their loads are in flight
+    // together, so a long chain of published counts costs one latency per
+    // window rather than one per tile
+    int t = tile - 1, spins = 0;
+    while (t >= 0) {
+      uint32_t v[kLookW];
+#pragma unroll
+      for (int q = 0; q < kLookW; ++q)
+        v[q] = (t - q >= 0) ? __hip_atomic_load(&st[(int64_t)(t - q) * 256 + tid], __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT)
+                            : kStPre;  // before tile 0: prefix 0
+      int used = 0;
+      bool done = false;
+#pragma unroll
+      for (int q = 0; q < kLookW; ++q) {
+        if (done || used < q) continue;  // stopped at an earlier entry
+        const uint32_t f = v[q] & ~kStMask;
+        if (f == 0u) continue;  // not published yet: poll again from here
+        excl += v[q] & kStMask;
+        used = q + 1;
+        done = f == kStPre;
+      }
+      if (done) break;
+      t -= used;
+      if (used == 0 && ++spins > kLookbackSpin) {
+        atomicOr(err, kErrSort);
+        break;
+      }
+    }
+    __hip_atomic_store(&st[(int64_t)tile * 256 + tid], kStPre | (excl + mine), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+  // start of every digit: keys with a smaller digit anywhere + this digit in earlier tiles
+  uint32_t all;
+  const uint32_t gofs = block256_excl_scan(ghist[pass * 256 + tid], lds4, &all);
+  run[tid] = gofs + excl;
+  wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
     const int i = base + k * 256 + tid;
     const bool valid = i < n;
-    const uint64_t key = valid ? kin[i] : 0ull;
-    const uint32_t val = valid ? vin[i] : 0u;
-    const uint32_t d = (uint32_t)((key >> shift) & 255ull);
+    const uint32_t d = (uint32_t)((key[k] >> shift) & 255ull);
     const uint64_t act = ballot64(valid);
     const uint64_t m = match_digit8(d, act);
     const uint32_t rank = (uint32_t)popc64(m & lanemask_lt());
@@ -373,12 +466,12 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t* __restric
     if (valid) {
       uint32_t pos = run[d] + rank;
       for (int q = 0; q < w; ++q) pos += wc[q][d];
-      kout[pos] = key;
-      vout[pos] = val;
+      kout[pos] = key[k];
+      vout[pos] = val[k];
     }
     __syncthreads();
     run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
-    wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0;
+    wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0u;
     __syncthreads();
   }
 }
@@ -2743,19 +2836,19 @@ hipError_t launch_predict_keys(sph_ctx* c, const sph_particles* s, bool predict,
 hipError_t launch_sort(sph_ctx* c) {
   const int n = c->n;
   const int nblk = (n + kSortTile - 1) / kSortTile;
+  const int64_t nst = (int64_t)c->n_max_sort_blocks * 8 * 256;
+  uint32_t* status = c->radix_cnt;
+  uint32_t* ghist = c->radix_cnt + nst;
+  uint32_t* tickets = ghist + 8 * 256;
+  hipLaunchKernelGGL(k_radix_init, dim3(1), dim3(256), 0, c->stream, ghist, tickets);
+  const int pblocks = std::min(nblk, 4 * c->n_cu);
+  hipLaunchKernelGGL(k_radix_prep, dim3(pblocks), dim3(256), 0, c->stream, c->keys[0], n, nblk,
+                     status, ghist);
   for (int pass = 0; pass < 8; ++pass) {
-    const int shift = 8 * pass;
     const int src = pass & 1, dst = src ^ 1;
-    hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(256), 0, c->stream, c->keys[src], n, shift,
-                       c->radix_cnt, nblk);
-    const int fused = 0;  // measured: the separate scan is faster even for few blocks
-    if (!fused) {
-      hipError_t e = scan_u32(c, c->radix_cnt, (int64_t)256 * nblk, c->scan_total, nullptr);
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(256), 0, c->stream, c->keys[src],
-                       c->vals[src], c->keys[dst], c->vals[dst], n, shift, c->radix_cnt, nblk,
-                       fused);
+    hipLaunchKernelGGL(k_radix_pass, dim3(nblk), dim3(256), 0, c->stream, c->keys[src],
+                       c->vals[src], c->keys[dst], c->vals[dst], n, pass, nblk, status, ghist,
+                       tickets, &c->ds->err);
   }
   return hipGetLastError();  // 8 passes: the result is back in buffer 0
 }
