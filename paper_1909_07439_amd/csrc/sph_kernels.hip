@@ -2488,6 +2488,10 @@ void k_force_lists(KParams kp, Parts p,
       const float vxi = ri.vx, vyi = ri.vy, vzi = ri.vz, hif = (float)hi;
       const float hinvi = ri.hinv, h4i = ri.hinv4pi, gi = ri.g, ki = ri.k, ci = ri.c;
       const float Pi = ri.P, rhoi = ri.rho, ui = ri.u;
+      // per-lane sums in FP32 (a lane takes one in LPI of the row's pairs),
+      // combined across the slot's lanes in FP64 below
+      float fax = 0.f, fay = 0.f, faz = 0.f, fdu = 0.f, fvmax = 0.f;
+      uint32_t npr = 0;
       auto pair = [&](const Rec& rj) {
         const float dx = (float)fold(xi - rj.x, kp.len[0], kp.half[0], kp.periodic[0]);
         const float dy = (float)fold(yi - rj.y, kp.len[1], kp.half[1], kp.periodic[1]);
@@ -2495,7 +2499,7 @@ void k_force_lists(KParams kp, Parts p,
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
         const float sr = (float)kp.support * fmaxf(hif, rj.h);
         if (!(r2 < sr * sr * 1.00001f)) return;
-        ++pairs;
+        ++npr;
         const float rinv = __builtin_amdgcn_rsqf(r2);
         const float r = r2 * rinv;
         const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
@@ -2509,17 +2513,17 @@ void k_force_lists(KParams kp, Parts p,
         const float ti = app ? fmaf(-0.5f * vsi * w, ki, gi) : gi;
         const float tj = app ? fmaf(-0.5f * vsj * w, rj.k, rj.g) : rj.g;
         const float pa = rj.m * fmaf(ti, Fi, tj * Fj);
-        ax -= (double)(pa * ex);
-        ay -= (double)(pa * ey);
-        az -= (double)(pa * ez);
+        fax = fmaf(-pa, ex, fax);
+        fay = fmaf(-pa, ey, fay);
+        faz = fmaf(-pa, ez, faz);
         const float mwF = rj.m * w * Fi;
         float e = gi * mwF;
         if (app) e = fmaf(-0.5f * ki * vsi * w, mwF, e);
         const float dP = fabsf(Pi - rj.P);
         const float vu = fast_sqrt(dP * fast_rcp(0.5f * (rhoi + rj.rho)));
         e = fmaf(rj.m * au * vu * (ui - rj.u), 0.5f * fmaf(Fi, ki, Fj * rj.k), e);
-        du += (double)e;
-        vmax = fmax(vmax, (double)vsi);
+        fdu += e;
+        fvmax = fmaxf(fvmax, vsi);
       };
       // row indices one iteration ahead, so that each iteration waits for
       // one gather of the two records only
@@ -2537,6 +2541,12 @@ void k_force_lists(KParams kp, Parts p,
         j1 = jn1;
         j2 = jn2;
       }
+      ax = fax;
+      ay = fay;
+      az = faz;
+      du = fdu;
+      vmax = fvmax;
+      pairs += npr;
     } else {
       const double al = kp.alpha, be = kp.beta, au = kp.alpha_u;
       const double vxi = ri.vx, vyi = ri.vy, vzi = ri.vz;
