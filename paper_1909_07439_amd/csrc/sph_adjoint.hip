@@ -34,14 +34,12 @@ namespace sph {
 
 namespace {
 
+// Nearest periodic image of a separation d (|d| < 1.5 len), without branches.
 __device__ __forceinline__ double afold(double d, double len, double half, int periodic) {
-  if (periodic) {
-    if (d > half)
-      d -= len;
-    else if (d < -half)
-      d += len;
-  }
-  return d;
+  const double lp = periodic ? len : 0.0;
+  double t = d > half ? d - lp : d;
+  t = d < -half ? d + lp : t;
+  return t;
 }
 
 template <typename R>

@@ -918,14 +918,14 @@ constexpr int kTile = 256;  // candidates staged in LDS at a time
 constexpr int kSG = 8;      // groups sharing one super-group walk
 constexpr int kSLCap = 256; // leaves a super-group walk may collect
 
+// Nearest periodic image of a separation d (|d| < 1.5 len for positions in
+// the box).  Branch-free: the two selects compile to conditional moves, so a
+// wavefront does not split over the sign of d.
 __device__ __forceinline__ double fold(double d, double len, double half, int periodic) {
-  if (periodic) {
-    if (d > half)
-      d -= len;
-    else if (d < -half)
-      d += len;
-  }
-  return d;
+  const double lp = periodic ? len : 0.0;
+  double t = d > half ? d - lp : d;
+  t = d < -half ? d + lp : t;
+  return t;
 }
 
 // Largest squared distance between a point of the group box and a point of
