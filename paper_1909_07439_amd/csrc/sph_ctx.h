@@ -59,6 +59,7 @@ struct sph_ctx {
   uint32_t* scan_total = nullptr; // scratch totals (several slots)
   // permute
   double* gtmp = nullptr;  // kMaxFields * n_max
+  double4* xyzm = nullptr; // packed x, y, z, m in key order (written by the permute)
   int64_t* gtmp_id = nullptr;
   // tree
   uint8_t* dlev = nullptr;

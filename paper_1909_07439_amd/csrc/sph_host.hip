@@ -250,6 +250,7 @@ sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ct
   ALLOC(c->scan_total, 16);
   ALLOC(c->gtmp, (int64_t)sph::kMaxFields * N);
   ALLOC(c->gtmp_id, N);
+  ALLOC(c->xyzm, N);
   ALLOC(c->dlev, N);
   ALLOC(c->lleaf, N);
   ALLOC(c->lgrp, N);
@@ -341,7 +342,7 @@ void sph_destroy(sph_ctx* c) {
                   c->nb_off,    c->red_part,    c->red_out,      c->ds,
                   c->leaf_pool, c->gl_off,      c->gl_cnt,       c->nl_idx,      c->nl_len,
                   c->gflag,     c->flag_list,   c->walk_spill,   c->grp_of,
-                  c->adj_abar,  c->adj_raw,     c->adj_ab};
+                  c->adj_abar,  c->adj_raw,     c->adj_ab,       c->xyzm};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->hs) (void)hipHostFree(c->hs);

@@ -483,6 +483,8 @@ struct FieldSet {
   double* f[kMaxFields];
   int64_t* id;
   int nf;
+  int im;           // index of m in f (x, y, z are f[0..2])
+  double4* xyzm;    // packed x, y, z, m in the new order (the density kernel's gathers)
 };
 
 __global__ __launch_bounds__(256) void k_gather(FieldSet fs, const uint32_t* __restrict__ perm,
@@ -502,6 +504,7 @@ __global__ __launch_bounds__(256) void k_copy_back(FieldSet fs, const double* __
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
     for (int f = 0; f < fs.nf; ++f) fs.f[f][k] = tmp[f * stride + k];
     if (fs.id) fs.id[k] = tmp_id[k];
+    fs.xyzm[k] = make_double4(tmp[k], tmp[stride + k], tmp[2 * stride + k], tmp[fs.im * stride + k]);
   }
 }
 
@@ -2222,6 +2225,7 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
                                                       int32_t* __restrict__ gflag,
                                                       int32_t* __restrict__ flag_list,
                                                       const int32_t* __restrict__ grp_of,
+                                                      const double4* __restrict__ xyzm,
                                                       void* __restrict__ frec_out,
                                                       DevState* __restrict__ ds) {
   using R = typename std::conditional<MIXED, float, double>::type;
@@ -2278,10 +2282,11 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
       double gx[4], gy[4], gz[4], gm[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        gx[q] = p.x[jj[q]];
-        gy[q] = p.y[jj[q]];
-        gz[q] = p.z[jj[q]];
-        gm[q] = p.m[jj[q]];
+        const double4 v = xyzm[jj[q]];
+        gx[q] = v.x;
+        gy[q] = v.y;
+        gz[q] = v.z;
+        gm[q] = v.w;
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -2869,11 +2874,14 @@ hipError_t launch_permute(sph_ctx* c, const sph_particles* s, bool outputs_too) 
   double* all[] = {s->x,  s->y,  s->z,    s->vx,  s->vy,   s->vz, s->m,  s->u,     s->h,
                    s->ax, s->ay, s->az,   s->dudt, s->rho, s->omega, s->P, s->cs, s->vsig_dt};
   const int n_in = 13;  // x..dudt are state; the rest are outputs
+  fs.im = -1;
   for (int k = 0; k < (int)(sizeof(all) / sizeof(all[0])); ++k) {
     if (!all[k]) continue;
     if (k >= n_in && !outputs_too) continue;
+    if (all[k] == s->m) fs.im = fs.nf;
     fs.f[fs.nf++] = all[k];
   }
+  fs.xyzm = c->xyzm;
   fs.id = s->id;
   const int nb = stream_blocks(c->n);
   hipLaunchKernelGGL(k_gather, dim3(nb), dim3(256), 0, c->stream, fs, c->vals[0], c->gtmp,
@@ -3009,7 +3017,8 @@ static void density_lists_dispatch(sph_ctx* c, const Parts& p) {
   SPH_LPI_SWITCH_LISTS(c->kp.n_group,
                        hipLaunchKernelGGL((k_density_lists<MIXED, LPI, CAP>), grid, block, 0,
                                           c->stream, c->kp, p, c->ginfo, c->nl_idx, c->nl_len,
-                                          c->gflag, c->flag_list, c->grp_of, c->frec, c->ds));
+                                          c->gflag, c->flag_list, c->grp_of, c->xyzm, c->frec,
+                                          c->ds));
 }
 
 hipError_t launch_density_lists(sph_ctx* c, const sph_particles* s) {
