@@ -2120,22 +2120,23 @@ __global__ __launch_bounds__(64) void k_lists(KParams kp, Parts p,
           cands += (unsigned long long)total * ((act && sub == 0) ? 1u : 0u);
           for_tiles<LPI, R>(L, nleaf, total, sub, p.x, p.y, p.z, p.h, T, G, kp,
                             [&](bool valid, int c) {
-            bool pred = false;
-            const int j = valid ? T.j[c] : -1;
-            if (valid && act) {
-              if constexpr (MIXED) {
-                const float dx = xr - T.x[c], dy = yr - T.y[c], dz = zr - T.z[c];
-                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                const float sr = (float)kp.support * fmaxf(hlf, marginf * T.a[c]);
-                pred = r2 < sr * sr * 1.00001f;
-              } else {
-                const double dx = fold(xi - T.x[c], kp.len[0], kp.half[0], kp.periodic[0]);
-                const double dy = fold(yi - T.y[c], kp.len[1], kp.half[1], kp.periodic[1]);
-                const double dz = fold(zi - T.z[c], kp.len[2], kp.half[2], kp.periodic[2]);
-                const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                const double sr = kp.support * fmax(hl, margin * T.a[c]);
-                pred = r2 < sr * sr;
-              }
+            // branch-free: lanes past the tile's end read entry 0 (always
+            // staged) and are masked out of the predicate
+            const int cc = valid ? c : 0;
+            const int j = T.j[cc];
+            bool pred;
+            if constexpr (MIXED) {
+              const float dx = xr - T.x[cc], dy = yr - T.y[cc], dz = zr - T.z[cc];
+              const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+              const float sr = (float)kp.support * fmaxf(hlf, marginf * T.a[cc]);
+              pred = valid && act && (r2 < sr * sr * 1.00001f);
+            } else {
+              const double dx = fold(xi - T.x[cc], kp.len[0], kp.half[0], kp.periodic[0]);
+              const double dy = fold(yi - T.y[cc], kp.len[1], kp.half[1], kp.periodic[1]);
+              const double dz = fold(zi - T.z[cc], kp.len[2], kp.half[2], kp.periodic[2]);
+              const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+              const double sr = kp.support * fmax(hl, margin * T.a[cc]);
+              pred = valid && act && (r2 < sr * sr);
             }
             const uint64_t b = ballot64(pred);
             const uint32_t seg = (uint32_t)((b >> (slot * LPI)) & ((LPI == 64) ? ~0ull : ((1ull << LPI) - 1ull)));
