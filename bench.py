@@ -51,8 +51,8 @@ LIST_FLOPS_PER_CANDIDATE = 14
 ADJ_FORCE_FLOPS_PER_PAIR = {0: 372, 1: 396, 2: 388}
 # Vector ALU peak of the 256 CUs at 2.4 GHz for non-packed FP32 (and FP64)
 # FMA: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz.  The published FP32
-# figure of 157.3 TFLOP/s needs packed FP32 instructions, which this build
-# does not emit.
+# figure of 157.3 TFLOP/s needs packed FP32 instructions, which the library
+# is compiled not to emit.
 ALU_PEAK_TFLOPS = 78.6
 PACKED_FP32_PEAK_TFLOPS = 157.3
 
@@ -295,7 +295,7 @@ def main():
                          "(scale for PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no "
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the library has no "
               "multi-GPU path.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
