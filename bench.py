@@ -265,10 +265,18 @@ def cpu_baseline(cfg, budget_s=12.0):
         oracle.evaluate(cfg, p)
         reps += 1
         t = time.perf_counter() - t0
-    return dict(value=cfg["n"] * reps / t, unit="particle-updates/s", cores=oracle.num_threads(),
-                kind="oracle",
-                sample=f"{reps} full FP64 evaluation(s) (tree, density iterated to the root, "
-                       f"force) of the {cfg['workload']} workload, N={cfg['n']}, {t:.1f} s")
+    cores = oracle.num_threads()
+    out = dict(value=cfg["n"] * reps / t, unit="particle-updates/s", cores=cores,
+               kind="oracle",
+               sample=f"{reps} full FP64 evaluation(s) (tree, density iterated to the root, "
+                      f"force) of the {cfg['workload']} workload, N={cfg['n']}, {t:.1f} s")
+    # one thread: a single evaluation
+    oracle.set_num_threads(1)
+    t1 = time.perf_counter()
+    oracle.evaluate(cfg, p)
+    out["value_1thread"] = cfg["n"] / (time.perf_counter() - t1)
+    oracle.set_num_threads(cores)
+    return out
 
 
 def main():

@@ -139,6 +139,8 @@ def _load():
         lib.orc_correct.argtypes = [ctypes.c_int64] + [_D] * 12 + [ctypes.c_double]
         lib.orc_reduce.argtypes = [ctypes.c_int64] + [_D] * 9 + [_D]
         lib.orc_num_threads.restype = ctypes.c_int
+        lib.orc_set_num_threads.argtypes = [ctypes.c_int]
+        lib.orc_set_num_threads.restype = None
         _lib = lib
         return lib
 
@@ -154,6 +156,11 @@ def _f64(a):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(k: int) -> None:
+    """Threads of the oracle's parallel loops from now on."""
+    _load().orc_set_num_threads(int(k))
 
 
 def kernel_m4(r, h):

@@ -1045,3 +1045,12 @@ int orc_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Threads of the following parallel loops (k <= 0: leave unchanged). */
+void orc_set_num_threads(int k) {
+#ifdef _OPENMP
+  if (k > 0) omp_set_num_threads(k);
+#else
+  (void)k;
+#endif
+}
