@@ -97,3 +97,59 @@ def test_several_steps_fp64_match_oracle():
         e = np.abs(g[k] - s[k]).max() / max(np.abs(s[k]).max(), 1e-300)
         say(f"  after 8 steps {k}: {e:.2e}")
         assert e < 1e-10, k
+
+
+def test_shock_tube_t02_window():
+    """t = 0.2 (the figure's time): the waves of the periodic mirror problem
+    have met the main shock (t = 0.1355) and the rarefaction heads have met
+    (t = 0.1936) near x = +-1/2; the window -0.24 < x < 0.13 is still the
+    single Riemann problem and is graded against it."""
+    cfg = inputs.sod()
+    g, e0, e1, steps = run_to(cfg, sph.SPH_PREC_MIXED, 0.2)
+    x = g["x"]
+    r, u, pr = riemann.sample(x / 0.2, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1), cfg["gamma"])
+    w = (x > -0.24) & (x < 0.13)
+    fan = (x > -0.22) & (x < -0.08)
+    errs = {k: float(np.abs(q[w] - ref[w]).mean()) for k, q, ref in
+            (("rho", g["rho"], r), ("v", g["vx"], u), ("P", g["P"], pr))}
+    fan_rho = float(np.abs(g["rho"][fan] - r[fan]).mean())
+    de = (e0[0] - e1[0]) / e0[0]
+    say(f"  steps {steps}, window L1 rho {errs['rho']:.4f} v {errs['v']:.4f} P {errs['P']:.4f}, "
+        f"fan rho {fan_rho:.4f}, dE {de:.2e}")
+    assert abs(de) < 5e-5
+    assert errs["rho"] < WINDOW_T02["rho"] and errs["v"] < WINDOW_T02["v"] and \
+        errs["P"] < WINDOW_T02["P"]
+    assert fan_rho < WINDOW_T02["fan_rho"]
+
+
+# measured (mixed, 479 steps): rho 0.0175, v 0.035, P 0.020, fan rho 0.017,
+# dE -9.5e-6; bounds with a margin
+WINDOW_T02 = {"rho": 0.03, "v": 0.06, "P": 0.035, "fan_rho": 0.03}
+
+
+@pytest.mark.parametrize("kernel", ["m4", "m6"])
+def test_shock_tube_error_with_resolution(kernel):
+    """L1 of rho over the unmirrored profile (|x| < 0.3) at t = 0.1 at
+    spacings 1/128, 1/256, 1/512 stays below 0.03 at every spacing.
+
+    The error is not asserted to fall monotonically: with an unsmoothed
+    contact in the initial lattice the start-up noise at the left star state
+    (printed) does not shrink with the spacing over this range, and measured
+    L1 goes 0.0132, 0.0157, 0.0121 (M4) and 0.0114, 0.0140, 0.0119 (M6).
+    The printed breakdown keeps that behaviour visible."""
+    out = []
+    for dxl in (1.0 / 128, 1.0 / 256, 1.0 / 512):
+        # the cross-section keeps the support of the right state below half the box
+        cfg = inputs.with_kernel(inputs.sod(dx_left=dxl, width=max(1.0 / 16, 32 * dxl)), kernel)
+        g, _, _, steps = run_to(cfg, sph.SPH_PREC_MIXED, 0.1)
+        x = g["x"]
+        r, u, pr = sod_exact_periodic(x, 0.1, cfg["gamma"])
+        m = np.abs(x) < 0.3
+        smooth = ((x > -0.11) & (x < -0.04)) | ((x > 0.10) & (x < 0.17))
+        star = (x > 0.0) & (x < 0.06)
+        out.append(float(np.abs(g["rho"][m] - r[m]).mean()))
+        say(f"  {kernel} dx_L = 1/{int(round(1 / dxl))}: N = {cfg['n']}, steps {steps}, "
+            f"L1 rho {out[-1]:.5f} (fan + plateau "
+            f"{float(np.abs(g['rho'][smooth] - r[smooth]).mean()):.5f}, left star "
+            f"{float(np.abs(g['rho'][star] - r[star]).mean()):.5f})")
+    assert max(out) < 0.03
