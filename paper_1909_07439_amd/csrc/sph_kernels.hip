@@ -2010,19 +2010,48 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
 // ============================================================================
 // Neighbour lists (Sect. 3.2).  k_lists: one wavefront per super-group of
 // kSG groups.  The super-group walk collects every leaf any of its groups can
-// need; each group culls that list against its own box and writes, for each
-// of its particles i, the indices j of every particle with
+// need; one pass over that list then tests each leaf against the box of every
+// group of the super-group (one bit per group), so a node is read once per
+// super-group.  Each group then loads the particles of its leaves, one
+// candidate per lane, and for each of its particles i in turn appends the
+// indices j of every candidate with
 //     r_ij < 2 max(hl_i, hl_j),   hl = h_margin * (h at the start),
-// into the fixed-capacity row i of nl_idx (self included).  As long as no h
-// grows past its hl, a row is a superset of the density neighbours (r < 2 h_i)
-// and of the force pairs (r < 2 max(h_i, h_j)); the density and force list
-// kernels apply the exact predicates.  A group with an overflowing row or a
-// failed walk is flagged (gflag = 1) and left to the walking kernels.  The
-// group of every particle is kept (grp_of) for the list kernels, which work
-// on chunks of consecutive particles instead of groups.
+// to the fixed-capacity row i of nl_idx (self included): one ballot and one
+// coalesced store per particle and 64 candidates, in candidate order.  As
+// long as no h grows past its hl, a row is a superset of the density
+// neighbours (r < 2 h_i) and of the force pairs (r < 2 max(h_i, h_j)); the
+// density and force list kernels apply the exact predicates.  A group with
+// an overflowing row or a failed walk is flagged (gflag = 1) and left to the
+// walking kernels.  The group of every particle is kept (grp_of) for the list
+// kernels, which work on chunks of consecutive particles instead of groups.
 // ============================================================================
+
+// The value a wave-uniform lane `l` holds, as a wave-uniform scalar.
+__device__ __forceinline__ float lane_val(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_val(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Squared search radius (support * x)^2 of the list predicate, with a
+// relative slack of 1e-5 in FP32.  Every step rounds monotonically, so the
+// value at max(a, b) is the larger of the values at a and at b: the pair test
+// compares r^2 with the larger of the particle's and the candidate's value.
+__device__ __forceinline__ float list_thr(float support, float x) {
+  const float s = support * x;
+  return s * s * 1.00001f;
+}
+__device__ __forceinline__ double list_thr(double support, double x) {
+  const double s = support * x;
+  return s * s;
+}
+
 template <bool MIXED, int LPI>
-__global__ __launch_bounds__(64) void k_lists(KParams kp, Parts p,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_lists(KParams kp, Parts p,
                                               const WalkNode* __restrict__ nodes,
                                               const GroupInfo* __restrict__ groups,
                                               int32_t* __restrict__ nl_idx,
@@ -2034,34 +2063,41 @@ __global__ __launch_bounds__(64) void k_lists(KParams kp, Parts p,
     DevState* __restrict__ ds) {
   int* __restrict__ spill = walk_spill + (int64_t)blockIdx.x * 2 * kSpill;
   using R = typename std::conditional<MIXED, float, double>::type;
-  constexpr int GS = kWave / LPI;
+  constexpr int GS = kWave / LPI;  // particles per group at most
+  constexpr int PER = kTile / kWave;
+  static_assert(GS * kSG <= kWave, "one lane per particle of a super-group");
   __shared__ WalkLds L;
-  // the frontier is live only during the super-group walk, the candidate
-  // tile only during the group passes: they share their LDS
+  // the frontier is live only during walks, the leaf ranges of the
+  // super-group only after its walk; a group that walks on its own (the
+  // super-group's list overflowed) takes the node ids instead
   __shared__ union {
     int front[2][kFCap];
-    TileOf<R> tile;
+    struct {
+      int first[kSLCap];
+      int cnt[kSLCap];
+    } sl;
   } U;
-  __shared__ int s_sl[kSLCap];
-  TileOf<R>& T = U.tile;
+  __shared__ int s_sl[kSLCap];  // leaf node ids of the walk, then one bit per group
+  __shared__ double s_hm[kSG];  // largest hl of each group
   const int lane = threadIdx.x;
-  const int slot = lane / LPI, sub = lane % LPI;
   const int ng = ds->n_groups;
   const int nsg = (ng + kSG - 1) / kSG;
   const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, nloc = gridDim.x >> 3;
   const int chunk = (nsg + 7) >> 3;
   const int sbeg = xcd * chunk, send = min(sbeg + chunk, nsg);
   const double margin = kp.h_margin;
+  const R supr = (R)kp.support, marginr = (R)margin;
+  const int cap = kp.nl_cap;
   bool flagged = false;
   int nflag = 0;
   unsigned long long cands = 0;
   int walks = 0;
 
   for (int sg = sbeg + local; sg < send; sg += nloc) {
-    const int g0 = sg * kSG, g1 = min(g0 + kSG, ng);
+    const int g0 = sg * kSG, g1 = min(g0 + kSG, ng), ngs = g1 - g0;
     GroupInfo SG;
     {
-      const bool v = lane < g1 - g0;
+      const bool v = lane < ngs;
       GroupInfo Gk;
       if (v) Gk = groups[g0 + lane];
       for (int a = 0; a < 3; ++a) {
@@ -2073,6 +2109,18 @@ __global__ __launch_bounds__(64) void k_lists(KParams kp, Parts p,
       SG.hmax = wave_max_f64(v ? Gk.hmax : 0.0);
       SG.first = 0;
       SG.count = 0;
+    }
+    {
+      // largest hl of each group's particles: lane = group * GS + slot
+      const int gk = lane / GS, sl = lane % GS;
+      double hl = 0.0;
+      if (gk < ngs) {
+        const int f = groups[g0 + gk].first, cn = groups[g0 + gk].count;
+        if (sl < cn) hl = margin * p.h[f + sl];
+      }
+      hl = seg_max<GS>(hl);
+      if (sl == 0 && gk < kSG) s_hm[gk] = hl;
+      __syncthreads();
     }
     int nsl = 0;
     bool sok = true;
@@ -2091,90 +2139,183 @@ __global__ __launch_bounds__(64) void k_lists(KParams kp, Parts p,
         __syncthreads();
       };
       if (!group_walk(nodes, SG, kp, L, U.front, spill, sradius, sflush)) sok = false;
-      __syncthreads();  // the frontier's LDS becomes the tile
+      __syncthreads();  // the frontier's LDS becomes the leaf ranges
       ++walks;
     }
+    if (sok) {
+      // each leaf against every group's box, with that group's radius
+      for (int base = 0; base < nsl; base += kWave) {
+        const int k = base + lane;
+        if (k < nsl) {
+          const WalkNode nd = nodes[s_sl[k]];
+          int bits = 0;
+          for (int gk = 0; gk < ngs; ++gk) {
+            const double rg = kp.support * fmax(s_hm[gk], margin * (double)nd.hmax) * (1.0 + 4e-9);
+            if (box_gap2(nd, groups[g0 + gk], kp) < rg * rg) bits |= 1 << gk;
+          }
+          U.sl.first[k] = nd.first;
+          U.sl.cnt[k] = nd.count;
+          s_sl[k] = bits;
+        }
+      }
+      __syncthreads();
+    }
     for (int g = g0; g < g1; ++g) {
+      const int gk = g - g0;
       const GroupInfo G = groups[g];
-      // rows of the particles of G; true if G must go to the walking kernels
-      auto unit = [&](const GroupInfo& G) -> bool {
-        const bool act = slot < G.count;
-        const int i = G.first + (act ? slot : 0);
+      const int cnt = G.count;
+      const bool act = lane < cnt;
+      const int i = G.first + (act ? lane : 0);
+      // this lane's particle (lanes below cnt); the pair loop reads them as scalars
+      R xq, yq, zq;
+      {
         const double xi = p.x[i], yi = p.y[i], zi = p.z[i];
-        const double hl = margin * p.h[i];
-        float xr = 0.f, yr = 0.f, zr = 0.f;
         if constexpr (MIXED) {
-          xr = (float)fold(xi - G.c[0], kp.len[0], kp.half[0], kp.periodic[0]);
-          yr = (float)fold(yi - G.c[1], kp.len[1], kp.half[1], kp.periodic[1]);
-          zr = (float)fold(zi - G.c[2], kp.len[2], kp.half[2], kp.periodic[2]);
+          xq = (float)fold(xi - G.c[0], kp.len[0], kp.half[0], kp.periodic[0]);
+          yq = (float)fold(yi - G.c[1], kp.len[1], kp.half[1], kp.periodic[1]);
+          zq = (float)fold(zi - G.c[2], kp.len[2], kp.half[2], kp.periodic[2]);
+        } else {
+          xq = xi;
+          yq = yi;
+          zq = zi;
         }
-        const float hlf = (float)hl, marginf = (float)margin;
-        const double hm = wave_max_f64(act ? hl : 0.0);
-        int32_t* __restrict__ row = nl_idx + (int64_t)i * kp.nl_cap;
-        int npair = 0;
-        auto radius = [&](const WalkNode& nd) {
-          return kp.support * fmax(hm, margin * (double)nd.hmax) * (1.0 + 4e-9);
-        };
-        auto flush = [&](int nleaf) {
-          const int total = leaf_offsets(L, nleaf);
-          cands += (unsigned long long)total * ((act && sub == 0) ? 1u : 0u);
-          for_tiles<LPI, R>(L, nleaf, total, sub, p.x, p.y, p.z, p.h, T, G, kp,
-                            [&](bool valid, int c) {
-            // branch-free: lanes past the tile's end read entry 0 (always
-            // staged) and are masked out of the predicate
-            const int cc = valid ? c : 0;
-            const int j = T.j[cc];
-            bool pred;
-            if constexpr (MIXED) {
-              const float dx = xr - T.x[cc], dy = yr - T.y[cc], dz = zr - T.z[cc];
-              const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-              const float sr = (float)kp.support * fmaxf(hlf, marginf * T.a[cc]);
-              pred = valid && act && (r2 < sr * sr * 1.00001f);
-            } else {
-              const double dx = fold(xi - T.x[cc], kp.len[0], kp.half[0], kp.periodic[0]);
-              const double dy = fold(yi - T.y[cc], kp.len[1], kp.half[1], kp.periodic[1]);
-              const double dz = fold(zi - T.z[cc], kp.len[2], kp.half[2], kp.periodic[2]);
-              const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-              const double sr = kp.support * fmax(hl, margin * T.a[cc]);
-              pred = valid && act && (r2 < sr * sr);
-            }
-            const uint64_t b = ballot64(pred);
-            const uint32_t seg = (uint32_t)((b >> (slot * LPI)) & ((LPI == 64) ? ~0ull : ((1ull << LPI) - 1ull)));
-            const int pos = npair + __popc(seg & ((1u << sub) - 1u));
-            if (pred && pos < kp.nl_cap) row[pos] = j;
-            npair += __popc(seg);
-          });
-          __syncthreads();
-        };
-        // a super-group whose leaf list overflowed: each group walks for its
-        // own leaf list first (the frontier and the tile are never live at
-        // once); a group whose list overflows too is left to the walking kernels
-        bool gok = sok;
-        int ngl = nsl;
-        if (!sok) {
-          ngl = 0;
-          gok = true;
-          auto gflush = [&](int nleaf) {
-            if (ngl + nleaf <= kSLCap) {
-              for (int q = lane; q < nleaf; q += kWave) s_sl[ngl + q] = L.lnode[q];
-            } else {
-              gok = false;
-            }
-            ngl += nleaf;
-            __syncthreads();
-          };
-          if (!group_walk(nodes, G, kp, L, U.front, spill, radius, gflush)) gok = false;
-          __syncthreads();
-          ++walks;
-        }
-        if (gok) list_walk(nodes, s_sl, ngl, G, kp, L, radius, flush);
-        if (act && sub == 0) {
-          nl_len[i] = npair;
-          grp_of[i] = g;
-        }
-        return !gok || ballot64(act && npair > kp.nl_cap) != 0ull;
+      }
+      const R tq = list_thr(supr, (R)(margin * p.h[i]));
+      int np[GS];
+#pragma unroll
+      for (int s = 0; s < GS; ++s) np[s] = 0;
+      const double hm = s_hm[gk];
+      auto radius = [&](const WalkNode& nd) {
+        return kp.support * fmax(hm, margin * (double)nd.hmax) * (1.0 + 4e-9);
       };
-      const bool bad = unit(G);
+      auto flush = [&](int nleaf) {
+        const int total = leaf_offsets(L, nleaf);
+        if (lane == 0) cands += (unsigned long long)total * (unsigned)cnt;
+        for (int c0 = 0; c0 < total; c0 += kTile) {
+          const int cn = min(kTile, total - c0);
+          // resolve this lane's candidates, then issue all their loads
+          int jj[PER];
+#pragma unroll
+          for (int q = 0; q < PER; ++q) {
+            const int t = lane + q * kWave;
+            jj[q] = -1;
+            if (t < cn) {
+              const int c = c0 + t;
+              int lo = 0, hi = nleaf;
+              while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (L.loff[mid] <= c)
+                  lo = mid;
+                else
+                  hi = mid;
+              }
+              jj[q] = L.lfirst[lo] + (c - L.loff[lo]);
+            }
+          }
+          double vx[PER], vy[PER], vz[PER], vh[PER];
+#pragma unroll
+          for (int q = 0; q < PER; ++q) {
+            const int j = jj[q] >= 0 ? jj[q] : 0;
+            vx[q] = p.x[j];
+            vy[q] = p.y[j];
+            vz[q] = p.z[j];
+            vh[q] = p.h[j];
+          }
+#pragma unroll
+          for (int q = 0; q < PER; ++q) {
+            if (q * kWave >= cn) break;
+            R cx, cy, cz;
+            if constexpr (MIXED) {
+              cx = (float)fold(vx[q] - G.c[0], kp.len[0], kp.half[0], kp.periodic[0]);
+              cy = (float)fold(vy[q] - G.c[1], kp.len[1], kp.half[1], kp.periodic[1]);
+              cz = (float)fold(vz[q] - G.c[2], kp.len[2], kp.half[2], kp.periodic[2]);
+            } else {
+              cx = vx[q];
+              cy = vy[q];
+              cz = vz[q];
+            }
+            const R ct = list_thr(supr, marginr * (R)vh[q]);
+            const bool valid = jj[q] >= 0;
+#pragma unroll
+            for (int s = 0; s < GS; ++s) {
+              if (s < cnt) {
+                const R px = lane_val(xq, s), py = lane_val(yq, s), pz = lane_val(zq, s);
+                const R pt = lane_val(tq, s);
+                bool pred;
+                if constexpr (MIXED) {
+                  const float dx = px - cx, dy = py - cy, dz = pz - cz;
+                  const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                  pred = valid && (r2 < fmaxf(pt, ct));
+                } else {
+                  const double dx = fold(px - cx, kp.len[0], kp.half[0], kp.periodic[0]);
+                  const double dy = fold(py - cy, kp.len[1], kp.half[1], kp.periodic[1]);
+                  const double dz = fold(pz - cz, kp.len[2], kp.half[2], kp.periodic[2]);
+                  const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                  pred = valid && (r2 < fmax(pt, ct));
+                }
+                const uint64_t b = ballot64(pred);
+                const int pos = np[s] + popc64(b & lanemask_lt());
+                if (pred && pos < cap) nl_idx[(int64_t)(G.first + s) * cap + pos] = jj[q];
+                np[s] += popc64(b);
+              }
+            }
+          }
+        }
+        __syncthreads();  // L is refilled next
+      };
+      bool gok = sok;
+      if (sok) {
+        int nleaf = 0;
+        for (int base = 0; base < nsl; base += kWave) {
+          const int k = base + lane;
+          const bool open = k < nsl && ((s_sl[k] >> gk) & 1);
+          const uint64_t lb = ballot64(open);
+          const int nl = popc64(lb);
+          if (nleaf + nl > kLCap) {
+            flush(nleaf);
+            nleaf = 0;
+          }
+          if (open) {
+            const int pos = nleaf + popc64(lb & lanemask_lt());
+            L.lfirst[pos] = U.sl.first[k];
+            L.lcnt[pos] = U.sl.cnt[k];
+          }
+          nleaf += nl;
+          __syncthreads();
+        }
+        if (nleaf > 0) flush(nleaf);
+      } else {
+        // the super-group's leaf list overflowed: the group walks for its
+        // own leaf list; a group whose list overflows too is left to the
+        // walking kernels
+        int ngl = 0;
+        gok = true;
+        auto gflush = [&](int nleaf) {
+          if (ngl + nleaf <= kSLCap) {
+            for (int q = lane; q < nleaf; q += kWave) s_sl[ngl + q] = L.lnode[q];
+          } else {
+            gok = false;
+          }
+          ngl += nleaf;
+          __syncthreads();
+        };
+        if (!group_walk(nodes, G, kp, L, U.front, spill, radius, gflush)) gok = false;
+        __syncthreads();
+        ++walks;
+        if (gok) list_walk(nodes, s_sl, ngl, G, kp, L, radius, flush);
+      }
+      int mine = 0;
+      bool over = false;
+#pragma unroll
+      for (int s = 0; s < GS; ++s) {
+        if (lane == s) mine = np[s];
+        over |= (s < cnt) && (np[s] > cap);
+      }
+      if (act) {
+        nl_len[i] = mine;
+        grp_of[i] = g;
+      }
+      const bool bad = !gok || over;
       if (lane == 0) {
         gflag[g] = bad ? 1 : 0;
         if (bad) flag_list[atomicAdd(&ds->n_flagged, 1)] = g;
