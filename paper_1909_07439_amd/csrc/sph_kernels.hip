@@ -2009,8 +2009,12 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
 
 // ============================================================================
 // Neighbour lists (Sect. 3.2).  k_lists: one wavefront per super-group of
-// kSG groups.  The super-group walk collects every leaf any of its groups can
-// need; one pass over that list then tests each leaf against the box of every
+// kSGL consecutive groups (aligned runs of the curve, hence compact).  Each
+// XCD's super-groups go round its wavefronts; those left over after the last
+// full round are cut into aligned units of 4, 2 or 1 groups, the largest size
+// that still gives every wavefront at most one unit, so that the last round
+// costs a fraction of a super-group.  The super-group walk collects every
+// leaf any of its groups can need; one pass over that list then tests each leaf against the box of every
 // group of the super-group (one bit per group), so a node is read once per
 // super-group.  Each group then loads the particles of its leaves, one
 // candidate per lane, and for each of its particles i in turn appends the
@@ -2025,6 +2029,9 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
 // walking kernels.  The group of every particle is kept (grp_of) for the list
 // kernels, which work on chunks of consecutive particles instead of groups.
 // ============================================================================
+
+constexpr int kSGL = 8;       // groups per super-group of the list kernel
+constexpr int kSLCapL = 512;  // leaves a list-kernel super-group walk may collect
 
 // The value a wave-uniform lane `l` holds, as a wave-uniform scalar.
 __device__ __forceinline__ float lane_val(float v, int l) {
@@ -2065,7 +2072,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   using R = typename std::conditional<MIXED, float, double>::type;
   constexpr int GS = kWave / LPI;  // particles per group at most
   constexpr int PER = kTile / kWave;
-  static_assert(GS * kSG <= kWave, "one lane per particle of a super-group");
   __shared__ WalkLds L;
   // the frontier is live only during walks, the leaf ranges of the
   // super-group only after its walk; a group that walks on its own (the
@@ -2073,18 +2079,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   __shared__ union {
     int front[2][kFCap];
     struct {
-      int first[kSLCap];
-      int cnt[kSLCap];
+      int first[kSLCapL];
+      int cnt[kSLCapL];
     } sl;
   } U;
-  __shared__ int s_sl[kSLCap];  // leaf node ids of the walk, then one bit per group
-  __shared__ double s_hm[kSG];  // largest hl of each group
+  __shared__ int s_sl[kSLCapL];  // leaf node ids of the walk, then one bit per group
+  __shared__ double s_hm[kSGL];  // largest hl of each group
   const int lane = threadIdx.x;
   const int ng = ds->n_groups;
-  const int nsg = (ng + kSG - 1) / kSG;
+  const int nsg = (ng + kSGL - 1) / kSGL;
   const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, nloc = gridDim.x >> 3;
   const int chunk = (nsg + 7) >> 3;
   const int sbeg = xcd * chunk, send = min(sbeg + chunk, nsg);
+  // full rounds of super-groups, then the tail [gt0, gx1) in units of tsz groups
+  const int nfull = (max(send - sbeg, 0) / nloc) * nloc;
+  const int gt0 = min((sbeg + nfull) * kSGL, ng), gx1 = min(send * kSGL, ng);
+  int tsz = 1;
+  while (tsz < kSGL && (gx1 - gt0 + tsz - 1) / tsz > nloc) tsz *= 2;
+  const int nunits = nfull + (gx1 - gt0 + tsz - 1) / tsz;
   const double margin = kp.h_margin;
   const R supr = (R)kp.support, marginr = (R)margin;
   const int cap = kp.nl_cap;
@@ -2093,8 +2105,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   unsigned long long cands = 0;
   int walks = 0;
 
-  for (int sg = sbeg + local; sg < send; sg += nloc) {
-    const int g0 = sg * kSG, g1 = min(g0 + kSG, ng), ngs = g1 - g0;
+  for (int u = local; u < nunits; u += nloc) {
+    int g0, g1;
+    if (u < nfull) {
+      g0 = (sbeg + u) * kSGL;
+      g1 = min(g0 + kSGL, ng);
+    } else {
+      g0 = gt0 + (u - nfull) * tsz;
+      g1 = min(g0 + tsz, gx1);
+    }
+    const int ngs = g1 - g0;
     GroupInfo SG;
     {
       const bool v = lane < ngs;
@@ -2110,18 +2130,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       SG.first = 0;
       SG.count = 0;
     }
-    {
-      // largest hl of each group's particles: lane = group * GS + slot
-      const int gk = lane / GS, sl = lane % GS;
+    // largest hl of each group's particles: lane = group * GS + slot
+    for (int gb = 0; gb < ngs; gb += kWave / GS) {
+      const int gk = gb + lane / GS, sl = lane % GS;
       double hl = 0.0;
       if (gk < ngs) {
         const int f = groups[g0 + gk].first, cn = groups[g0 + gk].count;
         if (sl < cn) hl = margin * p.h[f + sl];
       }
       hl = seg_max<GS>(hl);
-      if (sl == 0 && gk < kSG) s_hm[gk] = hl;
-      __syncthreads();
+      if (sl == 0 && gk < ngs) s_hm[gk] = hl;
     }
+    __syncthreads();
     int nsl = 0;
     bool sok = true;
     {
@@ -2130,7 +2150,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         return kp.support * fmax(hs, margin * (double)nd.hmax) * (1.0 + 4e-9);
       };
       auto sflush = [&](int nleaf) {
-        if (nsl + nleaf <= kSLCap) {
+        if (nsl + nleaf <= kSLCapL) {
           for (int q = lane; q < nleaf; q += kWave) s_sl[nsl + q] = L.lnode[q];
         } else {
           sok = false;
@@ -2291,7 +2311,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         int ngl = 0;
         gok = true;
         auto gflush = [&](int nleaf) {
-          if (ngl + nleaf <= kSLCap) {
+          if (ngl + nleaf <= kSLCapL) {
             for (int q = lane; q < nleaf; q += kWave) s_sl[ngl + q] = L.lnode[q];
           } else {
             gok = false;
