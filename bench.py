@@ -12,7 +12,8 @@ particle-updates/s = N * steps / wall time of the timed steps, with the state
 resident in HBM.  ``roofline`` is for the kernel with the longest mean launch
 among the neighbour-list, density and force kernels, from its algorithmic
 FLOPs and its mean launch time measured with HIP events on the library
-stream; ``other_kernel_rooflines`` holds the other two.
+stream (recorded on every 8th timed step); ``other_kernel_rooflines`` holds
+the other two.
 ``cpu_baseline`` times the FP64 CPU oracle on the host cores.
 """
 from __future__ import annotations
@@ -77,6 +78,12 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+# phase events (HIP events at every phase boundary of sph_step) are recorded on
+# one timed step in TIMING_EVERY: each recorded boundary idles the GPU for a
+# few microseconds, which sampling keeps out of the throughput
+TIMING_EVERY = 8
+
+
 def run(cfg, precision, steps, warmup):
     import numpy as np
     import torch
@@ -90,6 +97,7 @@ def run(cfg, precision, steps, warmup):
     sph.sph_density(ctx, parts, want_iters=True)
     sph.sph_force(ctx, parts, want_dt=True)
     init = parts.numpy("id", "rho", "h", "ax", "ay", "az", "dudt")
+    sph.sph_set_timing(ctx, TIMING_EVERY)
     for _ in range(warmup):
         sph.sph_step(ctx, parts, 0.0)
     torch.cuda.synchronize()
@@ -377,6 +385,7 @@ def main():
         "roofline": roof,
         "other_kernel_rooflines": others,
         "phase_ms": {k: round(v, 5) for k, v in tim.items()},
+        "phase_events_every": TIMING_EVERY,
         "interactions_per_s": inter,
         "true_pairs_per_particle": {"density": st["density_pairs"] / cfg["n"],
                                     "force": st["force_pairs"] / cfg["n"]},

@@ -191,6 +191,15 @@ sph_status sph_neighbours(sph_ctx* ctx, const sph_particles* p, int32_t mode, in
    events.  Synchronises. */
 sph_status sph_timings(sph_ctx* ctx, double out[12]);
 
+/* Which calls record the phase events of sph_timings: sph_step records them
+   on one call in `every` (the first after this call, then every every-th),
+   0 records none; every other entry point records them whenever every > 0.
+   The default is 1 (every call).  Each recorded phase boundary leaves the
+   GPU idle for a few microseconds, so a throughput run samples (e.g. every =
+   8) and sph_timings averages over the sampled launches.  Returns SPH_E_ARG
+   for every < 0.  Host-only; no GPU work. */
+sph_status sph_set_timing(sph_ctx* ctx, int32_t every);
+
 /* Counters of the work done (for throughput accounting).  out[0..9] refer
    to the last sph_build_tree / sph_step: {tree nodes, groups, most density
    sums any group needed, true density neighbours (r < S h, self included) at

@@ -104,7 +104,9 @@ struct sph_ctx {
   sph::DevState* ds = nullptr;
   sph::DevState* hs = nullptr;  // pinned host mirror
   struct sph_timing* tm = nullptr;  // phase event rings (host code)
-  bool timing = true;
+  bool timing = true;      // record phase events for the current call
+  int timing_every = 1;    // sph_step records them on one call in this many (0: never)
+  int64_t step_calls = 0;  // sph_step calls since sph_set_timing
   int64_t density_launches = 0;  // launches of the density kernel so far
   int64_t force_launches = 0;    // launches of the force kernel so far
   int64_t lists_launches = 0;    // launches of the neighbour-list kernel so far

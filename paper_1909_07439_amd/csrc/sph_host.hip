@@ -307,11 +307,15 @@ sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ct
   }
   c->tm = x;
   bool ok = true;
+  // timing-only events: no system-scope fence when one is recorded (the
+  // cache write-back and invalidation would idle the GPU for microseconds at
+  // every phase boundary); sph_timings reads them after a stream synchronise
+  const unsigned evf = hipEventDisableSystemFence;
   for (int ph = 0; ph < kNPh && ok; ++ph) {
     x->count[ph] = 0;
     for (int r = 0; r < kRing && ok; ++r) {
-      ok = hipEventCreate(&x->start[ph][r]) == hipSuccess &&
-           hipEventCreate(&x->stop[ph][r]) == hipSuccess;
+      ok = hipEventCreateWithFlags(&x->start[ph][r], evf) == hipSuccess &&
+           hipEventCreateWithFlags(&x->stop[ph][r], evf) == hipSuccess;
     }
   }
   x->ready = ok;
@@ -454,6 +458,12 @@ sph_status sph_step(sph_ctx* c, sph_particles* p, double dt, double* dt_next_out
   sph_status st = check_parts(c, p, true, true);
   if (st != SPH_OK) return st;
   if (!isfinite(dt)) return fail(c, SPH_E_ARG, "dt is not finite");
+  // phase events on one call in timing_every; other entry points always record
+  struct TimingScope {
+    sph_ctx* c;
+    ~TimingScope() { c->timing = c->timing_every > 0; }
+  } scope{c};
+  c->timing = c->timing_every > 0 && (c->step_calls++ % c->timing_every) == 0;
   ph_begin(c, kPhStep);
   HIPCHK(c, sph::launch_reset_counters(c));
   HIPCHK(c, sph::launch_set_dt(c, dt));
@@ -698,6 +708,14 @@ sph_status sph_neighbours(sph_ctx* c, const sph_particles* p, int32_t mode, int6
   if (e != hipSuccess) return hip_fail(c, e, "sph_neighbours");
   for (int i = 0; i < c->n; ++i) std::sort(idx + offsets[i], idx + offsets[i + 1]);
   return sync_state(c, true);
+}
+
+sph_status sph_set_timing(sph_ctx* c, int32_t every) {
+  if (!c || every < 0) return SPH_E_ARG;
+  c->timing_every = every;
+  c->timing = every > 0;
+  c->step_calls = 0;
+  return SPH_OK;
 }
 
 sph_status sph_timings(sph_ctx* c, double out[12]) {

@@ -110,6 +110,7 @@ def load() -> ctypes.CDLL:
         lib.sph_get_groups.argtypes = [vp, P(i64), vp, vp]
         lib.sph_neighbours.argtypes = [vp, P(sph_particles), i32, vp, vp, i64]
         lib.sph_timings.argtypes = [vp, P(d)]
+        lib.sph_set_timing.argtypes = [vp, i32]
         lib.sph_stats.argtypes = [vp, P(i64)]
         lib.sph_eval_adjoint.argtypes = [vp, P(sph_particles), P(sph_cotangents)]
         lib.sph_step_adjoint.argtypes = [vp, P(sph_particles), d, P(sph_cotangents)]
@@ -117,7 +118,8 @@ def load() -> ctypes.CDLL:
         lib.sph_last_error.restype = ctypes.c_char_p
         for name in ("sph_create", "sph_build_tree", "sph_density", "sph_force", "sph_step",
                      "sph_reduce", "sph_check", "sph_get_keys", "sph_get_tree",
-                     "sph_get_groups", "sph_neighbours", "sph_timings", "sph_stats",
+                     "sph_get_groups", "sph_neighbours", "sph_timings", "sph_set_timing",
+                     "sph_stats",
                      "sph_eval_adjoint", "sph_step_adjoint"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
@@ -439,6 +441,11 @@ def rollout(ctx: Context, state: dict, dt: float, K: int) -> dict:
 
 PHASES = ("keys_sort", "permute", "tree", "density", "force", "integrate", "step",
           "lists", "density_fallback", "force_fallback", "adjoint", "adjoint_force")
+
+
+def sph_set_timing(ctx: Context, every: int) -> None:
+    """Record the phase events on one sph_step call in ``every`` (0: none)."""
+    _check(ctx.h, ctx.lib.sph_set_timing(ctx.h, int(every)), "sph_set_timing")
 
 
 def sph_timings(ctx: Context) -> dict:

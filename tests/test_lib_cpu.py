@@ -106,5 +106,6 @@ def test_null_context_is_an_argument_error(lib):
     assert lib.sph_check(None) == sph.SPH_E_ARG
     assert lib.sph_eval_adjoint(None, None, None) == sph.SPH_E_ARG
     assert lib.sph_step_adjoint(None, None, 1.0, None) == sph.SPH_E_ARG
+    assert lib.sph_set_timing(None, 1) == sph.SPH_E_ARG
     assert isinstance(lib.sph_last_error(None), bytes)
     lib.sph_destroy(None)
