@@ -2201,9 +2201,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         }
       }
       const R tq = list_thr(supr, (R)(margin * p.h[i]));
-      int np[GS];
-#pragma unroll
-      for (int s = 0; s < GS; ++s) np[s] = 0;
+      int npv = 0;  // lane s: entries appended to particle s's row so far
       const double hm = s_hm[gk];
       auto radius = [&](const WalkNode& nd) {
         return kp.support * fmax(hm, margin * (double)nd.hmax) * (1.0 + 4e-9);
@@ -2241,43 +2239,50 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
             vz[q] = p.z[j];
             vh[q] = p.h[j];
           }
+          R cx[PER], cy[PER], cz[PER], ct[PER];
 #pragma unroll
           for (int q = 0; q < PER; ++q) {
-            if (q * kWave >= cn) break;
-            R cx, cy, cz;
             if constexpr (MIXED) {
-              cx = (float)fold(vx[q] - G.c[0], kp.len[0], kp.half[0], kp.periodic[0]);
-              cy = (float)fold(vy[q] - G.c[1], kp.len[1], kp.half[1], kp.periodic[1]);
-              cz = (float)fold(vz[q] - G.c[2], kp.len[2], kp.half[2], kp.periodic[2]);
+              cx[q] = (float)fold(vx[q] - G.c[0], kp.len[0], kp.half[0], kp.periodic[0]);
+              cy[q] = (float)fold(vy[q] - G.c[1], kp.len[1], kp.half[1], kp.periodic[1]);
+              cz[q] = (float)fold(vz[q] - G.c[2], kp.len[2], kp.half[2], kp.periodic[2]);
             } else {
-              cx = vx[q];
-              cy = vy[q];
-              cz = vz[q];
+              cx[q] = vx[q];
+              cy[q] = vy[q];
+              cz[q] = vz[q];
             }
-            const R ct = list_thr(supr, marginr * (R)vh[q]);
-            const bool valid = jj[q] >= 0;
+            ct[q] = list_thr(supr, marginr * (R)vh[q]);
+          }
+          // particle-major: each particle's values are read from its lane once
+          // per tile; its row gets the tile's candidates in order
+          for (int s = 0; s < cnt; ++s) {
+            {
+              const R px = lane_val(xq, s), py = lane_val(yq, s), pz = lane_val(zq, s);
+              const R pt = lane_val(tq, s);
+              int32_t* __restrict__ row = nl_idx + (int64_t)(G.first + s) * cap;
+              int n = __builtin_amdgcn_readlane(npv, s);
 #pragma unroll
-            for (int s = 0; s < GS; ++s) {
-              if (s < cnt) {
-                const R px = lane_val(xq, s), py = lane_val(yq, s), pz = lane_val(zq, s);
-                const R pt = lane_val(tq, s);
-                bool pred;
-                if constexpr (MIXED) {
-                  const float dx = px - cx, dy = py - cy, dz = pz - cz;
-                  const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                  pred = valid && (r2 < fmaxf(pt, ct));
-                } else {
-                  const double dx = fold(px - cx, kp.len[0], kp.half[0], kp.periodic[0]);
-                  const double dy = fold(py - cy, kp.len[1], kp.half[1], kp.periodic[1]);
-                  const double dz = fold(pz - cz, kp.len[2], kp.half[2], kp.periodic[2]);
-                  const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                  pred = valid && (r2 < fmax(pt, ct));
+              for (int q = 0; q < PER; ++q) {
+                if (q * kWave < cn) {
+                  bool pred;
+                  if constexpr (MIXED) {
+                    const float dx = px - cx[q], dy = py - cy[q], dz = pz - cz[q];
+                    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                    pred = jj[q] >= 0 && (r2 < fmaxf(pt, ct[q]));
+                  } else {
+                    const double dx = fold(px - cx[q], kp.len[0], kp.half[0], kp.periodic[0]);
+                    const double dy = fold(py - cy[q], kp.len[1], kp.half[1], kp.periodic[1]);
+                    const double dz = fold(pz - cz[q], kp.len[2], kp.half[2], kp.periodic[2]);
+                    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                    pred = jj[q] >= 0 && (r2 < fmax(pt, ct[q]));
+                  }
+                  const uint64_t b = ballot64(pred);
+                  const int pos = n + popc64(b & lanemask_lt());
+                  if (pred && pos < cap) row[pos] = jj[q];
+                  n += popc64(b);
                 }
-                const uint64_t b = ballot64(pred);
-                const int pos = np[s] + popc64(b & lanemask_lt());
-                if (pred && pos < cap) nl_idx[(int64_t)(G.first + s) * cap + pos] = jj[q];
-                np[s] += popc64(b);
               }
+              npv = lane == s ? n : npv;
             }
           }
         }
@@ -2324,18 +2329,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         ++walks;
         if (gok) list_walk(nodes, s_sl, ngl, G, kp, L, radius, flush);
       }
-      int mine = 0;
-      bool over = false;
-#pragma unroll
-      for (int s = 0; s < GS; ++s) {
-        if (lane == s) mine = np[s];
-        over |= (s < cnt) && (np[s] > cap);
-      }
       if (act) {
-        nl_len[i] = mine;
+        nl_len[i] = npv;
         grp_of[i] = g;
       }
-      const bool bad = !gok || over;
+      const bool bad = !gok || ballot64(act && npv > cap) != 0ull;
       if (lane == 0) {
         gflag[g] = bad ? 1 : 0;
         if (bad) flag_list[atomicAdd(&ds->n_flagged, 1)] = g;
