@@ -13,6 +13,7 @@
 namespace sph {
 hipError_t launch_node_boxes(sph_ctx* c, const sph_particles* s);
 hipError_t launch_reset_counters(sph_ctx* c);
+hipError_t launch_step_begin(sph_ctx* c, double dt_host);
 hipError_t launch_force_reset(sph_ctx* c);
 hipError_t launch_leaf_state(sph_ctx* c, int v);
 }  // namespace sph
@@ -465,15 +466,12 @@ sph_status sph_step(sph_ctx* c, sph_particles* p, double dt, double* dt_next_out
   } scope{c};
   c->timing = c->timing_every > 0 && (c->step_calls++ % c->timing_every) == 0;
   ph_begin(c, kPhStep);
-  HIPCHK(c, sph::launch_reset_counters(c));
-  HIPCHK(c, sph::launch_set_dt(c, dt));
+  HIPCHK(c, sph::launch_step_begin(c, dt));
   st = do_build(c, p, false, true);
   if (st != SPH_OK) return st;
-  HIPCHK(c, sph::launch_leaf_state(c, 1));
   st = run_density(c, p);
   if (st != SPH_OK) return st;
   HIPCHK(c, sph::launch_node_h(c, p, false));
-  HIPCHK(c, sph::launch_force_reset(c));
   st = run_force(c, p, true);
   if (st != SPH_OK) return st;
   ph_begin(c, kPhIntegrate);
@@ -566,15 +564,12 @@ sph_status sph_step_adjoint(sph_ctx* c, sph_particles* p, double dt, sph_cotange
   if (!(dt > 0.0) || !isfinite(dt)) return fail(c, SPH_E_ARG, "the step adjoint needs dt > 0");
   // the forward step up to the corrector (as sph_step)
   ph_begin(c, kPhStep);
-  HIPCHK(c, sph::launch_reset_counters(c));
-  HIPCHK(c, sph::launch_set_dt(c, dt));
+  HIPCHK(c, sph::launch_step_begin(c, dt));
   st = do_build(c, p, false, true);
   if (st != SPH_OK) return st;
-  HIPCHK(c, sph::launch_leaf_state(c, 1));
   st = run_density(c, p);
   if (st != SPH_OK) return st;
   HIPCHK(c, sph::launch_node_h(c, p, false));
-  HIPCHK(c, sph::launch_force_reset(c));
   st = run_force(c, p, true);
   if (st != SPH_OK) return st;
   ph_end(c, kPhStep);

@@ -137,7 +137,6 @@ hipError_t launch_density(sph_ctx* c, const sph_particles* p, bool flagged_only)
 hipError_t launch_force_lists(sph_ctx* c, const sph_particles* p, bool step_mode);
 hipError_t launch_force(sph_ctx* c, const sph_particles* p, bool step_mode, bool flagged_only);
 hipError_t launch_correct(sph_ctx* c, const sph_particles* p);
-hipError_t launch_set_dt(sph_ctx* c, double dt_host);
 hipError_t launch_reduce(sph_ctx* c, const sph_particles* p, double* dev_out);
 hipError_t launch_neighbours(sph_ctx* c, const sph_particles* p, int mode, int32_t* counts,
                              const int64_t* offsets, int32_t* idx);

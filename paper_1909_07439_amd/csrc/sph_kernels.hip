@@ -260,11 +260,19 @@ __device__ __forceinline__ double wrap_coord(double v, double lo, double len, in
   return v;
 }
 
+// Block 0 also clears the radix sort's digit histograms and tile tickets
+// (the sort follows at once).
 __global__ __launch_bounds__(256) void k_predict_keys(KParams kp, Parts p, int predict,
                                                        const DevState* __restrict__ ds,
                                                        uint64_t* __restrict__ keys,
                                                        uint32_t* __restrict__ vals,
+                                                       uint32_t* __restrict__ ghist,
+                                                       uint32_t* __restrict__ tickets,
                                                        uint32_t* __restrict__ err) {
+  if (blockIdx.x == 0) {
+    for (int k = threadIdx.x; k < 8 * 256; k += blockDim.x) ghist[k] = 0u;
+    if (threadIdx.x < 8) tickets[threadIdx.x] = 0u;
+  }
   const int n = kp.n;
   const double dt = predict ? ds->dt_cur : 0.0;
   const double hdt2 = 0.5 * dt * dt;
@@ -339,11 +347,6 @@ __device__ __forceinline__ void lds_count_digit(uint32_t* cnt, uint32_t d, bool 
 constexpr uint32_t kStAgg = 1u << 30, kStPre = 2u << 30, kStMask = (1u << 30) - 1u;
 constexpr int kLookbackSpin = 1 << 22;  // bounded wait; the predecessors always publish
 constexpr int kLookW = 16;               // earlier tiles read per look-back round
-
-__global__ void k_radix_init(uint32_t* __restrict__ ghist, uint32_t* __restrict__ tickets) {
-  for (int k = threadIdx.x; k < 8 * 256; k += blockDim.x) ghist[k] = 0u;
-  if (threadIdx.x < 8) tickets[threadIdx.x] = 0u;
-}
 
 __global__ __launch_bounds__(256) void k_radix_prep(const uint64_t* __restrict__ keys, int n,
                                                      int nblk, uint32_t* __restrict__ status,
@@ -2032,6 +2035,7 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
 
 constexpr int kSGL = 8;       // groups per super-group of the list kernel
 constexpr int kSLCapL = 512;  // leaves a list-kernel super-group walk may collect
+constexpr int kListPer = 4;   // candidates each lane loads per list-kernel tile
 
 // The value a wave-uniform lane `l` holds, as a wave-uniform scalar.
 __device__ __forceinline__ float lane_val(float v, int l) {
@@ -2071,7 +2075,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   int* __restrict__ spill = walk_spill + (int64_t)blockIdx.x * 2 * kSpill;
   using R = typename std::conditional<MIXED, float, double>::type;
   constexpr int GS = kWave / LPI;  // particles per group at most
-  constexpr int PER = kTile / kWave;
+  constexpr int PER = kListPer;  // candidates per lane per tile
   __shared__ WalkLds L;
   // the frontier is live only during walks, the leaf ranges of the
   // super-group only after its walk; a group that walks on its own (the
@@ -2209,8 +2213,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       auto flush = [&](int nleaf) {
         const int total = leaf_offsets(L, nleaf);
         if (lane == 0) cands += (unsigned long long)total * (unsigned)cnt;
-        for (int c0 = 0; c0 < total; c0 += kTile) {
-          const int cn = min(kTile, total - c0);
+        for (int c0 = 0; c0 < total; c0 += PER * kWave) {
+          const int cn = min(PER * kWave, total - c0);
           // resolve this lane's candidates, then issue all their loads
           int jj[PER];
 #pragma unroll
@@ -2865,12 +2869,6 @@ __global__ __launch_bounds__(64) void k_neighbours(KParams kp, Parts p, int mode
 // ============================================================================
 // Integration and reductions (one thread per particle)
 // ============================================================================
-__global__ void k_set_dt(DevState* ds, double dt_host) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    ds->dt_cur = (dt_host > 0.0) ? dt_host : dec_f64(ds->dt_min_enc);
-  }
-}
-
 __global__ void k_set_leaf_state(DevState* ds, int v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     ds->leaf_state = v;
@@ -2885,20 +2883,35 @@ __global__ void k_reset_force_state(DevState* ds) {
   if (threadIdx.x == 0 && blockIdx.x == 0) ds->dt_min_enc = enc_f64(SPH_INF);
 }
 
+__device__ __forceinline__ void clear_counters(DevState* ds) {
+  ds->max_iter = 0;
+  ds->n_pairs_density = 0;
+  ds->n_pairs_force = 0;
+  ds->n_sums_density = 0;
+  ds->n_cand_density = 0;
+  ds->n_cand_force = 0;
+  ds->n_rewalk = 0;
+  ds->leaf_state = 0;
+  ds->lists_missing = 0;
+  ds->n_flag_rows = 0;
+  ds->n_flag_grew = 0;
+  ds->n_flagged = 0;
+}
+
 __global__ void k_reset_counters(DevState* ds) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) clear_counters(ds);
+}
+
+// Start of a step: counters cleared; the step's dt (the host's, or the
+// previous force pass's Courant minimum) taken before that minimum is reset
+// for this step's force pass; neighbour lists wanted (leaf_state 1: the tree
+// kernels before the density do not read it).
+__global__ void k_step_begin(DevState* ds, double dt_host) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    ds->max_iter = 0;
-    ds->n_pairs_density = 0;
-    ds->n_pairs_force = 0;
-    ds->n_sums_density = 0;
-    ds->n_cand_density = 0;
-    ds->n_cand_force = 0;
-    ds->n_rewalk = 0;
-    ds->leaf_state = 0;
-    ds->lists_missing = 0;
-    ds->n_flag_rows = 0;
-    ds->n_flag_grew = 0;
-    ds->n_flagged = 0;
+    ds->dt_cur = (dt_host > 0.0) ? dt_host : dec_f64(ds->dt_min_enc);
+    ds->dt_min_enc = enc_f64(SPH_INF);
+    clear_counters(ds);
+    ds->leaf_state = 1;
   }
 }
 
@@ -2996,26 +3009,37 @@ static int stream_blocks(int n) {
   return b < 1 ? 1 : (b > 8192 ? 8192 : b);
 }
 
-hipError_t launch_set_dt(sph_ctx* c, double dt_host) {
-  hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(64), 0, c->stream, c->ds, dt_host);
-  return hipGetLastError();
+// The radix sort's workspace: look-back status words of every pass and tile,
+// then the eight digit histograms, then the eight tile tickets.
+struct SortWs {
+  uint32_t *status, *ghist, *tickets;
+};
+static SortWs sort_ws(sph_ctx* c) {
+  const int64_t nst = (int64_t)c->n_max_sort_blocks * 8 * 256;
+  SortWs w;
+  w.status = c->radix_cnt;
+  w.ghist = c->radix_cnt + nst;
+  w.tickets = w.ghist + 8 * 256;
+  return w;
 }
 
 hipError_t launch_predict_keys(sph_ctx* c, const sph_particles* s, bool predict, double) {
   c->kp.n = c->n;
+  const SortWs w = sort_ws(c);
   hipLaunchKernelGGL(k_predict_keys, dim3(stream_blocks(c->n)), dim3(256), 0, c->stream, c->kp,
-                     parts_of(s), predict ? 1 : 0, c->ds, c->keys[0], c->vals[0], &c->ds->err);
+                     parts_of(s), predict ? 1 : 0, c->ds, c->keys[0], c->vals[0], w.ghist,
+                     w.tickets, &c->ds->err);
   return hipGetLastError();
 }
 
+// Follows launch_predict_keys, which cleared the histograms and tickets.
 hipError_t launch_sort(sph_ctx* c) {
   const int n = c->n;
   const int nblk = (n + kSortTile - 1) / kSortTile;
-  const int64_t nst = (int64_t)c->n_max_sort_blocks * 8 * 256;
-  uint32_t* status = c->radix_cnt;
-  uint32_t* ghist = c->radix_cnt + nst;
-  uint32_t* tickets = ghist + 8 * 256;
-  hipLaunchKernelGGL(k_radix_init, dim3(1), dim3(256), 0, c->stream, ghist, tickets);
+  const SortWs w = sort_ws(c);
+  uint32_t* status = w.status;
+  uint32_t* ghist = w.ghist;
+  uint32_t* tickets = w.tickets;
   const int pblocks = std::min(nblk, 4 * c->n_cu);
   hipLaunchKernelGGL(k_radix_prep, dim3(pblocks), dim3(256), 0, c->stream, c->keys[0], n, nblk,
                      status, ghist);
@@ -3269,6 +3293,11 @@ hipError_t launch_reduce(sph_ctx* c, const sph_particles* s, double* dev_out) {
   hipLaunchKernelGGL(k_reduce_part, dim3(kRedBlocks), dim3(256), 0, c->stream, parts_of(s),
                      (int)s->n, c->red_part);
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, c->stream, c->red_part, dev_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_begin(sph_ctx* c, double dt_host) {
+  hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(64), 0, c->stream, c->ds, dt_host);
   return hipGetLastError();
 }
 
