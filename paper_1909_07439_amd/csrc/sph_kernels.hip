@@ -549,8 +549,14 @@ __global__ __launch_bounds__(256) void k_tree_levels(const uint64_t* __restrict_
                                                       uint8_t* __restrict__ lgrp,
                                                       uint8_t* __restrict__ gstart,
                                                       uint32_t* __restrict__ tree_cnt,
-                                                      uint32_t* __restrict__ grp_cnt, int nblk) {
+                                                      uint32_t* __restrict__ grp_cnt, int nblk,
+                                                      int32_t* __restrict__ nnchild,
+                                                      int64_t node_cap) {
   __shared__ uint8_t d[kTreeTile + 2 * kHalo + 1];
+  // child counts of every node slot cleared for k_tree_emit's increments
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < node_cap;
+       k += (int64_t)gridDim.x * blockDim.x)
+    nnchild[k] = 0;
   __shared__ uint32_t lc[kLevels];
   __shared__ uint32_t gc;
   const int base = blockIdx.x * kTreeTile;
@@ -606,14 +612,6 @@ __device__ __forceinline__ int cell_end(const uint64_t* __restrict__ keys, int n
       hi = mid;
   }
   return hi;
-}
-
-__global__ __launch_bounds__(256) void k_zero_i32(int32_t* __restrict__ a, const int32_t* count,
-                                                   int64_t cap) {
-  const int64_t m = min((int64_t)*count, cap);
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m;
-       k += (int64_t)gridDim.x * blockDim.x)
-    a[k] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_tree_emit(
@@ -682,14 +680,13 @@ __global__ __launch_bounds__(256) void k_tree_emit(
 }
 
 // If the tree outgrew the node arrays, report it and leave an empty tree so
-// that no later launch reads or writes past the arrays.
-__global__ void k_tree_guard(DevState* ds, int64_t node_cap) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    if ((int64_t)ds->n_nodes > node_cap || ds->n_nodes < 0) {
-      atomicOr(&ds->err, kErrNodes);
-      ds->n_nodes = 0;
-      ds->n_groups = 0;
-    }
+// that no later launch reads or writes past the arrays (one thread, after
+// k_tree_emit; repeating it changes nothing).
+__device__ __forceinline__ void tree_guard(DevState* ds, int64_t node_cap) {
+  if ((int64_t)ds->n_nodes > node_cap || ds->n_nodes < 0) {
+    atomicOr(&ds->err, kErrNodes);
+    ds->n_nodes = 0;
+    ds->n_groups = 0;
   }
 }
 
@@ -756,7 +753,10 @@ __global__ __launch_bounds__(256) void k_chunk_boxes(const double* __restrict__ 
                                                       const double* __restrict__ z,
                                                       const double* __restrict__ h, int n,
                                                       double* __restrict__ cb,
-                                                      const DevState* __restrict__ ds, int mode) {
+                                                      DevState* __restrict__ ds, int mode,
+                                                      int64_t node_cap) {
+  // boxes of a new tree: its node count is checked before k_range_boxes reads it
+  if (mode == 1 && blockIdx.x == 0 && threadIdx.x == 0) tree_guard(ds, node_cap);
   if (!h_refresh_needed(ds, mode)) return;
   const int do_bb = mode == 1 ? 1 : 0;
   const int nch = (n + kChunk - 1) / kChunk;
@@ -3080,20 +3080,17 @@ hipError_t launch_tree(sph_ctx* c) {
   const int nblk = (n + kTreeTile - 1) / kTreeTile;
   hipLaunchKernelGGL(k_tree_levels, dim3(nblk), dim3(256), 0, c->stream, c->keys[0], n,
                      c->kp.n_leaf, c->kp.n_group, c->dlev, c->lleaf, c->lgrp, c->gstart,
-                     c->tree_cnt, c->grp_cnt, nblk);
+                     c->tree_cnt, c->grp_cnt, nblk, c->node_nchild, c->node_cap);
   hipError_t e = scan_u32(c, c->tree_cnt, (int64_t)kLevels * nblk, nullptr, &c->ds->n_nodes);
   if (e != hipSuccess) return e;
   e = scan_u32(c, c->grp_cnt, nblk, nullptr, &c->ds->n_groups);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_zero_i32, dim3(1024), dim3(256), 0, c->stream, c->node_nchild,
-                     &c->ds->n_nodes, c->node_cap);
   hipLaunchKernelGGL(k_tree_emit, dim3(nblk), dim3(256), 0, c->stream, c->keys[0], n,
                      c->kp.n_group, c->dlev, c->lleaf, c->lgrp, c->gstart, c->tree_cnt,
                      c->grp_cnt, nblk, c->node_cap, c->node_level, c->node_first,
                      c->node_count, c->node_parent, c->node_child, c->node_nchild,
                      c->grp_first, c->grp_count, c->ds);
-  hipLaunchKernelGGL(k_tree_guard, dim3(1), dim3(64), 0, c->stream, c->ds, c->node_cap);
-  return hipGetLastError();
+  return hipGetLastError();  // node_props checks the node count (tree_guard)
 }
 
 // Node boxes (positions) and largest h; group boxes.  The positions are the
@@ -3103,7 +3100,7 @@ static hipError_t node_props(sph_ctx* c, const sph_particles* s, int mode) {
   const int nch = (n + kChunk - 1) / kChunk;
   const int flag = mode;
   hipLaunchKernelGGL(k_chunk_boxes, dim3((nch + 3) / 4), dim3(256), 0, c->stream, s->x, s->y,
-                     s->z, s->h, n, c->chunk_box, c->ds, flag);
+                     s->z, s->h, n, c->chunk_box, c->ds, flag, c->node_cap);
   // leaves and groups: about one per thread; inner nodes (about a seventh of
   // the nodes): about two per wavefront
   const int64_t items = c->node_cap + (int64_t)n;
