@@ -2076,6 +2076,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   using R = typename std::conditional<MIXED, float, double>::type;
   constexpr int GS = kWave / LPI;  // particles per group at most
   constexpr int PER = kListPer;  // candidates per lane per tile
+  static_assert(kSGL * GS <= kWave, "one lane per particle of a super-group");
   __shared__ WalkLds L;
   // the frontier is live only during walks, the leaf ranges of the
   // super-group only after its walk; a group that walks on its own (the
@@ -2134,18 +2135,38 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       SG.first = 0;
       SG.count = 0;
     }
-    // largest hl of each group's particles: lane = group * GS + slot
-    for (int gb = 0; gb < ngs; gb += kWave / GS) {
-      const int gk = gb + lane / GS, sl = lane % GS;
+    // one particle per lane for the whole super-group (lane = group * GS +
+    // slot): position (FP32 path: relative to its group's centre, folded) and
+    // squared search radius, read as scalars by the pair loop; the largest
+    // hl of each group
+    const int pgk = lane / GS, psl = lane % GS;
+    bool pact = false;
+    int pi = 0;
+    R xq = R(0), yq = R(0), zq = R(0), tq = R(0);
+    {
       double hl = 0.0;
-      if (gk < ngs) {
-        const int f = groups[g0 + gk].first, cn = groups[g0 + gk].count;
-        if (sl < cn) hl = margin * p.h[f + sl];
+      if (pgk < ngs) {
+        const GroupInfo& Gp = groups[g0 + pgk];
+        pact = psl < Gp.count;
+        pi = Gp.first + (pact ? psl : 0);
+        const double xi = p.x[pi], yi = p.y[pi], zi = p.z[pi], hi = p.h[pi];
+        if constexpr (MIXED) {
+          xq = (float)fold(xi - Gp.c[0], kp.len[0], kp.half[0], kp.periodic[0]);
+          yq = (float)fold(yi - Gp.c[1], kp.len[1], kp.half[1], kp.periodic[1]);
+          zq = (float)fold(zi - Gp.c[2], kp.len[2], kp.half[2], kp.periodic[2]);
+        } else {
+          xq = xi;
+          yq = yi;
+          zq = zi;
+        }
+        tq = list_thr(supr, (R)(margin * hi));
+        if (pact) hl = margin * hi;
       }
       hl = seg_max<GS>(hl);
-      if (sl == 0 && gk < ngs) s_hm[gk] = hl;
+      if (psl == 0 && pgk < ngs) s_hm[pgk] = hl;
     }
     __syncthreads();
+    int npv = 0;  // entries appended to this lane's particle's row so far
     int nsl = 0;
     bool sok = true;
     {
@@ -2188,24 +2209,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       const int gk = g - g0;
       const GroupInfo G = groups[g];
       const int cnt = G.count;
-      const bool act = lane < cnt;
-      const int i = G.first + (act ? lane : 0);
-      // this lane's particle (lanes below cnt); the pair loop reads them as scalars
-      R xq, yq, zq;
-      {
-        const double xi = p.x[i], yi = p.y[i], zi = p.z[i];
-        if constexpr (MIXED) {
-          xq = (float)fold(xi - G.c[0], kp.len[0], kp.half[0], kp.periodic[0]);
-          yq = (float)fold(yi - G.c[1], kp.len[1], kp.half[1], kp.periodic[1]);
-          zq = (float)fold(zi - G.c[2], kp.len[2], kp.half[2], kp.periodic[2]);
-        } else {
-          xq = xi;
-          yq = yi;
-          zq = zi;
-        }
-      }
-      const R tq = list_thr(supr, (R)(margin * p.h[i]));
-      int npv = 0;  // lane s: entries appended to particle s's row so far
+      const int l0 = gk * GS;  // lane of the group's first particle
       const double hm = s_hm[gk];
       auto radius = [&](const WalkNode& nd) {
         return kp.support * fmax(hm, margin * (double)nd.hmax) * (1.0 + 4e-9);
@@ -2261,10 +2265,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
           // per tile; its row gets the tile's candidates in order
           for (int s = 0; s < cnt; ++s) {
             {
-              const R px = lane_val(xq, s), py = lane_val(yq, s), pz = lane_val(zq, s);
-              const R pt = lane_val(tq, s);
+              const int ls = l0 + s;
+              const R px = lane_val(xq, ls), py = lane_val(yq, ls), pz = lane_val(zq, ls);
+              const R pt = lane_val(tq, ls);
               int32_t* __restrict__ row = nl_idx + (int64_t)(G.first + s) * cap;
-              int n = __builtin_amdgcn_readlane(npv, s);
+              int n = __builtin_amdgcn_readlane(npv, ls);
 #pragma unroll
               for (int q = 0; q < PER; ++q) {
                 if (q * kWave < cn) {
@@ -2286,7 +2291,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                   n += popc64(b);
                 }
               }
-              npv = lane == s ? n : npv;
+              npv = lane == ls ? n : npv;
             }
           }
         }
@@ -2333,17 +2338,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         ++walks;
         if (gok) list_walk(nodes, s_sl, ngl, G, kp, L, radius, flush);
       }
-      if (act) {
-        nl_len[i] = npv;
-        grp_of[i] = g;
-      }
-      const bool bad = !gok || ballot64(act && npv > cap) != 0ull;
+      const bool mine = lane >= l0 && lane < l0 + cnt;
+      const bool bad = !gok || ballot64(mine && npv > cap) != 0ull;
       if (lane == 0) {
         gflag[g] = bad ? 1 : 0;
         if (bad) flag_list[atomicAdd(&ds->n_flagged, 1)] = g;
       }
       flagged |= bad;
       nflag += bad ? 1 : 0;
+    }
+    if (pact) {
+      nl_len[pi] = npv;
+      grp_of[pi] = g0 + pgk;
     }
   }
   unsigned long long cd = cands;
