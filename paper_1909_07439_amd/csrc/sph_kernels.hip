@@ -2048,6 +2048,12 @@ __device__ __forceinline__ double lane_val(double v, int l) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// base + the number of set bits of m below this lane (mbcnt: two VALU ops)
+__device__ __forceinline__ int rank_below(uint64_t m, int base) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)base));
+}
+
 // Squared search radius (support * x)^2 of the list predicate, with a
 // relative slack of 1e-5 in FP32.  Every step rounds monotonically, so the
 // value at max(a, b) is the larger of the values at a and at b: the pair test
@@ -2261,6 +2267,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
             }
             ct[q] = list_thr(supr, marginr * (R)vh[q]);
           }
+          uint64_t vm[PER];  // lanes holding a candidate, per quarter of the tile
+#pragma unroll
+          for (int q = 0; q < PER; ++q) vm[q] = ballot64(jj[q] >= 0);
           // particle-major: each particle's values are read from its lane once
           // per tile; its row gets the tile's candidates in order
           for (int s = 0; s < cnt; ++s) {
@@ -2273,21 +2282,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 #pragma unroll
               for (int q = 0; q < PER; ++q) {
                 if (q * kWave < cn) {
-                  bool pred;
+                  // one compare per ballot; candidates past the tile's end
+                  // are masked out afterwards (scalar AND)
+                  bool hit;
                   if constexpr (MIXED) {
                     const float dx = px - cx[q], dy = py - cy[q], dz = pz - cz[q];
                     const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                    pred = jj[q] >= 0 && (r2 < fmaxf(pt, ct[q]));
+                    // r2 and the radii are >= 0: their bit patterns order
+                    // like their values (an integer max needs no NaN care)
+                    hit = __float_as_int(r2) < max(__float_as_int(pt), __float_as_int(ct[q]));
                   } else {
                     const double dx = fold(px - cx[q], kp.len[0], kp.half[0], kp.periodic[0]);
                     const double dy = fold(py - cy[q], kp.len[1], kp.half[1], kp.periodic[1]);
                     const double dz = fold(pz - cz[q], kp.len[2], kp.half[2], kp.periodic[2]);
                     const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                    pred = jj[q] >= 0 && (r2 < fmax(pt, ct[q]));
+                    hit = r2 < fmax(pt, ct[q]);
                   }
-                  const uint64_t b = ballot64(pred);
-                  const int pos = n + popc64(b & lanemask_lt());
-                  if (pred && pos < cap) row[pos] = jj[q];
+                  const bool pred = hit & (jj[q] >= 0);
+                  const uint64_t b = ballot64(hit) & vm[q];
+                  const int pos = rank_below(b, n);
+                  if (pred & (pos < cap)) row[(unsigned)pos] = jj[q];
                   n += popc64(b);
                 }
               }
