@@ -62,3 +62,21 @@ def test_turbulent_box_full_size_sampled():
     sel = np.random.default_rng(1909).choice(cfg["n"], 256, replace=False)
     o = oracle.evaluate_subset(cfg, oracle.make_params(cfg), sel)
     check(g, o, sph.SPH_PREC_MIXED, idx=sel)
+
+
+@pytest.mark.parametrize("n_side", [44, 60])
+def test_list_work_units_lattices(n_side):
+    """Jittered lattices whose group counts leave different remainders of
+    super-groups after the list kernel's full rounds (cut into units of 1, 2,
+    4 or 8 groups): FP64 values and the exact pair counts of the oracle.  On
+    the 256-CU launch, 44^3 (32,768 groups) fills whole rounds and 60^3
+    (38,324 groups) leaves units of 2 groups; the shock tube leaves single
+    groups and its M6 run units of 4."""
+    cfg = inputs.lattice(n_side, jitter=0.2, velocities=True)
+    g, ctx, parts, info = gpu_eval(cfg, sph.SPH_PREC_FP64)
+    say(f"  n_groups={info['stats']['n_groups']}")
+    o = oracle.evaluate(cfg, oracle.make_params(cfg))
+    check(g, o, sph.SPH_PREC_FP64)
+    assert info["stats"]["density_pairs"] == int(o["nneigh"].sum())
+    assert info["stats"]["force_pairs"] == int(o["nneigh_force"].sum())
+    ctx.close()
