@@ -385,33 +385,61 @@ __global__ __launch_bounds__(256) void k_radix_pass(const uint64_t* __restrict__
                                                      uint32_t* __restrict__ tickets,
                                                      uint32_t* __restrict__ err) {
   constexpr int PER = kSortTile / 256;
-  __shared__ uint32_t cnt[256];
+  constexpr int NS = PER * 4;  // (key slice, wavefront) sets of 64 keys, in key order
+  // wc[d * NS + s]: keys of digit d in set s, then the tile's keys of digit d
+  // before set s (at most kSortTile: 16 bits suffice)
+  __shared__ uint16_t wc[256 * NS];
   __shared__ uint32_t run[256];
-  __shared__ uint32_t wc[4][256];
   __shared__ uint32_t lds4[4];
   __shared__ int s_tile;
+  static_assert(kSortTile <= 65535, "16-bit tile offsets");
   const int tid = threadIdx.x, w = tid >> 6;
   const int shift = 8 * pass;
-  cnt[tid] = 0u;
+  {
+    uint32_t* z = reinterpret_cast<uint32_t*>(wc);
+#pragma unroll
+    for (int q = 0; q < NS / 2; ++q) z[q * 256 + tid] = 0u;
+  }
   if (tid == 0) s_tile = (int)atomicAdd(&tickets[pass], 1u);
   __syncthreads();
   const int tile = s_tile;
   const int base = tile * kSortTile;
   uint64_t key[PER];
-  uint32_t val[PER];
+  uint32_t val[PER], rank[PER];
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int i = base + k * 256 + tid;
     key[k] = i < n ? kin[i] : 0ull;
     val[k] = i < n ? vin[i] : 0u;
   }
+  // rank of each key among the equal digits of its set (wave ballots), and
+  // the count of every digit in every set
 #pragma unroll
-  for (int k = 0; k < PER; ++k)
-    lds_count_digit(cnt, (uint32_t)((key[k] >> shift) & 255ull), base + k * 256 + tid < n);
+  for (int k = 0; k < PER; ++k) {
+    const bool valid = base + k * 256 + tid < n;
+    const uint32_t d = (uint32_t)((key[k] >> shift) & 255ull);
+    const uint64_t m = match_digit8(d, ballot64(valid));
+    rank[k] = (uint32_t)popc64(m & lanemask_lt());
+    if (valid && rank[k] == 0) wc[d * NS + k * 4 + w] = (uint16_t)popc64(m);
+  }
   __syncthreads();
+  // thread d: exclusive offsets of digit d over the sets, and the tile's count
+  uint32_t mine = 0u;
+  {
+    uint16_t c[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) c[q] = wc[tid * NS + q];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      const uint32_t v = c[q];
+      c[q] = (uint16_t)mine;
+      mine += v;
+    }
+#pragma unroll
+    for (int q = 0; q < NS; ++q) wc[tid * NS + q] = c[q];
+  }
   // publish this tile's counts, then the exclusive prefix over earlier tiles
   uint32_t* st = status + (int64_t)pass * nblk * 256;
-  const uint32_t mine = cnt[tid];
   uint32_t excl = 0u;
   if (tile == 0) {
     __hip_atomic_store(&st[tid], kStPre | mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -454,28 +482,16 @@ __global__ __launch_bounds__(256) void k_radix_pass(const uint64_t* __restrict__
   uint32_t all;
   const uint32_t gofs = block256_excl_scan(ghist[pass * 256 + tid], lds4, &all);
   run[tid] = gofs + excl;
-  wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0u;
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int i = base + k * 256 + tid;
-    const bool valid = i < n;
-    const uint32_t d = (uint32_t)((key[k] >> shift) & 255ull);
-    const uint64_t act = ballot64(valid);
-    const uint64_t m = match_digit8(d, act);
-    const uint32_t rank = (uint32_t)popc64(m & lanemask_lt());
-    if (valid && rank == 0) wc[w][d] = (uint32_t)popc64(m);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = run[d] + rank;
-      for (int q = 0; q < w; ++q) pos += wc[q][d];
+    if (i < n) {
+      const uint32_t d = (uint32_t)((key[k] >> shift) & 255ull);
+      const uint32_t pos = run[d] + (uint32_t)wc[d * NS + k * 4 + w] + rank[k];
       kout[pos] = key[k];
       vout[pos] = val[k];
     }
-    __syncthreads();
-    run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
-    wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0u;
-    __syncthreads();
   }
 }
 
