@@ -395,6 +395,7 @@ __global__ __launch_bounds__(256) void k_radix_pass(const uint64_t* __restrict__
   static_assert(kSortTile <= 65535, "16-bit tile offsets");
   const int tid = threadIdx.x, w = tid >> 6;
   const int shift = 8 * pass;
+  const uint32_t gh = ghist[pass * 256 + tid];  // in flight from the start
   {
     uint32_t* z = reinterpret_cast<uint32_t*>(wc);
 #pragma unroll
@@ -438,14 +439,16 @@ __global__ __launch_bounds__(256) void k_radix_pass(const uint64_t* __restrict__
 #pragma unroll
     for (int q = 0; q < NS; ++q) wc[tid * NS + q] = c[q];
   }
-  // publish this tile's counts, then the exclusive prefix over earlier tiles
+  // publish this tile's counts; scan the global digit counts while earlier
+  // tiles publish theirs; then the exclusive prefix over earlier tiles
   uint32_t* st = status + (int64_t)pass * nblk * 256;
+  __hip_atomic_store(&st[(int64_t)tile * 256 + tid], (tile == 0 ? kStPre : kStAgg) | mine,
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // start of every digit: keys with a smaller digit anywhere
+  uint32_t all;
+  const uint32_t gofs = block256_excl_scan(gh, lds4, &all);
   uint32_t excl = 0u;
-  if (tile == 0) {
-    __hip_atomic_store(&st[tid], kStPre | mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  } else {
-    __hip_atomic_store(&st[(int64_t)tile * 256 + tid], kStAgg | mine, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+  if (tile > 0) {
     // a window of kLookW earlier tiles per round: their loads are in flight
     // together, so a long chain of published counts costs one latency per
     // window rather than one per tile
@@ -478,9 +481,7 @@ __global__ __launch_bounds__(256) void k_radix_pass(const uint64_t* __restrict__
     __hip_atomic_store(&st[(int64_t)tile * 256 + tid], kStPre | (excl + mine), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
   }
-  // start of every digit: keys with a smaller digit anywhere + this digit in earlier tiles
-  uint32_t all;
-  const uint32_t gofs = block256_excl_scan(ghist[pass * 256 + tid], lds4, &all);
+  // + this digit in earlier tiles
   run[tid] = gofs + excl;
   __syncthreads();
 #pragma unroll
