@@ -2033,12 +2033,13 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
 // XCD's super-groups go round its wavefronts; those left over after the last
 // full round are cut into aligned units of 4, 2 or 1 groups, the largest size
 // that still gives every wavefront at most one unit, so that the last round
-// costs a fraction of a super-group.  The super-group walk collects every
-// leaf any of its groups can need; one pass over that list then tests each leaf against the box of every
-// group of the super-group (one bit per group), so a node is read once per
-// super-group.  Each group then loads the particles of its leaves, one
-// candidate per lane, and for each of its particles i in turn appends the
-// indices j of every candidate with
+// costs a fraction of a super-group.  The super-group's particles are loaded
+// once, one per lane.  The super-group walk collects every leaf any of its
+// groups can need; one pass over that list then tests each leaf against the
+// box of every group of the super-group (one bit per group), so a node is
+// read once per super-group.  Each group then loads the particles of its
+// leaves, one candidate per lane, and for each of its particles i in turn
+// appends the indices j of every candidate with
 //     r_ij < 2 max(hl_i, hl_j),   hl = h_margin * (h at the start),
 // to the fixed-capacity row i of nl_idx (self included): one ballot and one
 // coalesced store per particle and 64 candidates, in candidate order.  As
@@ -2085,16 +2086,12 @@ __device__ __forceinline__ double list_thr(double support, double x) {
 }
 
 template <bool MIXED, int LPI>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_lists(KParams kp, Parts p,
-                                              const WalkNode* __restrict__ nodes,
-                                              const GroupInfo* __restrict__ groups,
-                                              int32_t* __restrict__ nl_idx,
-                                              int32_t* __restrict__ nl_len,
-                                              int32_t* __restrict__ gflag,
-                                              int32_t* __restrict__ flag_list,
-                                              int32_t* __restrict__ grp_of,
-                                              int32_t* __restrict__ walk_spill,
-    DevState* __restrict__ ds) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
+void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
+             const GroupInfo* __restrict__ groups, int32_t* __restrict__ nl_idx,
+             int32_t* __restrict__ nl_len, int32_t* __restrict__ gflag,
+             int32_t* __restrict__ flag_list, int32_t* __restrict__ grp_of,
+             int32_t* __restrict__ walk_spill, DevState* __restrict__ ds) {
   int* __restrict__ spill = walk_spill + (int64_t)blockIdx.x * 2 * kSpill;
   using R = typename std::conditional<MIXED, float, double>::type;
   constexpr int GS = kWave / LPI;  // particles per group at most
