@@ -2486,9 +2486,11 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
         gz[q] = v.z;
         gm[q] = v.w;
       }
+      // every slot is computed and stored (entries past the row's length sit
+      // below CAP and are never read): a conditional use would let the
+      // compiler sink each load into it and serialise the four gathers
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        if (!vv[q]) continue;
         const int k = sub + LPI * (t0 + q);
         const double dx = fold(xi - gx[q], kp.len[0], kp.half[0], kp.periodic[0]);
         const double dy = fold(yi - gy[q], kp.len[1], kp.half[1], kp.periodic[1]);
