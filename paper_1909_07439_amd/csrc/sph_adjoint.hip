@@ -218,8 +218,11 @@ __global__ __launch_bounds__(64) void k_adj_force(KParams kp, Parts p,
     R bx = 0, by = 0, bz = 0, bvx = 0, bvy = 0, bvz = 0;
     R bh = 0, bg = 0, bk = 0, bc = 0, bp = 0, br = 0, bu = 0;
     R s1 = 0, s2 = 0;  // density sums of dW/dh and d2W/dh2 (without C / h^4, C / h^5)
+    // row index one iteration ahead
+    int jn = (sub < len) ? row[sub] : k;
     for (int t = sub; t < len; t += LPI) {
-      const int j = row[t];
+      const int j = jn;
+      jn = (t + LPI < len) ? row[t + LPI] : k;
       if (j == k) continue;
       const Rec rj = rec[j];
       const R dx = (R)afold(xk - rj.x, kp.len[0], kp.half[0], kp.periodic[0]);
