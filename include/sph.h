@@ -123,7 +123,10 @@ sph_status sph_build_tree(sph_ctx* ctx, sph_particles* p);
    wavefront-wide convergence vote per group; then rho, Omega = 1 + h S1/(3
    rho), P = (gamma-1) rho u and cs = sqrt(gamma (gamma-1) u) are written.
    iters_out (may be NULL; if given, the call synchronises): the largest
-   number of density sums any group needed.
+   number of density sums any group needed.  The positions must be those the
+   tree was built from (in its order); m, h, u and v may have changed since:
+   the call takes them as they are (a later call on the same tree starts from
+   the h the previous one converged to).
    Errors: SPH_E_NOCONV, SPH_E_OVERFLOW, SPH_E_DOMAIN, SPH_E_NONFINITE. */
 sph_status sph_density(sph_ctx* ctx, sph_particles* p, int32_t* iters_out);
 

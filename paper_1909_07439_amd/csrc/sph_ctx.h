@@ -108,6 +108,7 @@ struct sph_ctx {
   int timing_every = 1;    // sph_step records them on one call in this many (0: never)
   int64_t step_calls = 0;  // sph_step calls since sph_set_timing
   int64_t density_launches = 0;  // launches of the density kernel so far
+  int32_t densities_on_tree = 0; // density passes since the last tree build
   int64_t force_launches = 0;    // launches of the force kernel so far
   int64_t lists_launches = 0;    // launches of the neighbour-list kernel so far
   std::string err;

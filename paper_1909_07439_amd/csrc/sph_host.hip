@@ -14,6 +14,7 @@ namespace sph {
 hipError_t launch_node_boxes(sph_ctx* c, const sph_particles* s);
 hipError_t launch_reset_counters(sph_ctx* c);
 hipError_t launch_step_begin(sph_ctx* c, double dt_host);
+hipError_t launch_pack_xyzm(sph_ctx* c, const sph_particles* s);
 hipError_t launch_force_reset(sph_ctx* c);
 hipError_t launch_leaf_state(sph_ctx* c, int v);
 }  // namespace sph
@@ -357,6 +358,7 @@ void sph_destroy(sph_ctx* c) {
 static sph_status do_build(sph_ctx* c, sph_particles* p, bool outputs_too, bool predict) {
   c->n = (int32_t)p->n;
   c->kp.n = c->n;
+  c->densities_on_tree = 0;
   ph_begin(c, kPhSort);
   HIPCHK(c, sph::launch_predict_keys(c, p, predict, 0.0));
   HIPCHK(c, sph::launch_sort(c));
@@ -399,6 +401,7 @@ static sph_status run_density(sph_ctx* c, sph_particles* p) {
     ph_end(c, kPhDensity);
   }
   ++c->density_launches;
+  ++c->densities_on_tree;
   return SPH_OK;
 }
 
@@ -426,6 +429,13 @@ sph_status sph_density(sph_ctx* c, sph_particles* p, int32_t* iters_out) {
   sph_status st = check_parts(c, p, false, true);
   if (st != SPH_OK) return st;
   if (p->n != c->n) return fail(c, SPH_E_ARG, "n differs from the last sph_build_tree");
+  // the packed positions and masses the list and density kernels gather are
+  // taken from the arrays as they are now (m may have changed since the build)
+  HIPCHK(c, sph::launch_pack_xyzm(c, p));
+  // a later density pass on the same tree starts from the h the last one
+  // converged to: the node and group h_max are brought up to it first, or the
+  // list walk could leave out a neighbour whose h grew past its node's h_max
+  if (c->densities_on_tree > 0) HIPCHK(c, sph::launch_node_h(c, p, true));
   HIPCHK(c, sph::launch_leaf_state(c, 1));
   st = run_density(c, p);
   if (st != SPH_OK) return st;

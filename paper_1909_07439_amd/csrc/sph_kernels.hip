@@ -528,6 +528,13 @@ __global__ __launch_bounds__(256) void k_copy_back(FieldSet fs, const double* __
   }
 }
 
+// Packed x, y, z, m from the particle arrays (the density entry point: the
+// caller may have changed m, or x with it, since the permute wrote them).
+__global__ __launch_bounds__(256) void k_pack_xyzm(Parts p, int n, double4* __restrict__ xyzm) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
+    xyzm[k] = make_double4(p.x[k], p.y[k], p.z[k], p.m[k]);
+}
+
 // ============================================================================
 // Tree and groups from the sorted keys, in three launches.
 //
@@ -3108,6 +3115,12 @@ hipError_t launch_permute(sph_ctx* c, const sph_particles* s, bool outputs_too) 
                      c->gtmp_id, c->n, (int64_t)c->n_max);
   hipLaunchKernelGGL(k_copy_back, dim3(nb), dim3(256), 0, c->stream, fs, c->gtmp, c->gtmp_id,
                      c->n, (int64_t)c->n_max);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_xyzm(sph_ctx* c, const sph_particles* s) {
+  hipLaunchKernelGGL(k_pack_xyzm, dim3(stream_blocks(c->n)), dim3(256), 0, c->stream,
+                     parts_of(s), c->n, c->xyzm);
   return hipGetLastError();
 }
 

@@ -431,3 +431,37 @@ def test_m6_steps_fp64_match_oracle():
     g = to_orig(parts.numpy())
     for k in ("x", "vx", "u", "rho", "h"):
         assert np.abs(g[k] - s[k]).max() <= 1e-10 * max(np.abs(s[k]).max(), 1e-300), k
+
+
+def test_second_density_on_the_same_tree():
+    """A density pass on a tree that already had one starts from the h the
+    last pass converged to; here the masses are raised between the two passes,
+    so h grows past the h_margin of the build's h.  The pairs and values of the
+    force that follows equal those of a tree built at the final state (the
+    node h_max are refreshed before the second pass)."""
+    cfg = inputs.sod(dx_left=1.0 / 256, width=1.0 / 16)
+    cfg = dict(cfg)
+    cfg["h"] = 0.95 * np.asarray(cfg["h"])
+    p = sph.make_params(cfg, sph.SPH_PREC_FP64)
+    parts = sph.Particles(cfg)
+    ctx = sph.Context(p, cfg["n"])
+    sph.sph_build_tree(ctx, parts)
+    sph.sph_density(ctx, parts)
+    parts.t["m"].mul_(1.3)  # h grows by about 1.3^(1/3) in the next pass
+    sph.sph_density(ctx, parts)
+    sph.sph_force(ctx, parts)
+    st_a = sph.sph_stats(ctx)
+    a = to_orig(parts.numpy())
+    ctx.close()
+    say(f"  h grew by up to {np.max(a['h'] / np.asarray(cfg['h'])):.3f} over the build's")
+    fresh = dict(cfg)
+    for k in ("x", "y", "z", "vx", "vy", "vz", "u", "m", "h"):
+        fresh[k] = a[k]
+    g, ctx_b, _, info = gpu_eval(fresh, sph.SPH_PREC_FP64)
+    ctx_b.close()
+    assert st_a["force_pairs"] == info["stats"]["force_pairs"]
+    for k in ("h", "rho"):
+        assert rel_err(a[k], g[k]).max() <= 1e-12, k
+    scale = np.sqrt(g["ax"] ** 2 + g["ay"] ** 2 + g["az"] ** 2).max()
+    for k in ("ax", "ay", "az"):
+        assert np.abs(a[k] - g[k]).max() <= 1e-10 * scale, k
