@@ -133,7 +133,9 @@ sph_status sph_density(sph_ctx* ctx, sph_particles* p, int32_t* iters_out);
 /* Hydrodynamic force (Sect. 2.4-2.6): for every pair with r < S max(h_i,h_j)
    the pressure, artificial-viscosity and conductivity terms; writes ax, ay,
    az, dudt and vsig_dt.  Needs rho, omega, P, cs from sph_density on the
-   same tree.  dt_next_out (may be NULL; if given the call synchronises):
+   same tree; the neighbours' x, m, h, v and u are those of that call (the
+   density pass packs them into per-particle records the force gathers), so
+   a change to v or u takes effect through another sph_density.  dt_next_out (may be NULL; if given the call synchronises):
    c_cour * min_i h_i / vsig_dt_i.  The same value is also kept on the device
    for sph_step.
    Errors: SPH_E_OVERFLOW, SPH_E_NONFINITE, SPH_E_HIP. */
