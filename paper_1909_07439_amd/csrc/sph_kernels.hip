@@ -325,7 +325,7 @@ __device__ __forceinline__ void lds_count_digit(uint32_t* cnt, uint32_t d, bool 
   const uint64_t act = ballot64(valid);
   if (act == 0ull) return;
   const int lead = __builtin_ctzll(act);
-  const uint32_t d0 = (uint32_t)__shfl((int)d, lead, kWave);
+  const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)d, lead);  // lead is uniform
   const uint64_t same = ballot64(valid && d == d0);
   if (same == act) {
     if (lane_id() == lead) atomicAdd(&cnt[d0], (uint32_t)popc64(act));
