@@ -125,8 +125,9 @@ sph_status sph_build_tree(sph_ctx* ctx, sph_particles* p);
    iters_out (may be NULL; if given, the call synchronises): the largest
    number of density sums any group needed.  The positions must be those the
    tree was built from (in its order); m, h, u and v may have changed since:
-   the call takes them as they are (a later call on the same tree starts from
-   the h the previous one converged to).
+   the call takes them as they are, and first brings the tree's node and group
+   h_max up to the h in p->h (a later call on the same tree starts from the h
+   the previous one converged to).
    Errors: SPH_E_NOCONV, SPH_E_OVERFLOW, SPH_E_DOMAIN, SPH_E_NONFINITE. */
 sph_status sph_density(sph_ctx* ctx, sph_particles* p, int32_t* iters_out);
 
@@ -151,7 +152,10 @@ sph_status sph_step(sph_ctx* ctx, sph_particles* p, double dt, double* dt_next_o
 
 /* Global FP64 sums in a fixed order (deterministic): out[12] = {E, E_kin,
    E_th, p_x, p_y, p_z, sum m a_x, sum m a_y, sum m a_z, dE/dt = sum m (v.a +
-   du/dt), sum m |a|, sum m (|v.a| + |du/dt|)}.  Synchronises. */
+   du/dt), sum m |a|, sum m (|v.a| + |du/dt|)}.  E is the total energy whose
+   relative change the paper uses as its conservation measure (Sect. 4.5,
+   eq:energy_error); the momentum and energy-rate sums test the
+   conservation of the pair forms of eq:acc and eq:energy.  Synchronises. */
 sph_status sph_reduce(sph_ctx* ctx, const sph_particles* p, double out[12]);
 
 /* Device error word of the last calls, as a status (SPH_OK if clean); clears
@@ -160,11 +164,14 @@ sph_status sph_check(sph_ctx* ctx);
 
 /* ---- inspection (host copies; synchronising; for tests and tools) ---- */
 
-/* Sorted keys of the last sph_build_tree and perm[k] = pre-sort index of the
-   particle now at position k.  Host arrays of n entries (either may be NULL). */
+/* Sorted keys of the last sph_build_tree (the space-filling-curve keys of
+   Sect. 3.1) and perm[k] = pre-sort index of the particle now at position k.
+   Host arrays of n entries (either may be NULL). */
 sph_status sph_get_keys(sph_ctx* ctx, uint64_t* keys, int64_t* perm);
 
-/* Tree of the last sph_build_tree in canonical order (by level, then key).
+/* Octree of the last sph_build_tree (Sect. 3.1: the sorted curve chopped
+   into sections of at most n_leaf particles) in canonical order (by level,
+   then key).
    *n_nodes: in = capacity of the arrays, out = node count.  With all arrays
    NULL only the count is returned.  child_first is -1 for leaves.
    Errors: SPH_E_ARG if the capacity is too small. */
@@ -172,17 +179,40 @@ sph_status sph_get_tree(sph_ctx* ctx, int64_t* n_nodes, int32_t* level, uint64_t
                         int64_t* first, int64_t* count, int64_t* child_first,
                         int32_t* n_child);
 
-/* Groups of the last sph_build_tree, ordered by first particle. */
+/* Particle groups of the last sph_build_tree (Sect. 3.1: sections of the
+   sorted curve with at most n_group particles, which walk the tree
+   together), ordered by first particle.  *n_groups: in = capacity of the
+   host arrays first, count; out = group count (NULL arrays: count only). */
 sph_status sph_get_groups(sph_ctx* ctx, int64_t* n_groups, int64_t* first, int64_t* count);
 
-/* Neighbour sets found by the group tree walk, as CSR over the current
-   particle order with ascending indices: mode 0 = density set (r < S h_i,
-   self included), mode 1 = force set (j != i, r < S max(h_i, h_j)), using
-   the h currently in p->h and the FP64 predicate of both precision modes.
+/* Neighbour sets found by the group tree walk (Sect. 3.2: a node is opened
+   while it lies within the group's search radius; the density set uses the
+   particle's own smoothing range, the force set the larger of the pair's),
+   as CSR over the current particle order with ascending indices: mode 0 =
+   density set (r < S h_i, self included), mode 1 = force set (j != i,
+   r < S max(h_i, h_j)), using the h currently in p->h and the FP64
+   predicate of both precision modes.  This is an inspection walk of its
+   own; sph_list_pairs gives the sets of the hot path.
    offsets: host array of n+1 entries (always filled); idx: host array of
    cap entries (may be NULL to query the total in offsets[n]).
    Errors: SPH_E_ARG (cap too small: offsets are still filled). */
 sph_status sph_neighbours(sph_ctx* ctx, const sph_particles* p, int32_t mode, int64_t* offsets,
+                          int32_t* idx, int64_t cap);
+
+/* The pairs the hot path's density (mode 0) and force (mode 1) list
+   kernels accept (Sect. 3.2, 3.2.1): each particle's neighbour-list row
+   written by the last density pass's list walk, filtered with the exact
+   FP64 predicate at the h currently in p->h (density: r < S h_i, self
+   included; force: j != i, r < S max(h_i, h_j)).  The mixed mode's FP32
+   test is settled in FP64 near the boundary, so both precisions accept the
+   FP64 sets.  CSR over the current particle order with ascending indices;
+   offsets, idx and cap as in sph_neighbours.  If some group was flagged in
+   that pass (a row overflowed or an h outgrew it) the rows are first
+   rebuilt at the current h; particles still flagged went through the walking
+   kernels, and the sets then come from the group walk with the same exact
+   predicate (as sph_neighbours).  Needs n_group 4 or 8 and a density pass on
+   the current tree.  Errors: SPH_E_ARG, SPH_E_HIP. */
+sph_status sph_list_pairs(sph_ctx* ctx, const sph_particles* p, int32_t mode, int64_t* offsets,
                           int32_t* idx, int64_t cap);
 
 /* Mean duration of the launches of each phase since the previous call, in

@@ -432,10 +432,11 @@ sph_status sph_density(sph_ctx* c, sph_particles* p, int32_t* iters_out) {
   // the packed positions and masses the list and density kernels gather are
   // taken from the arrays as they are now (m may have changed since the build)
   HIPCHK(c, sph::launch_pack_xyzm(c, p));
-  // a later density pass on the same tree starts from the h the last one
-  // converged to: the node and group h_max are brought up to it first, or the
-  // list walk could leave out a neighbour whose h grew past its node's h_max
-  if (c->densities_on_tree > 0) HIPCHK(c, sph::launch_node_h(c, p, true));
+  // the node and group h_max are brought up to the h in p->h first (the
+  // caller may have changed h since the build, and a later pass on the same
+  // tree starts from the h the last one converged to), or the list walk
+  // could leave out a neighbour whose h grew past its node's h_max
+  HIPCHK(c, sph::launch_node_h(c, p, true));
   HIPCHK(c, sph::launch_leaf_state(c, 1));
   st = run_density(c, p);
   if (st != SPH_OK) return st;
@@ -683,21 +684,26 @@ sph_status sph_get_groups(sph_ctx* c, int64_t* n_groups, int64_t* first, int64_t
   return SPH_OK;
 }
 
-sph_status sph_neighbours(sph_ctx* c, const sph_particles* p, int32_t mode, int64_t* offsets,
-                          int32_t* idx, int64_t cap) {
-  if (!c || !offsets || (mode != 0 && mode != 1)) return SPH_E_ARG;
-  sph_status st = check_parts(c, p, false, false);
-  if (st != SPH_OK) return st;
-  if (p->n != c->n) return fail(c, SPH_E_ARG, "n differs from the last sph_build_tree");
-  HIPCHK(c, sph::launch_node_h(c, p, true));  // the current h, whatever the force used
-  HIPCHK(c, sph::launch_neighbours(c, p, mode, c->nb_cnt, nullptr, nullptr));
+// CSR of exact neighbour sets at the current h on the host, from the group
+// walk (source 0) or from the list rows (source 1).
+static sph_status export_sets(sph_ctx* c, const sph_particles* p, int mode, int source,
+                              int64_t* offsets, int32_t* idx, int64_t cap, const char* who) {
+  if (source == 0) {
+    HIPCHK(c, sph::launch_node_h(c, p, true));  // the current h, whatever the force used
+    HIPCHK(c, sph::launch_neighbours(c, p, mode, c->nb_cnt, nullptr, nullptr));
+  } else {
+    HIPCHK(c, sph::launch_row_sets(c, p, mode, c->nb_cnt, nullptr, nullptr));
+  }
   std::vector<int32_t> cnt(c->n);
   HIPCHK(c, hipMemcpyAsync(cnt.data(), c->nb_cnt, 4 * (size_t)c->n, hipMemcpyDeviceToHost,
                            c->stream));
-  st = sync_state(c, true);
+  sph_status st = sync_state(c, true);
   if (st != SPH_OK) return st;
   offsets[0] = 0;
-  for (int i = 0; i < c->n; ++i) offsets[i + 1] = offsets[i] + cnt[i];
+  for (int i = 0; i < c->n; ++i) {
+    if (cnt[i] < 0) return fail(c, SPH_E_OVERFLOW, "a particle's list row is incomplete");
+    offsets[i + 1] = offsets[i] + cnt[i];
+  }
   const int64_t total = offsets[c->n];
   if (!idx) return SPH_OK;
   if (cap < total) return fail(c, SPH_E_ARG, "idx capacity too small");
@@ -705,14 +711,51 @@ sph_status sph_neighbours(sph_ctx* c, const sph_particles* p, int32_t mode, int6
   HIPCHK(c, hipMalloc((void**)&didx, sizeof(int32_t) * (size_t)std::max<int64_t>(total, 1)));
   hipError_t e = hipMemcpyAsync(c->nb_off, offsets, 8 * ((size_t)c->n + 1), hipMemcpyHostToDevice,
                                 c->stream);
-  if (e == hipSuccess) e = sph::launch_neighbours(c, p, mode, nullptr, c->nb_off, didx);
+  if (e == hipSuccess)
+    e = source == 0 ? sph::launch_neighbours(c, p, mode, nullptr, c->nb_off, didx)
+                    : sph::launch_row_sets(c, p, mode, c->nb_cnt, didx, c->nb_off);
   if (e == hipSuccess)
     e = hipMemcpyAsync(idx, didx, 4 * (size_t)total, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   (void)hipFree(didx);
-  if (e != hipSuccess) return hip_fail(c, e, "sph_neighbours");
+  if (e != hipSuccess) return hip_fail(c, e, who);
   for (int i = 0; i < c->n; ++i) std::sort(idx + offsets[i], idx + offsets[i + 1]);
   return sync_state(c, true);
+}
+
+sph_status sph_neighbours(sph_ctx* c, const sph_particles* p, int32_t mode, int64_t* offsets,
+                          int32_t* idx, int64_t cap) {
+  if (!c || !offsets || (mode != 0 && mode != 1)) return SPH_E_ARG;
+  sph_status st = check_parts(c, p, false, false);
+  if (st != SPH_OK) return st;
+  if (p->n != c->n) return fail(c, SPH_E_ARG, "n differs from the last sph_build_tree");
+  return export_sets(c, p, mode, 0, offsets, idx, cap, "sph_neighbours");
+}
+
+sph_status sph_list_pairs(sph_ctx* c, const sph_particles* p, int32_t mode, int64_t* offsets,
+                          int32_t* idx, int64_t cap) {
+  if (!c || !offsets || (mode != 0 && mode != 1)) return SPH_E_ARG;
+  sph_status st = check_parts(c, p, false, false);
+  if (st != SPH_OK) return st;
+  if (p->n != c->n) return fail(c, SPH_E_ARG, "n differs from the last sph_build_tree");
+  if (!sph::lists_mode(c)) return fail(c, SPH_E_ARG, "the list rows need n_group 4 or 8");
+  if (c->lists_launches == 0 || c->densities_on_tree == 0)
+    return fail(c, SPH_E_ARG, "no density pass on this tree has built the list rows");
+  // rows of flagged groups are incomplete: rebuilt at the current h once;
+  // particles still flagged went through the walking kernels, whose sets the
+  // group walk with the same exact predicate gives
+  st = sync_state(c, true);
+  if (st != SPH_OK) return st;
+  if (c->hs->n_flagged != 0) {
+    HIPCHK(c, sph::launch_node_h(c, p, true));
+    HIPCHK(c, sph::launch_leaf_state(c, 1));
+    HIPCHK(c, sph::launch_lists(c, p));
+    ++c->lists_launches;
+    st = sync_state(c, true);
+    if (st != SPH_OK) return st;
+  }
+  const int source = c->hs->n_flagged == 0 ? 1 : 0;
+  return export_sets(c, p, mode, source, offsets, idx, cap, "sph_list_pairs");
 }
 
 sph_status sph_set_timing(sph_ctx* c, int32_t every) {

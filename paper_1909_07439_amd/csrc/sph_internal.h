@@ -135,6 +135,8 @@ hipError_t launch_lists(sph_ctx* c, const sph_particles* p);
 hipError_t launch_density_lists(sph_ctx* c, const sph_particles* p);
 hipError_t launch_density(sph_ctx* c, const sph_particles* p, bool flagged_only);
 hipError_t launch_force_lists(sph_ctx* c, const sph_particles* p, bool step_mode);
+hipError_t launch_row_sets(sph_ctx* c, const sph_particles* p, int mode, int32_t* counts,
+                           int32_t* idx, const int64_t* offsets);
 hipError_t launch_force(sph_ctx* c, const sph_particles* p, bool step_mode, bool flagged_only);
 hipError_t launch_correct(sph_ctx* c, const sph_particles* p);
 hipError_t launch_reduce(sph_ctx* c, const sph_particles* p, double* dev_out);

@@ -1293,6 +1293,83 @@ __device__ __forceinline__ T kern_df(int kind, T q) {
 __device__ __forceinline__ float fast_sqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
 __device__ __forceinline__ float fast_rcp(float v) { return __builtin_amdgcn_rcpf(v); }
 
+// The same shapes with the kind fixed at compile time (the list kernels are
+// instantiated per kind, so their pair loops carry no branch on it) and the
+// polynomials in fused multiply-adds.  M4 in one expression for both
+// branches: f = t^3/4 - s^3, f' = 3 s^2 - 3 t^2/4, s = max(1-q, 0),
+// t = max(2-q, 0).
+template <int KIND, typename T>
+__device__ __forceinline__ void kf_df(T q, T& f, T& df) {
+  if constexpr (KIND == 1) {
+    const T a = T(3) - q, b = T(2) - q, c = T(1) - q;
+    const T t3 = a > T(0) ? a : T(0), t2 = b > T(0) ? b : T(0), t1 = c > T(0) ? c : T(0);
+    const T s3 = t3 * t3, s2 = t2 * t2, s1 = t1 * t1;
+    const T q3 = s3 * s3, q2 = s2 * s2, q1 = s1 * s1;  // fourth powers
+    f = fma(T(15) * q1, t1, fma(T(-6) * q2, t2, q3 * t3));
+    df = fma(T(-75), q1, fma(T(30), q2, T(-5) * q3));
+  } else if constexpr (KIND == 2) {
+    const T u = fma(T(-0.5), q, T(1));
+    const T s = u > T(0) ? u : T(0);
+    const T s2 = s * s, s4 = s2 * s2, s7 = s4 * s2 * s;
+    f = (s7 * s) * fma(fma(fma(T(4), q, T(6.25)), q, T(4)), q, T(1));
+    df = (T(-2.75) * q) * fma(fma(T(8), q, T(7)), q, T(2)) * s7;
+  } else {
+    const T a = T(2) - q, b = T(1) - q;
+    const T t = a > T(0) ? a : T(0), s = b > T(0) ? b : T(0);
+    const T t2 = t * t, s2 = s * s;
+    f = fma(T(0.25) * t2, t, -(s2 * s));
+    df = fma(T(3) * s, s, T(-0.75) * t2);
+  }
+}
+
+template <int KIND, typename T>
+__device__ __forceinline__ T kdf(T q) {
+  if constexpr (KIND == 1) {
+    const T a = T(3) - q, b = T(2) - q, c = T(1) - q;
+    const T t3 = a > T(0) ? a : T(0), t2 = b > T(0) ? b : T(0), t1 = c > T(0) ? c : T(0);
+    const T s3 = t3 * t3, s2 = t2 * t2, s1 = t1 * t1;
+    return fma(T(-75) * s1, s1, fma(T(30) * s2, s2, T(-5) * s3 * s3));
+  } else if constexpr (KIND == 2) {
+    const T u = fma(T(-0.5), q, T(1));
+    const T s = u > T(0) ? u : T(0);
+    const T s2 = s * s, s4 = s2 * s2;
+    return (T(-2.75) * q) * fma(fma(T(8), q, T(7)), q, T(2)) * (s4 * s2 * s);
+  } else {
+    const T a = T(2) - q, b = T(1) - q;
+    const T t = a > T(0) ? a : T(0), s = b > T(0) ? b : T(0);
+    return fma(T(3) * s, s, T(-0.75) * (t * t));
+  }
+}
+
+// Nearest periodic image of a separation d (|d| < L) of the mixed-precision
+// pair loops, in three FP64 operations: d - L rint(d / L) (lp = L, ilp = 1/L
+// on periodic axes, 0 on open ones).  It agrees with fold() except within a
+// rounding of |d| = L/2, far outside any support (S h < L/2).
+__device__ __forceinline__ double fold_r(double d, double lp, double ilp) {
+  return fma(-lp, rint(d * ilp), d);
+}
+
+// The exact FP64 pair predicate of both precisions: r^2 = fma(dz, dz,
+// fma(dy, dy, dx dx)) of the nearest-image separation against
+// (S max(h_i, h_j))^2 (force set, `force`) or (S h_i)^2 (density set).
+__device__ __forceinline__ bool exact_pair(const KParams& kp, const double* __restrict__ x,
+                                           const double* __restrict__ y,
+                                           const double* __restrict__ z,
+                                           const double* __restrict__ h, int i, int j,
+                                           bool force) {
+  const double dx = fold(x[i] - x[j], kp.len[0], kp.half[0], kp.periodic[0]);
+  const double dy = fold(y[i] - y[j], kp.len[1], kp.half[1], kp.periodic[1]);
+  const double dz = fold(z[i] - z[j], kp.len[2], kp.half[2], kp.periodic[2]);
+  const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+  const double hi = h[i], hj = h[j];
+  const double sr = kp.support * ((force && hj > hi) ? hj : hi);
+  return r2 < sr * sr;
+}
+
+// FP32 pair tests of the mixed mode lie within about 1e-6 (relative) of the
+// FP64 ones; a test this close to the boundary is settled by exact_pair.
+constexpr float kBorder = 4e-5f;
+
 // ============================================================================
 // Density: one wave per group (GS = 64/LPI particle slots of LPI lanes).
 // Pair lists (r, m_j) for r < 2 h_i * margin are built once by the walk and
@@ -2422,7 +2499,7 @@ __device__ __forceinline__ GroupRange xcd_groups(int ng) {
 // neighbours) is flagged (gflag = 2) for the walking kernel, and the force
 // pass then walks for every group (leaf_state 2).
 // ============================================================================
-template <bool MIXED, int LPI, int CAP>
+template <bool MIXED, int LPI, int CAP, int KIND>
 __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
                                                       const GroupInfo* __restrict__ groups,
                                                       const int32_t* __restrict__ nl_idx,
@@ -2452,6 +2529,11 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
   unsigned long long pairs_final = 0, sums = 0;
   bool outgrew_any = false;
   int ngrew = 0;
+  double lp[3], ilp[3];  // periodic lengths and their inverses (0 on open axes)
+  for (int a = 0; a < 3; ++a) {
+    lp[a] = kp.periodic[a] ? kp.len[a] : 0.0;
+    ilp[a] = kp.periodic[a] ? kp.inv_len[a] : 0.0;
+  }
 
   for (int g = gr.beg; g < gr.end; g += gr.step) {
     const int first = g * CS, count = min(CS, kp.n - first);
@@ -2499,9 +2581,16 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int k = sub + LPI * (t0 + q);
-        const double dx = fold(xi - gx[q], kp.len[0], kp.half[0], kp.periodic[0]);
-        const double dy = fold(yi - gy[q], kp.len[1], kp.half[1], kp.periodic[1]);
-        const double dz = fold(zi - gz[q], kp.len[2], kp.half[2], kp.periodic[2]);
+        double dx, dy, dz;
+        if constexpr (MIXED) {
+          dx = fold_r(xi - gx[q], lp[0], ilp[0]);
+          dy = fold_r(yi - gy[q], lp[1], ilp[1]);
+          dz = fold_r(zi - gz[q], lp[2], ilp[2]);
+        } else {
+          dx = fold(xi - gx[q], kp.len[0], kp.half[0], kp.periodic[0]);
+          dy = fold(yi - gy[q], kp.len[1], kp.half[1], kp.periodic[1]);
+          dz = fold(zi - gz[q], kp.len[2], kp.half[2], kp.periodic[2]);
+        }
         if constexpr (MIXED) {
           const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
           s_r[k * GS + slot] = fast_sqrt(fmaf(fz, fz, fmaf(fy, fy, fx * fx)));
@@ -2530,7 +2619,7 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
           const float r = s_r[k * GS + slot], m = s_m[k * GS + slot];
           const float q = r * hinvf;
           float f, df;
-          kern_f_df<float>(kp.kernel, q, f, df);
+          kf_df<KIND, float>(q, f, df);
           s0 = fmaf(m, f, s0);
           s1 = fmaf(m, fmaf(q, df, 3.0f * f), s1);
           cnt += (r < twohf) ? 1u : 0u;
@@ -2543,9 +2632,9 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
           const double r = s_r[k * GS + slot], m = s_m[k * GS + slot];
           const double q = r * hinv;
           double f, df;
-          kern_f_df<double>(kp.kernel, q, f, df);
-          a0 += m * f;
-          a1 += m * (3.0 * f + q * df);
+          kf_df<KIND, double>(q, f, df);
+          a0 = fma(m, f, a0);
+          a1 = fma(m, fma(q, df, 3.0 * f), a1);
           cnt += (r < twoh) ? 1u : 0u;
         }
       }
@@ -2654,7 +2743,7 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
 // terms.  Runs only while every row is complete (leaf_state 1); flagged
 // groups are left to the walking kernel.
 // ============================================================================
-template <bool MIXED, int LPI>
+template <bool MIXED, int LPI, int KIND>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 void k_force_lists(KParams kp, Parts p,
                                                     const GroupInfo* __restrict__ groups,
@@ -2679,6 +2768,11 @@ void k_force_lists(KParams kp, Parts p,
   uint32_t err = 0;
   unsigned long long pairs = 0, cands = 0;
   double dtmin = SPH_INF;
+  double lp[3], ilp[3];  // periodic lengths and their inverses (0 on open axes)
+  for (int a = 0; a < 3; ++a) {
+    lp[a] = kp.periodic[a] ? kp.len[a] : 0.0;
+    ilp[a] = kp.periodic[a] ? kp.inv_len[a] : 0.0;
+  }
 
   for (int g = gr.beg; g < gr.end; g += gr.step) {
     const int first = g * CS, count = min(CS, kp.n - first);
@@ -2696,45 +2790,55 @@ void k_force_lists(KParams kp, Parts p,
     cands += (act && sub == 0) ? (unsigned long long)len : 0ull;
     double ax = 0.0, ay = 0.0, az = 0.0, du = 0.0, vmax = 0.0;
     if constexpr (MIXED) {
-      const float al = (float)kp.alpha, be = (float)kp.beta, au = (float)kp.alpha_u;
+      const float al = (float)kp.alpha, be = (float)kp.beta, hau = (float)(0.5 * kp.alpha_u);
       const float vxi = ri.vx, vyi = ri.vy, vzi = ri.vz, hif = (float)hi;
-      const float hinvi = ri.hinv, h4i = ri.hinv4pi, gi = ri.g, ki = ri.k, ci = ri.c;
+      const float hinvi = ri.hinv, h4i = ri.hinv4pi, gi = ri.g, ki = ri.k;
       const float Pi = ri.P, rhoi = ri.rho, ui = ri.u;
+      const float aci = al * ri.c, nhki = -0.5f * ki, S = (float)kp.support;
       // per-lane sums in FP32 (a lane takes one in LPI of the row's pairs),
       // combined across the slot's lanes in FP64 below
       float fax = 0.f, fay = 0.f, faz = 0.f, fdu = 0.f, fvmax = 0.f;
       uint32_t npr = 0;
-      auto pair = [&](const Rec& rj) {
-        const float dx = (float)fold(xi - rj.x, kp.len[0], kp.half[0], kp.periodic[0]);
-        const float dy = (float)fold(yi - rj.y, kp.len[1], kp.half[1], kp.periodic[1]);
-        const float dz = (float)fold(zi - rj.z, kp.len[2], kp.half[2], kp.periodic[2]);
+      // The pair terms of eq:acc and eq:energy with the switch w_ = min(w, 0)
+      // of the approaching pairs (w = v_ij . e_ij):
+      //   t_i = g_i - k_i vsig_i w_ / 2,  A_i = t_i m_j F_i,  pa = A_i + t_j m_j F_j,
+      //   a_i -= pa e_ij,  du_i += w A_i + (alpha_u / 2) v^u (u_i - u_j)
+      //                                   (k_i m_j F_i + k_j m_j F_j);
+      // the viscous heating of an approaching pair is the w_ part of w A_i.
+      // The FP32 support test is settled in FP64 near its boundary, so the
+      // accepted pairs are those of the FP64 predicate.
+      auto pair = [&](const Rec& rj, int j) {
+        const float dx = (float)fold_r(xi - rj.x, lp[0], ilp[0]);
+        const float dy = (float)fold_r(yi - rj.y, lp[1], ilp[1]);
+        const float dz = (float)fold_r(zi - rj.z, lp[2], ilp[2]);
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        const float sr = (float)kp.support * fmaxf(hif, rj.h);
-        if (!(r2 < sr * sr * 1.00001f)) return;
+        const float sr = S * fmaxf(hif, rj.h);
+        const float sr2 = sr * sr;
+        bool in = r2 < sr2;
+        const bool border = fabsf(r2 - sr2) <= kBorder * sr2;
+        if (ballot64(border) != 0ull)
+          if (border) in = exact_pair(kp, p.x, p.y, p.z, p.h, i, j, true);
+        if (!in) return;
         ++npr;
         const float rinv = __builtin_amdgcn_rsqf(r2);
         const float r = r2 * rinv;
         const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
         const float w = fmaf(vzi - rj.vz, ez, fmaf(vyi - rj.vy, ey, (vxi - rj.vx) * ex));
-        const float Fi = kern_df<float>(kp.kernel, r * hinvi) * h4i;
-        const float Fj = kern_df<float>(kp.kernel, r * rj.hinv) * rj.hinv4pi;
-        const float aw = fabsf(w);
-        const bool app = w < 0.0f;
-        const float vsi = fmaf(be, aw, al * ci);
+        const float mFi = rj.m * (kdf<KIND, float>(r * hinvi) * h4i);
+        const float mFj = kdf<KIND, float>(r * rj.hinv) * (rj.m * rj.hinv4pi);
+        const float aw = fabsf(w), wn = fminf(w, 0.f);
+        const float vsi = fmaf(be, aw, aci);
         const float vsj = fmaf(be, aw, al * rj.c);
-        const float ti = app ? fmaf(-0.5f * vsi * w, ki, gi) : gi;
-        const float tj = app ? fmaf(-0.5f * vsj * w, rj.k, rj.g) : rj.g;
-        const float pa = rj.m * fmaf(ti, Fi, tj * Fj);
+        const float ti = fmaf(nhki * vsi, wn, gi);
+        const float tj = fmaf(-0.5f * rj.k * vsj, wn, rj.g);
+        const float Ai = ti * mFi;
+        const float pa = fmaf(tj, mFj, Ai);
         fax = fmaf(-pa, ex, fax);
         fay = fmaf(-pa, ey, fay);
         faz = fmaf(-pa, ez, faz);
-        const float mwF = rj.m * w * Fi;
-        float e = gi * mwF;
-        if (app) e = fmaf(-0.5f * ki * vsi * w, mwF, e);
-        const float dP = fabsf(Pi - rj.P);
-        const float vu = fast_sqrt(dP * fast_rcp(0.5f * (rhoi + rj.rho)));
-        e = fmaf(rj.m * au * vu * (ui - rj.u), 0.5f * fmaf(Fi, ki, Fj * rj.k), e);
-        fdu += e;
+        const float vu = fast_sqrt(fabsf(Pi - rj.P) * fast_rcp(0.5f * (rhoi + rj.rho)));
+        const float X = fmaf(mFi, ki, mFj * rj.k);
+        fdu = fmaf(w, Ai, fmaf(hau * vu * (ui - rj.u), X, fdu));
         fvmax = fmaxf(fvmax, vsi);
       };
       // row indices one iteration ahead, so that each iteration waits for
@@ -2748,8 +2852,8 @@ void k_force_lists(KParams kp, Parts p,
         const int kn = k + 2 * LPI;
         const int jn1 = (kn < len) ? row[kn] : i;
         const int jn2 = (kn + LPI < len) ? row[kn + LPI] : i;
-        if (v1 && j1 != i) pair(r1);
-        if (v2 && j2 != i) pair(r2);
+        if (v1 && j1 != i) pair(r1, j1);
+        if (v2 && j2 != i) pair(r2, j2);
         j1 = jn1;
         j2 = jn2;
       }
@@ -2776,8 +2880,8 @@ void k_force_lists(KParams kp, Parts p,
         const double rinv = 1.0 / r;
         const double ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
         const double w = fma(vzi - rj.vz, ez, fma(vyi - rj.vy, ey, (vxi - rj.vx) * ex));
-        const double Fi = kern_df<double>(kp.kernel, r * hinvi) * h4i;
-        const double Fj = kern_df<double>(kp.kernel, r * rj.hinv) * rj.hinv4pi;
+        const double Fi = kdf<KIND, double>(r * hinvi) * h4i;
+        const double Fj = kdf<KIND, double>(r * rj.hinv) * rj.hinv4pi;
         const double aw = fabs(w);
         const bool app = w < 0.0;
         const double vsi = fma(be, aw, al * ci);
@@ -2841,6 +2945,57 @@ void k_force_lists(KParams kp, Parts p,
     if (pf) atomicAdd(&ds->tot_pairs_force, pf);
     if (cd) atomicAdd(&ds->n_cand_force, cd);
     if (dm < SPH_INF) dt_min_update(ds, dm);
+  }
+}
+
+// ============================================================================
+// The pairs the list kernels accept (Sect. 3.2), for inspection and for the
+// adjoint's frozen neighbour sets: each particle's row filtered with the
+// exact FP64 predicate at the h in p.h (the mixed force kernel settles its
+// FP32 test in FP64 near the boundary, so it accepts the same pairs); mode
+// 0: density set (r < S h_i, self included), 1: force set (j != i,
+// r < S max(h_i, h_j)).  Particles of flagged groups (incomplete rows) get
+// the count -1.  Indices are written at offsets[i] in row order.
+// ============================================================================
+template <int LPI>
+__global__ __launch_bounds__(64) void k_row_sets(KParams kp, Parts p, int mode,
+                                                 const int32_t* __restrict__ nl_idx,
+                                                 const int32_t* __restrict__ nl_len,
+                                                 const int32_t* __restrict__ gflag,
+                                                 const int32_t* __restrict__ grp_of,
+                                                 int32_t* __restrict__ counts,
+                                                 int32_t* __restrict__ idx,
+                                                 const int64_t* __restrict__ offsets) {
+  const int lane = threadIdx.x;
+  const int slot = lane / LPI, sub = lane % LPI;
+  constexpr int CS = kWave / LPI;
+  const int nch = (kp.n + CS - 1) / CS;
+  const GroupRange gr = xcd_groups(nch);
+  for (int g = gr.beg; g < gr.end; g += gr.step) {
+    const int first = g * CS, count = min(CS, kp.n - first);
+    const bool inr = slot < count;
+    const int i = first + (inr ? slot : 0);
+    const bool act = inr && gflag[grp_of[i]] == 0;
+    const int len = act ? min(nl_len[i], kp.nl_cap) : 0;
+    int lmax = len;
+    for (int d = 32; d > 0; d >>= 1) lmax = max(lmax, __shfl_xor(lmax, d, kWave));
+    const int32_t* __restrict__ row = nl_idx + (int64_t)i * kp.nl_cap;
+    const int64_t base = (act && idx) ? offsets[i] : 0;
+    int n = 0;  // accepted entries of this slot so far (uniform over the slot's lanes)
+    for (int k0 = 0; k0 < lmax; k0 += LPI) {
+      const int k = k0 + sub;
+      bool hit = false;
+      int j = i;
+      if (k < len) {
+        j = row[k];
+        hit = exact_pair(kp, p.x, p.y, p.z, p.h, i, j, mode == 1) && (mode == 0 || j != i);
+      }
+      const uint64_t b = ballot64(hit);
+      const uint32_t seg = (uint32_t)(b >> (slot * LPI)) & ((1u << LPI) - 1u);
+      if (hit && idx) idx[base + n + __popc(seg & ((1u << sub) - 1u))] = j;
+      n += __popc(seg);
+    }
+    if (inr && sub == 0) counts[i] = act ? n : -1;
   }
 }
 
@@ -3241,14 +3396,36 @@ hipError_t launch_lists(sph_ctx* c, const sph_particles* s) {
   return hipGetLastError();
 }
 
-template <bool MIXED, int CAP>
-static void density_lists_dispatch(sph_ctx* c, const Parts& p) {
+// The list kernels are instantiated per smoothing kernel (Sect. 2.3).
+#define SPH_KIND_SWITCH(KD, BODY) \
+  switch (KD) {                   \
+    case 1: {                     \
+      constexpr int KIND = 1;     \
+      BODY;                       \
+    } break;                      \
+    case 2: {                     \
+      constexpr int KIND = 2;     \
+      BODY;                       \
+    } break;                      \
+    default: {                    \
+      constexpr int KIND = 0;     \
+      BODY;                       \
+    } break;                      \
+  }
+
+template <bool MIXED, int CAP, int KIND>
+static void density_lists_kind(sph_ctx* c, const Parts& p) {
   const dim3 grid(c->walk_blocks), block(64);
   SPH_LPI_SWITCH_LISTS(c->kp.n_group,
-                       hipLaunchKernelGGL((k_density_lists<MIXED, LPI, CAP>), grid, block, 0,
-                                          c->stream, c->kp, p, c->ginfo, c->nl_idx, c->nl_len,
+                       hipLaunchKernelGGL((k_density_lists<MIXED, LPI, CAP, KIND>), grid, block,
+                                          0, c->stream, c->kp, p, c->ginfo, c->nl_idx, c->nl_len,
                                           c->gflag, c->flag_list, c->grp_of, c->xyzm, c->frec,
                                           c->ds));
+}
+
+template <bool MIXED, int CAP>
+static void density_lists_dispatch(sph_ctx* c, const Parts& p) {
+  SPH_KIND_SWITCH(c->kp.kernel, (density_lists_kind<MIXED, CAP, KIND>(c, p)));
 }
 
 hipError_t launch_density_lists(sph_ctx* c, const sph_particles* s) {
@@ -3297,25 +3474,41 @@ hipError_t launch_force(sph_ctx* c, const sph_particles* s, bool step_mode, bool
                                            : force_dispatch<false>(c, s, o[0], o[1], o[2], o[3], gf);
 }
 
+template <bool MIXED, int KIND>
+static void force_lists_kind(sph_ctx* c, const Parts& p, double* const* o) {
+  const dim3 grid(c->walk_blocks), block(64);
+  SPH_LPI_SWITCH_LISTS(c->kp.n_group,
+                       hipLaunchKernelGGL((k_force_lists<MIXED, LPI, KIND>), grid, block, 0,
+                                          c->stream, c->kp, p, c->ginfo, c->frec, c->nl_idx,
+                                          c->nl_len, c->gflag, c->grp_of, o[0], o[1], o[2], o[3],
+                                          c->ds));
+}
+
 hipError_t launch_force_lists(sph_ctx* c, const sph_particles* s, bool step_mode) {
   c->kp.n = c->n;
   double* o[4];
   force_outputs(c, s, step_mode, o);
   const Parts p = parts_of(s);
-  const dim3 grid(c->walk_blocks), block(64);
   if (c->kp.precision == SPH_PREC_MIXED) {
-    SPH_LPI_SWITCH_LISTS(c->kp.n_group,
-                         hipLaunchKernelGGL((k_force_lists<true, LPI>), grid, block, 0,
-                                            c->stream, c->kp, p, c->ginfo, c->frec, c->nl_idx,
-                                            c->nl_len, c->gflag, c->grp_of, o[0], o[1], o[2], o[3],
-                                            c->ds));
+    SPH_KIND_SWITCH(c->kp.kernel, (force_lists_kind<true, KIND>(c, p, o)));
   } else {
-    SPH_LPI_SWITCH_LISTS(c->kp.n_group,
-                         hipLaunchKernelGGL((k_force_lists<false, LPI>), grid, block, 0,
-                                            c->stream, c->kp, p, c->ginfo, c->frec, c->nl_idx,
-                                            c->nl_len, c->gflag, c->grp_of, o[0], o[1], o[2], o[3],
-                                            c->ds));
+    SPH_KIND_SWITCH(c->kp.kernel, (force_lists_kind<false, KIND>(c, p, o)));
   }
+  return hipGetLastError();
+}
+
+// Each particle's pairs among its list row that pass the exact FP64
+// predicate at the h in p->h (mode 0: density set, self included; 1: force
+// set): counts, and the indices at offsets[i] when idx is given.
+hipError_t launch_row_sets(sph_ctx* c, const sph_particles* s, int mode, int32_t* counts,
+                           int32_t* idx, const int64_t* offsets) {
+  c->kp.n = c->n;
+  const Parts p = parts_of(s);
+  const dim3 grid(c->walk_blocks), block(64);
+  SPH_LPI_SWITCH_LISTS(c->kp.n_group,
+                       hipLaunchKernelGGL((k_row_sets<LPI>), grid, block, 0, c->stream, c->kp, p,
+                                          mode, c->nl_idx, c->nl_len, c->gflag, c->grp_of,
+                                          counts, idx, offsets));
   return hipGetLastError();
 }
 

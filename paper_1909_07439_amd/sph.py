@@ -109,6 +109,7 @@ def load() -> ctypes.CDLL:
         lib.sph_get_tree.argtypes = [vp, P(i64), vp, vp, vp, vp, vp, vp]
         lib.sph_get_groups.argtypes = [vp, P(i64), vp, vp]
         lib.sph_neighbours.argtypes = [vp, P(sph_particles), i32, vp, vp, i64]
+        lib.sph_list_pairs.argtypes = [vp, P(sph_particles), i32, vp, vp, i64]
         lib.sph_timings.argtypes = [vp, P(d)]
         lib.sph_set_timing.argtypes = [vp, i32]
         lib.sph_stats.argtypes = [vp, P(i64)]
@@ -118,7 +119,8 @@ def load() -> ctypes.CDLL:
         lib.sph_last_error.restype = ctypes.c_char_p
         for name in ("sph_create", "sph_build_tree", "sph_density", "sph_force", "sph_step",
                      "sph_reduce", "sph_check", "sph_get_keys", "sph_get_tree",
-                     "sph_get_groups", "sph_neighbours", "sph_timings", "sph_set_timing",
+                     "sph_get_groups", "sph_neighbours", "sph_list_pairs", "sph_timings",
+                     "sph_set_timing",
                      "sph_stats",
                      "sph_eval_adjoint", "sph_step_adjoint"):
             getattr(lib, name).restype = ctypes.c_int
@@ -324,6 +326,19 @@ def sph_neighbours(ctx: Context, p: Particles, mode: int):
     idx = np.empty(max(total, 1), np.int32)
     _check(ctx.h, ctx.lib.sph_neighbours(ctx.h, ctypes.byref(p.c), int(mode), off.ctypes.data,
                                          idx.ctypes.data, total), "sph_neighbours")
+    return off, idx[:total]
+
+
+def sph_list_pairs(ctx: Context, p: Particles, mode: int):
+    """Pairs the hot path's density (0) or force (1) kernel accepts, as
+    (offsets, indices) over the current particle order."""
+    off = np.empty(p.n + 1, np.int64)
+    _check(ctx.h, ctx.lib.sph_list_pairs(ctx.h, ctypes.byref(p.c), int(mode), off.ctypes.data,
+                                         None, 0), "sph_list_pairs")
+    total = int(off[-1])
+    idx = np.empty(max(total, 1), np.int32)
+    _check(ctx.h, ctx.lib.sph_list_pairs(ctx.h, ctypes.byref(p.c), int(mode), off.ctypes.data,
+                                         idx.ctypes.data, total), "sph_list_pairs")
     return off, idx[:total]
 
 
