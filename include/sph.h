@@ -158,6 +158,21 @@ sph_status sph_step(sph_ctx* ctx, sph_particles* p, double dt, double* dt_next_o
    conservation of the pair forms of eq:acc and eq:energy.  Synchronises. */
 sph_status sph_reduce(sph_ctx* ctx, const sph_particles* p, double out[12]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid allocation): the sums
+   of sph_reduce without a context.  The per-block partial sums and the
+   results live in one file-scope device array of the library (49,280 bytes
+   on each GPU it runs on, held until the process ends); the call allocates
+   nothing.  Every call on a GPU uses that GPU's array, so calls that overlap
+   on one GPU (several host threads or streams) race; calls in sequence do
+   not (each writes every partial before reading it).  p: n in [1, 2^31 - 1],
+   and m, vx, vy, vz, u, ax, ay, az, dudt (device arrays of the current
+   device).  stream: a hipStream_t of the current device (NULL = default).
+   out: HOST array of 12 doubles, the values of sph_reduce bit for bit.
+   Synchronises the stream.  Errors: SPH_E_ARG (NULL pointers, n out of
+   range, a missing field), SPH_E_HIP; sph_last_error(NULL) describes them. */
+sph_status sph_reduce_noalloc(const sph_particles* p, void* stream, double out[12]);
+
 /* Device error word of the last calls, as a status (SPH_OK if clean); clears
    it.  Synchronises. */
 sph_status sph_check(sph_ctx* ctx);

@@ -605,6 +605,23 @@ sph_status sph_reduce(sph_ctx* c, const sph_particles* p, double out[12]) {
   return SPH_OK;
 }
 
+sph_status sph_reduce_noalloc(const sph_particles* p, void* stream, double out[12]) {
+  auto reject = [](const char* why) {
+    g_create_err = std::string("sph_reduce_noalloc: ") + why;
+    return SPH_E_ARG;
+  };
+  if (!p || !out) return reject("particles or out is NULL");
+  if (p->n < 1 || p->n > (int64_t)0x7fffffff) return reject("n must be in [1, 2^31 - 1]");
+  if (!p->m || !p->vx || !p->vy || !p->vz || !p->u || !p->ax || !p->ay || !p->az || !p->dudt)
+    return reject("m, vx, vy, vz, u, ax, ay, az and dudt are required");
+  const hipError_t e = sph::reduce_noalloc(p, (hipStream_t)stream, out);
+  if (e != hipSuccess) {
+    g_create_err = std::string("sph_reduce_noalloc: ") + hipGetErrorString(e);
+    return SPH_E_HIP;
+  }
+  return SPH_OK;
+}
+
 sph_status sph_check(sph_ctx* c) {
   if (!c) return SPH_E_ARG;
   return sync_state(c, true);

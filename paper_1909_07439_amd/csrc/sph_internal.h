@@ -140,6 +140,7 @@ hipError_t launch_row_sets(sph_ctx* c, const sph_particles* p, int mode, int32_t
 hipError_t launch_force(sph_ctx* c, const sph_particles* p, bool step_mode, bool flagged_only);
 hipError_t launch_correct(sph_ctx* c, const sph_particles* p);
 hipError_t launch_reduce(sph_ctx* c, const sph_particles* p, double* dev_out);
+hipError_t reduce_noalloc(const sph_particles* p, hipStream_t stream, double* out);
 hipError_t launch_neighbours(sph_ctx* c, const sph_particles* p, int mode, int32_t* counts,
                              const int64_t* offsets, int32_t* idx);
 // implemented in sph_adjoint.hip

@@ -11,6 +11,8 @@
 // Built with -ffp-contract=off: every fused multiply-add is an explicit fma().
 #include <math.h>
 
+#include <mutex>
+
 #include <type_traits>
 
 #include "sph_ctx.h"
@@ -3176,6 +3178,42 @@ __global__ void k_reduce_final(const double* __restrict__ part, double* __restri
 }
 
 // ============================================================================
+// Allocation-free reduction: the partial sums of k_reduce_part and the 12
+// results of k_reduce_final in a file-scope device array instead of context
+// scratch.  Each GPU the library runs on holds its own copy, until the
+// process ends.  Host code never passes the array's name to a kernel or a
+// copy: it takes the array's device address on each device once
+// (hipGetSymbolAddress, with that device current) and uses that address.
+// ============================================================================
+constexpr int kRedScratch = kRedBlocks * 12 + 16;  // doubles: partials, then the 12 sums
+static __device__ __align__(256) double scratch[kRedScratch];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of `scratch` on the current device (looked up on the first
+// call there).
+static hipError_t scratch_address(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// ============================================================================
 // Host-side launchers
 // ============================================================================
 static Parts parts_of(const sph_particles* s) {
@@ -3526,6 +3564,24 @@ hipError_t launch_correct(sph_ctx* c, const sph_particles* s) {
   hipLaunchKernelGGL(k_correct, dim3(stream_blocks(c->n)), dim3(256), 0, c->stream, parts_of(s),
                      c->n, c->a1, (int64_t)c->n_max, c->ds);
   return hipGetLastError();
+}
+
+// The sums of launch_reduce with the partials in `scratch` (its device
+// address on the current device), copied into the host array out; the
+// stream is synchronised.  Allocates nothing.
+hipError_t reduce_noalloc(const sph_particles* s, hipStream_t stream, double* out) {
+  double* base = nullptr;
+  hipError_t e = scratch_address(&base);
+  if (e != hipSuccess) return e;
+  double* part = base;
+  double* res = base + kRedBlocks * 12;
+  hipLaunchKernelGGL(k_reduce_part, dim3(kRedBlocks), dim3(256), 0, stream, parts_of(s),
+                     (int)s->n, part);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, stream, part, res);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(out, res, 12 * sizeof(double), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  return e;
 }
 
 hipError_t launch_reduce(sph_ctx* c, const sph_particles* s, double* dev_out) {

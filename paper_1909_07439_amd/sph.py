@@ -104,6 +104,7 @@ def load() -> ctypes.CDLL:
         lib.sph_force.argtypes = [vp, P(sph_particles), P(d)]
         lib.sph_step.argtypes = [vp, P(sph_particles), d, P(d)]
         lib.sph_reduce.argtypes = [vp, P(sph_particles), P(d)]
+        lib.sph_reduce_noalloc.argtypes = [P(sph_particles), vp, P(d)]
         lib.sph_check.argtypes = [vp]
         lib.sph_get_keys.argtypes = [vp, vp, vp]
         lib.sph_get_tree.argtypes = [vp, P(i64), vp, vp, vp, vp, vp, vp]
@@ -118,7 +119,8 @@ def load() -> ctypes.CDLL:
         lib.sph_last_error.argtypes = [vp]
         lib.sph_last_error.restype = ctypes.c_char_p
         for name in ("sph_create", "sph_build_tree", "sph_density", "sph_force", "sph_step",
-                     "sph_reduce", "sph_check", "sph_get_keys", "sph_get_tree",
+                     "sph_reduce", "sph_reduce_noalloc", "sph_check", "sph_get_keys",
+                     "sph_get_tree",
                      "sph_get_groups", "sph_neighbours", "sph_list_pairs", "sph_timings",
                      "sph_set_timing",
                      "sph_stats",
@@ -281,6 +283,21 @@ def sph_step(ctx: Context, p: Particles, dt: float = 0.0, want_dt: bool = False)
 def sph_reduce(ctx: Context, p: Particles) -> np.ndarray:
     out = (ctypes.c_double * 12)()
     _check(ctx.h, ctx.lib.sph_reduce(ctx.h, ctypes.byref(p.c), out), "sph_reduce")
+    return np.array(out[:])
+
+
+def sph_reduce_noalloc(p: Particles, stream=None) -> np.ndarray:
+    """sph_reduce without a context (the library's allocation-free entry
+    point); on the current torch stream unless one is given."""
+    import torch
+
+    lib = load()
+    s = torch.cuda.current_stream() if stream is None else stream
+    out = (ctypes.c_double * 12)()
+    st = lib.sph_reduce_noalloc(ctypes.byref(p.c), ctypes.c_void_p(s.cuda_stream), out)
+    if st != 0:
+        msg = lib.sph_last_error(None)
+        raise SphError(st, f"sph_reduce_noalloc: {msg.decode() if msg else ''}")
     return np.array(out[:])
 
 
