@@ -763,7 +763,10 @@ int orc_density_sel(int64_t n, const double* x, const double* y, const double* z
       double h = h_in[i];
       int it = 0, done = 0, need_bisect = 0, s = ORC_OK;
       if (!(h > 0.0) || !(m[i] > 0.0)) s = ORC_E_ARG;
-      int passes = fixed ? 3 : max_it;
+      /* fixed passes (Sect. 3.2.1: the density is computed three times):   */
+      /* two clamped Newton updates from the sums at h0 and h1, then the    */
+      /* third sum at h2 below gives rho and Omega                          */
+      int passes = fixed ? 2 : max_it;
       for (it = 0; it < passes && s == ORC_OK; ++it) {
         double S0, S1;
         s = dens_sums(&c, i, h, &S0, &S1, NULL);

@@ -1776,7 +1776,9 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
             hn = 1.2 * h;
           else if (hn < 0.8 * h)
             hn = 0.8 * h;
-          conv = (nit + 1) >= 3;
+          // three density computations (Sect. 3.2.1): two updates, then
+          // rho and Omega from the third sum at the h it used
+          conv = (nit + 1) >= 2;
           moved = true;
         } else if (fabs(f) <= 3.0 * kp.h_tol * rh) {
           // |f| / f' <= tol h (f' = 3 rho_h Omega / h): converged at this h
@@ -2663,7 +2665,9 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
             hn = 1.2 * h;
           else if (hn < 0.8 * h)
             hn = 0.8 * h;
-          conv = (nit + 1) >= 3;
+          // three density computations (Sect. 3.2.1): two updates, then
+          // rho and Omega from the third sum at the h it used
+          conv = (nit + 1) >= 2;
           moved = true;
         } else if (fabs(f) <= 3.0 * kp.h_tol * rh) {
           conv = true;

@@ -182,7 +182,7 @@ def test_fixed_three_passes_matches_oracle():
     o = oracle.evaluate(cfg, oracle.make_params(oc))
     for k in ("h", "rho", "omega"):
         assert rel_err(g[k], o[k]).max() <= FP64_TOL, k
-    assert info["iters"] == 4  # three updates, then the sum at the final h
+    assert info["iters"] == 3  # three density sums: two updates, rho from the third
 
 
 def boundary_particles(cfg, o, delta=1e-5):

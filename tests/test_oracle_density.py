@@ -141,3 +141,59 @@ def test_perfect_lattice_root_other_kernels(kind, wfun, nn_expect):
     assert np.all(o["nneigh"] == int(np.sum(r < S * hs)))
     assert abs(int(np.sum(r < S * hs)) - nn_expect) <= 12
     assert abs(o["rho"].mean() - 1.0) < 3e-3  # each kernel's lattice-sum bias
+
+
+def dwdh_ref(r, h):
+    """dW/dh of the M4 kernel, -(3 f(q) + q f'(q)) / (pi h^4) with f = 1.5 B3
+    and f' from scipy's derivative of the B-spline."""
+    q = np.asarray(r) / h
+    f = 1.5 * np.nan_to_num(B3(q), nan=0.0)
+    fp = 1.5 * np.nan_to_num(B3.derivative()(q), nan=0.0)
+    return -(3.0 * f + q * fp) / (np.pi * h ** 4)
+
+
+@pytest.mark.parametrize("start", [0.93, 1.45, 0.7])
+def test_fixed_passes_recurrence_on_perfect_lattice(start):
+    """The paper's fixed iteration (Sect. 3.2.1: the density is computed three
+    times), read as two Newton updates of h clamped to [0.8 h, 1.2 h] (h kept
+    where f' <= 0) from the sums at h0 and h1, then rho and Omega from the
+    third sum at h2.  The recurrence is run here on the infinite-lattice sums
+    with scipy's B-spline and its derivative; from 1.45 and 0.7 times the root
+    the first steps hit the clamps."""
+    c = inputs.lattice(16, jitter=0.0)
+    dx, m, hf = c["dx"], c["m"][0], c["hfact"]
+    g = np.arange(-6, 7)
+    I, J, K = np.meshgrid(g, g, g, indexing="ij")
+    r = dx * np.sqrt(I ** 2 + J ** 2 + K ** 2).ravel()
+    S0 = lambda h: m * w_ref(r, h).sum()
+    S1 = lambda h: m * dwdh_ref(r, h).sum()
+    root = brentq(lambda h: S0(h) - m * (hf / h) ** 3, 0.8 * dx, 1.6 * dx, xtol=1e-16,
+                  rtol=1e-15)
+    h = start * root
+    h0 = h
+    clamped = 0
+    for _ in range(2):
+        rh = m * (hf / h) ** 3
+        f, fp = S0(h) - rh, S1(h) + 3.0 * rh / h
+        hn = h - f / fp
+        if not fp > 0.0:
+            hn = h
+        elif hn > 1.2 * h:
+            hn, clamped = 1.2 * h, clamped + 1
+        elif hn < 0.8 * h:
+            hn, clamped = 0.8 * h, clamped + 1
+        h = hn
+    rho = S0(h)
+    omega = 1.0 + h * S1(h) / (3.0 * rho)
+    oc = dict(c)
+    oc["h_tol_oracle"] = -1.0
+    o = oracle.density(c["x"], c["y"], c["z"], c["m"], np.full(c["n"], h0),
+                       oracle.make_params(oc))
+    np.testing.assert_allclose(o["h"], h, rtol=1e-12)
+    np.testing.assert_allclose(o["rho"], rho, rtol=1e-12)
+    np.testing.assert_allclose(o["omega"], omega, rtol=1e-10)
+    assert np.all(o["iters"] == 2)
+    if start != 0.93:
+        assert clamped >= 1  # the case exercises a clamp
+    else:
+        assert clamped == 0 and abs(h / root - 1) < 1e-3  # two free steps land near the root
