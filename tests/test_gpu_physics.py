@@ -2,7 +2,9 @@
 solution (Sect. 4, Sod test), total energy and momentum over the run
 (Sect. 4.5, eq:energy_error), and several leapfrog steps against the oracle.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -67,8 +69,10 @@ def test_shock_tube_against_exact_solution(precision):
     # Bounds from the measured full-resolution runs (dx_L = 1/512), with a
     # margin: the undisturbed states and the right star state (post-shock)
     # follow the exact solution closely; the fan and the left star state
-    # carry the resolution-independent offset of the M4 kernel on a lattice
-    # stretched along x only (also shown by the oracle at dx_L = 1/128).
+    # carry the offset of the M4 kernel at h_fact 1.2 at the unsmoothed
+    # contact, which the oracle shows too (left star rho +0.044, P +0.060 at
+    # dx_L = 1/128, tests/golden/sod_dx128_t01_regions.json) and which goes
+    # away at h_fact 1.5 (test_shock_tube_regions_match_oracle below).
     assert err["far"][0] < 0.003 and err["far"][2] < 0.003
     assert err["post"][0] < 0.01 and err["post"][2] < 0.02 and err["post"][1] < 0.05
     assert err["fan"][0] < 0.03 and err["fan"][1] < 0.07 and err["fan"][2] < 0.04
@@ -153,3 +157,39 @@ def test_shock_tube_error_with_resolution(kernel):
             f"{float(np.abs(g['rho'][smooth] - r[smooth]).mean()):.5f}, left star "
             f"{float(np.abs(g['rho'][star] - r[star]).mean()):.5f})")
     assert max(out) < 0.03
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "sod_dx128_t01_regions.json")
+
+
+@pytest.mark.parametrize("precision", [sph.SPH_PREC_FP64, sph.SPH_PREC_MIXED],
+                         ids=["fp64", "mixed"])
+@pytest.mark.parametrize("hfact", [1.2, 1.5])
+def test_shock_tube_regions_match_oracle(hfact, precision):
+    """The shock tube at dx_L = 1/128 to t = 0.1 on the GPU against the FP64
+    oracle's run of the same set-up (region means written by
+    tests/golden/make_sod_regions.py from oracle/ alone): the GPU reproduces
+    the oracle's left and right star states, the left-star offset at h_fact
+    1.2 included, and at h_fact 1.5 both star states match the exact
+    solution."""
+    gold = json.load(open(GOLDEN))
+    ref = gold["cases"][f"hfact_{hfact}"]
+    cfg = inputs.sod(dx_left=1.0 / 128, width=1.0 / 8)
+    cfg["h"] = cfg["h"] * hfact / cfg["hfact"]
+    cfg["hfact"] = hfact
+    g, e0, e1, steps = run_to(cfg, precision, 0.1)
+    x = g["x"]
+    say(f"  h_fact {hfact}: {steps} steps (oracle {ref['steps']})")
+    for name, (a, b) in gold["regions"].items():
+        m = (x > a) & (x < b)
+        for q in ("rho", "P", "vx"):
+            gm, om = float(g[q][m].mean()), ref[name][q]
+            scale = max(abs(om), 0.1)
+            say(f"    {name} {q}: gpu {gm:.5f} oracle {om:.5f}")
+            assert abs(gm - om) <= 5e-3 * scale, (name, q)
+    if hfact == 1.5:
+        st = riemann.star_state((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), cfg["gamma"])
+        for name in ("left_star", "right_star"):
+            a, b = gold["regions"][name]
+            m = (x > a) & (x < b)
+            assert abs(g["P"][m].mean() / st["p_star"] - 1) < 0.02, name
