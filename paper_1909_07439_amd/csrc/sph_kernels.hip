@@ -859,7 +859,8 @@ __global__ __launch_bounds__(256) void k_range_boxes(
     const int32_t* __restrict__ nparent, const int32_t* __restrict__ nchild,
     const int32_t* __restrict__ nnchild, WalkNode* __restrict__ wn,
     const int32_t* __restrict__ gfirst, const int32_t* __restrict__ gcount,
-    GroupInfo* __restrict__ gi, const DevState* __restrict__ ds, int mode, int nb_small) {
+    GroupInfo* __restrict__ gi, float4* __restrict__ lrec, const DevState* __restrict__ ds,
+    int mode, int nb_small) {
   if (!h_refresh_needed(ds, mode)) return;
   const int do_bb = mode == 1 ? 1 : 0;
   const int nn = ds->n_nodes, ng = ds->n_groups;
@@ -885,10 +886,19 @@ __global__ __launch_bounds__(256) void k_range_boxes(
         }
         b.hm = fmax(b.hm, h[s]);
       }
-      if (is_node)
+      if (is_node) {
         write_node_box(b, it, f, e, 0, nchild, wn, do_bb);
-      else
+        // each particle relative to its leaf's centre, and h, in FP32: the
+        // mixed list kernel's candidate loads (before a density pass)
+        if (mode != 0) {
+          const double c0 = wn[it].c[0], c1 = wn[it].c[1], c2 = wn[it].c[2];
+          for (int s = f; s < e; ++s)
+            lrec[s] = make_float4((float)(x[s] - c0), (float)(y[s] - c1), (float)(z[s] - c2),
+                                  (float)h[s]);
+        }
+      } else {
         write_group_box(b, it - nn, f, e, gi, do_bb);
+      }
     }
     return;
   }
@@ -1018,7 +1028,7 @@ struct TileOf {
 // global memory (`spill`, kSpill entries per level; search regions much
 // larger than the local particle spacing need it).  Returns false on
 // frontier overflow.
-template <typename RadiusFn, typename FlushFn>
+template <bool WHOLE = true, typename RadiusFn, typename FlushFn>
 __device__ bool group_walk(const WalkNode* __restrict__ nodes, const GroupInfo& G,
                            const KParams& kp, WalkLds& L, int (&front)[2][kFCap],
                            int* __restrict__ spill, RadiusFn open_r, FlushFn flush) {
@@ -1054,8 +1064,9 @@ __device__ bool group_walk(const WalkNode* __restrict__ nodes, const GroupInfo& 
         const double R = open_r(nd);
         open = box_gap2(nd, G, kp) < R * R;
         // an inner node wholly within the radius of every point of the group
-        // box is taken whole, like a leaf: all of its leaves would be opened
-        inside = open && nd.nchild > 0 && box_far2(nd, G, kp) < R * R;
+        // box is taken whole, like a leaf, all of its leaves being opened
+        // (unless WHOLE is false: then only true leaves are listed)
+        inside = WHOLE && open && nd.nchild > 0 && box_far2(nd, G, kp) < R * R;
       }
       const bool leaf = open && (nd.nchild == 0 || inside);
       const bool inner = open && nd.nchild > 0 && !inside;
@@ -2179,7 +2190,8 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
              const GroupInfo* __restrict__ groups, int32_t* __restrict__ nl_idx,
              int32_t* __restrict__ nl_len, int32_t* __restrict__ gflag,
              int32_t* __restrict__ flag_list, int32_t* __restrict__ grp_of,
-             int32_t* __restrict__ walk_spill, DevState* __restrict__ ds) {
+             const float4* __restrict__ lrec, int32_t* __restrict__ walk_spill,
+             DevState* __restrict__ ds) {
   int* __restrict__ spill = walk_spill + (int64_t)blockIdx.x * 2 * kSpill;
   using R = typename std::conditional<MIXED, float, double>::type;
   constexpr int GS = kWave / LPI;  // particles per group at most
@@ -2193,11 +2205,14 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
     int front[2][kFCap];
     struct {
       int first[kSLCapL];
-      int cnt[kSLCapL];
+      int cntbits[kSLCapL];  // particle count | (one bit per group) << 24
     } sl;
   } U;
-  __shared__ int s_sl[kSLCapL];  // leaf node ids of the walk, then one bit per group
+  __shared__ int s_sl[kSLCapL];  // leaf node ids of the walk
   __shared__ double s_hm[kSGL];  // largest hl of each group
+  // FP32 path: the centre of each flushed leaf relative to the group's centre
+  // (folded), added to the candidates' leaf-relative positions
+  __shared__ float s_loff[3][kLCap];
   const int lane = threadIdx.x;
   const int ng = ds->n_groups;
   const int nsg = (ng + kSGL - 1) / kSGL;
@@ -2291,14 +2306,17 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
         nsl += nleaf;
         __syncthreads();
       };
-      if (!group_walk(nodes, SG, kp, L, U.front, spill, sradius, sflush)) sok = false;
+      if (!group_walk<!MIXED>(nodes, SG, kp, L, U.front, spill, sradius, sflush)) sok = false;
       __syncthreads();  // the frontier's LDS becomes the leaf ranges
       ++walks;
     }
     if (sok) {
-      // each leaf against every group's box, with that group's radius
+      // each leaf against every group's box, with that group's radius; a
+      // range of 2^24 particles or more (coincident keys, or a whole inner
+      // node) does not fit beside the bits: the groups then walk on their own
       for (int base = 0; base < nsl; base += kWave) {
         const int k = base + lane;
+        bool big = false;
         if (k < nsl) {
           const WalkNode nd = nodes[s_sl[k]];
           int bits = 0;
@@ -2306,10 +2324,11 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
             const double rg = kp.support * fmax(s_hm[gk], margin * (double)nd.hmax) * (1.0 + 4e-9);
             if (box_gap2(nd, groups[g0 + gk], kp) < rg * rg) bits |= 1 << gk;
           }
+          big = nd.count >= (1 << 24);
           U.sl.first[k] = nd.first;
-          U.sl.cnt[k] = nd.count;
-          s_sl[k] = bits;
+          U.sl.cntbits[k] = (nd.count & 0xffffff) | (bits << 24);
         }
+        if (ballot64(big) != 0ull) sok = false;
       }
       __syncthreads();
     }
@@ -2325,14 +2344,24 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
       auto flush = [&](int nleaf) {
         const int total = leaf_offsets(L, nleaf);
         if (lane == 0) cands += (unsigned long long)total * (unsigned)cnt;
+        if constexpr (MIXED) {
+          for (int l = lane; l < nleaf; l += kWave) {
+            const WalkNode& nd = nodes[L.lnode[l]];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+              s_loff[a][l] = (float)fold(nd.c[a] - G.c[a], kp.len[a], kp.half[a], kp.periodic[a]);
+          }
+          __syncthreads();
+        }
         for (int c0 = 0; c0 < total; c0 += PER * kWave) {
           const int cn = min(PER * kWave, total - c0);
           // resolve this lane's candidates, then issue all their loads
-          int jj[PER];
+          int jj[PER], ll[PER];
 #pragma unroll
           for (int q = 0; q < PER; ++q) {
             const int t = lane + q * kWave;
             jj[q] = -1;
+            ll[q] = 0;
             if (t < cn) {
               const int c = c0 + t;
               int lo = 0, hi = nleaf;
@@ -2344,30 +2373,41 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
                   hi = mid;
               }
               jj[q] = L.lfirst[lo] + (c - L.loff[lo]);
+              ll[q] = lo;
             }
           }
-          double vx[PER], vy[PER], vz[PER], vh[PER];
-#pragma unroll
-          for (int q = 0; q < PER; ++q) {
-            const int j = jj[q] >= 0 ? jj[q] : 0;
-            vx[q] = p.x[j];
-            vy[q] = p.y[j];
-            vz[q] = p.z[j];
-            vh[q] = p.h[j];
-          }
           R cx[PER], cy[PER], cz[PER], ct[PER];
+          if constexpr (MIXED) {
+            // one 16-byte load per candidate: its position relative to its
+            // leaf's centre and its h; the leaf's offset from the group's
+            // centre comes from LDS
+            float4 v[PER];
 #pragma unroll
-          for (int q = 0; q < PER; ++q) {
-            if constexpr (MIXED) {
-              cx[q] = (float)fold(vx[q] - G.c[0], kp.len[0], kp.half[0], kp.periodic[0]);
-              cy[q] = (float)fold(vy[q] - G.c[1], kp.len[1], kp.half[1], kp.periodic[1]);
-              cz[q] = (float)fold(vz[q] - G.c[2], kp.len[2], kp.half[2], kp.periodic[2]);
-            } else {
+            for (int q = 0; q < PER; ++q) v[q] = lrec[jj[q] >= 0 ? jj[q] : 0];
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+              cx[q] = v[q].x + s_loff[0][ll[q]];
+              cy[q] = v[q].y + s_loff[1][ll[q]];
+              cz[q] = v[q].z + s_loff[2][ll[q]];
+              ct[q] = list_thr(supr, marginr * v[q].w);
+            }
+          } else {
+            double vx[PER], vy[PER], vz[PER], vh[PER];
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+              const int j = jj[q] >= 0 ? jj[q] : 0;
+              vx[q] = p.x[j];
+              vy[q] = p.y[j];
+              vz[q] = p.z[j];
+              vh[q] = p.h[j];
+            }
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
               cx[q] = vx[q];
               cy[q] = vy[q];
               cz[q] = vz[q];
+              ct[q] = list_thr(supr, marginr * (R)vh[q]);
             }
-            ct[q] = list_thr(supr, marginr * (R)vh[q]);
           }
           uint64_t vm[PER];  // lanes holding a candidate, per quarter of the tile
 #pragma unroll
@@ -2418,7 +2458,7 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
         int nleaf = 0;
         for (int base = 0; base < nsl; base += kWave) {
           const int k = base + lane;
-          const bool open = k < nsl && ((s_sl[k] >> gk) & 1);
+          const bool open = k < nsl && ((U.sl.cntbits[k] >> (24 + gk)) & 1);
           const uint64_t lb = ballot64(open);
           const int nl = popc64(lb);
           if (nleaf + nl > kLCap) {
@@ -2428,7 +2468,8 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
           if (open) {
             const int pos = nleaf + popc64(lb & lanemask_lt());
             L.lfirst[pos] = U.sl.first[k];
-            L.lcnt[pos] = U.sl.cnt[k];
+            L.lcnt[pos] = U.sl.cntbits[k] & 0xffffff;
+            L.lnode[pos] = s_sl[k];
           }
           nleaf += nl;
           __syncthreads();
@@ -2449,7 +2490,7 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
           ngl += nleaf;
           __syncthreads();
         };
-        if (!group_walk(nodes, G, kp, L, U.front, spill, radius, gflush)) gok = false;
+        if (!group_walk<!MIXED>(nodes, G, kp, L, U.front, spill, radius, gflush)) gok = false;
         __syncthreads();
         ++walks;
         if (gok) list_walk(nodes, s_sl, ngl, G, kp, L, radius, flush);
@@ -3355,7 +3396,7 @@ static hipError_t node_props(sph_ctx* c, const sph_particles* s, int mode) {
   hipLaunchKernelGGL(k_range_boxes, dim3(nb_small + nb_inner), dim3(256), 0, c->stream, s->x,
                      s->y, s->z, s->h, n, c->chunk_box, c->node_first, c->node_count,
                      c->node_parent, c->node_child, c->node_nchild, c->wnode, c->grp_first,
-                     c->grp_count, c->ginfo, c->ds, flag, nb_small);
+                     c->grp_count, c->ginfo, c->lrec, c->ds, flag, nb_small);
   return hipGetLastError();
 }
 
@@ -3426,14 +3467,14 @@ hipError_t launch_lists(sph_ctx* c, const sph_particles* s) {
     SPH_LPI_SWITCH_LISTS(c->kp.n_group,
                          hipLaunchKernelGGL((k_lists<true, LPI>), grid, block, 0, c->stream,
                                             c->kp, p, c->wnode, c->ginfo, c->nl_idx, c->nl_len,
-                                            c->gflag, c->flag_list, c->grp_of, c->walk_spill,
-                                            c->ds));
+                                            c->gflag, c->flag_list, c->grp_of, c->lrec,
+                                            c->walk_spill, c->ds));
   } else {
     SPH_LPI_SWITCH_LISTS(c->kp.n_group,
                          hipLaunchKernelGGL((k_lists<false, LPI>), grid, block, 0, c->stream,
                                             c->kp, p, c->wnode, c->ginfo, c->nl_idx, c->nl_len,
-                                            c->gflag, c->flag_list, c->grp_of, c->walk_spill,
-                                            c->ds));
+                                            c->gflag, c->flag_list, c->grp_of, c->lrec,
+                                            c->walk_spill, c->ds));
   }
   return hipGetLastError();
 }
