@@ -4,8 +4,10 @@
 One step = one pass of the whole hot path through the C ABI (sph_step):
 leapfrog predict, Morton keys, radix sort, permute, tree + groups, density
 with the smoothing-length iteration, force, correct, Courant dt.  The default
-workload is the 3D shock tube (294,912 particles, mixed FP32/FP64 pairs);
-the same steps are also timed in FP64 to give the mixed/FP64 ratio.
+workload is the largest single-GPU configuration, the turbulent box (256^3 =
+16,777,216 particles, mixed FP32/FP64 pairs); the same steps are also timed
+in FP64 to give the mixed/FP64 ratio, and the adjoint of one step of the same
+box is timed against that step.
 
 Prints ONE JSON line (the last line of stdout).  ``value`` is
 particle-updates/s = N * steps / wall time of the timed steps, with the state
@@ -14,7 +16,10 @@ among the neighbour-list, density and force kernels, from its algorithmic
 FLOPs and its mean launch time measured with HIP events on the library
 stream (recorded on every 8th timed step); ``other_kernel_rooflines`` holds
 the other two.
-``cpu_baseline`` times the FP64 CPU oracle on the host cores.
+``cpu_baseline`` times the FP64 CPU oracle on the host cores: one full
+evaluation of the workload on every core, whose fields also give the mixed
+path's error per quantity against the oracle; and one thread on the same
+recipe at 64^3.
 """
 from __future__ import annotations
 
@@ -40,10 +45,12 @@ FORCE_FLOPS_PER_PAIR = {0: 85, 1: 103, 2: 97}
 #   density pair term per smoothing-length pass: q 1, f and f' (M4 14, M6 25,
 #   C6 22), two accumulations 7
 DENSITY_FLOPS_PER_PAIR_SUM = {0: 22, 1: 33, 2: 30}
-#   candidate test of the neighbour-list kernel: separation 3, r^2 5, list
+#   distance test of the neighbour-list kernel: separation 3, r^2 5, list
 #   radius 2 max(hl_i, h_margin h_j) 3, its square with the FP32 guard 2,
-#   compare 1
-LIST_FLOPS_PER_CANDIDATE = 14
+#   compare 1.  Its algorithmic work is one test per row entry (a pair within
+#   the list radius); the candidates the walk's leaves bring in beyond those
+#   are waste, reported as tests per row entry and per force pair.
+LIST_FLOPS_PER_ENTRY = 14
 #   adjoint force pair (k_adj_force, per ordered pair (k, j), both the term of
 #   a_k and the mirror term of a_j): geometry and predicate 17, r and e 5,
 #   w 8, F, F_r, F_h at h_k and h_j 47, viscosity speeds and T, dT/dw 24,
@@ -69,6 +76,8 @@ def workload(name: str):
         return inputs.kelvin_helmholtz(100)
     if name == "turb":
         return inputs.turbulent_box(256)
+    if name == "turb64":
+        return inputs.turbulent_box(64)
     if name == "blast":
         return inputs.blast_wave()
     if name == "sedov":
@@ -95,8 +104,8 @@ def run(cfg, precision, steps, warmup):
     ctx = sph.Context(p, cfg["n"])
     sph.sph_build_tree(ctx, parts)
     sph.sph_density(ctx, parts, want_iters=True)
-    sph.sph_force(ctx, parts, want_dt=True)
-    init = parts.numpy("id", "rho", "h", "ax", "ay", "az", "dudt")
+    dt0 = sph.sph_force(ctx, parts, want_dt=True)
+    init = parts.numpy("id", "rho", "h", "omega", "ax", "ay", "az", "dudt", "vsig_dt")
     sph.sph_set_timing(ctx, TIMING_EVERY)
     for _ in range(warmup):
         sph.sph_step(ctx, parts, 0.0)
@@ -127,7 +136,7 @@ def run(cfg, precision, steps, warmup):
     n = cfg["n"]
     order = np.argsort(init["id"])
     return dict(wall=wall, rate=n * steps / wall, ms_per_step=1e3 * wall / steps, timings=tim,
-                stats=st, energy=e, init={k: v[order] for k, v in init.items()})
+                stats=st, energy=e, init={k: v[order] for k, v in init.items()}, dt0=dt0)
 
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1909_07439_amd", "csrc", "sph_kernels.hip")
@@ -263,36 +272,63 @@ def adjoint_cost(precision, cfg=None, K=8, reps=3):
             if tim.get("adjoint_force", 0.0) > 0 else None}
 
 
-def cpu_baseline(cfg, budget_s=12.0):
+def cpu_baseline(cfg):
+    """The FP64 oracle on the host cores: one full evaluation (tree, density
+    iterated to the root, force) of the workload on every core, and one
+    thread on the same recipe at 64^3 (a full evaluation of the big box on one
+    thread would take minutes).  Returns the baseline record and the oracle's
+    fields of the full evaluation (by original index)."""
     import oracle
 
     p = oracle.make_params(cfg)
-    reps, t = 0, 0.0
-    t0 = time.perf_counter()
-    while reps < 1 or (t < budget_s and reps < 20):
-        oracle.evaluate(cfg, p)
-        reps += 1
-        t = time.perf_counter() - t0
     cores = oracle.num_threads()
-    out = dict(value=cfg["n"] * reps / t, unit="particle-updates/s", cores=cores,
-               kind="oracle",
-               sample=f"{reps} full FP64 evaluation(s) (tree, density iterated to the root, "
-                      f"force) of the {cfg['workload']} workload, N={cfg['n']}, {t:.1f} s")
-    # one thread: a single evaluation
-    oracle.set_num_threads(1)
-    t1 = time.perf_counter()
-    oracle.evaluate(cfg, p)
-    out["value_1thread"] = cfg["n"] / (time.perf_counter() - t1)
-    oracle.set_num_threads(cores)
-    return out
+    t0 = time.perf_counter()
+    o = oracle.evaluate(cfg, p)
+    t = time.perf_counter() - t0
+    out = dict(value=cfg["n"] / t, unit="particle-updates/s", cores=cores, kind="oracle",
+               sample=f"one full FP64 evaluation (tree, density iterated to the root, force) of "
+                      f"the {cfg['workload']} workload, N={cfg['n']}, on {cores} threads: {t:.1f} s")
+    small = workload("turb64") if cfg["workload"].startswith("turb") else None
+    if small is not None:
+        oracle.set_num_threads(1)
+        t1 = time.perf_counter()
+        oracle.evaluate(small, oracle.make_params(small))
+        t1 = time.perf_counter() - t1
+        oracle.set_num_threads(cores)
+        out["value_1thread"] = small["n"] / t1
+        out["sample_1thread"] = (f"one full FP64 evaluation of the same recipe at 64^3 "
+                                 f"(N={small['n']}) on 1 thread: {t1:.1f} s")
+    return out, o
+
+
+def mixed_vs_oracle(init, dt0, o, c_cour):
+    """Largest error of the mixed path's first evaluation against the FP64
+    oracle, per quantity (h, rho, Omega relative; a and du/dt relative to the
+    sum of the magnitudes of their pair terms; vsig_dt relative; the Courant
+    dt relative) and the RMS of the same."""
+    import numpy as np
+
+    def rel(a, b):
+        return np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+
+    res = {}
+    for k in ("h", "rho", "omega", "vsig_dt"):
+        e = rel(init[k], o[k])
+        res[k] = {"max": float(e.max()), "rms": float(np.sqrt(np.mean(e * e)))}
+    ea = np.maximum.reduce([np.abs(init[k] - o[k]) / o["anorm"] for k in ("ax", "ay", "az")])
+    eu = np.abs(init["dudt"] - o["dudt"]) / np.maximum(o["unorm"], 1e-300)
+    res["a_over_anorm"] = {"max": float(ea.max()), "rms": float(np.sqrt(np.mean(ea * ea)))}
+    res["dudt_over_unorm"] = {"max": float(eu.max()), "rms": float(np.sqrt(np.mean(eu * eu)))}
+    res["dt"] = abs(dt0 - o["dt_next"]) / o["dt_next"]
+    return res
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="sod")
+    ap.add_argument("--workload", default="turb")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -302,10 +338,10 @@ def main():
                     help="smoothing kernel (M4 cubic, M6 quintic, Wendland C6)")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the rollout-gradient cost on the adjoint workload")
-    ap.add_argument("--adjoint-on-workload", action="store_true",
-                    help="measure the gradient cost of ONE step of the bench workload itself "
-                         "(e.g. the final step of the turbulent box) instead of the 8-step "
-                         "adjoint lattice")
+    ap.add_argument("--adjoint-lattice", action="store_true",
+                    help="measure the gradient cost of the 8-step rollout on the 64^3 adjoint "
+                         "lattice instead of ONE step of the bench workload itself (the final "
+                         "step of the turbulent box by default)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run a plain streaming kernel over MIB MiB "
                          "(scale for PMC byte counters)")
@@ -355,10 +391,14 @@ def main():
     kernels = [(tim["density"], dens), (tim["force"], force)]
     if lists:
         lpl = st["list_candidates_per_launch"]
-        kernels.append((tim["lists"], roofline(
-            f"k_lists<{tag}>", LIST_FLOPS_PER_CANDIDATE * lpl, tim["lists"],
-            {"candidate_tests": lpl}, LIST_FLOPS_PER_CANDIDATE,
-            traffic_record("k_lists", cfg, tag))))
+        # row entries written per launch = the entries the force kernel reads
+        rpl = st["force_candidates"]
+        rl = roofline(f"k_lists<{tag}>", LIST_FLOPS_PER_ENTRY * rpl, tim["lists"],
+                      {"row_entries": rpl}, LIST_FLOPS_PER_ENTRY,
+                      traffic_record("k_lists", cfg, tag))
+        rl["candidate_tests_per_row_entry"] = lpl / max(rpl, 1)
+        rl["candidate_tests_per_force_pair"] = lpl / max(fpl, 1)
+        kernels.append((tim["lists"], rl))
     # the dominant kernel (longest mean launch) carries the headline roofline
     kernels.sort(key=lambda kv: -kv[0])
     roof = kernels[0][1]
@@ -398,6 +438,7 @@ def main():
     }
     if other is not None:
         out["fp64_value"] = other["rate"]
+        out["fp64_ms_per_step"] = other["ms_per_step"]
         out["mixed_over_fp64"] = main_run["rate"] / other["rate"]
         out["fp64_phase_ms"] = {k: round(v, 5) for k, v in other["timings"].items()}
         a, b = main_run["init"], other["init"]
@@ -410,15 +451,20 @@ def main():
                                       / scale),
         }
     if not args.no_adjoint:
-        if args.adjoint_on_workload:
-            out["adjoint"] = adjoint_cost(prec, cfg=cfg, K=1, reps=2)
-        else:
+        if args.adjoint_lattice:
             out["adjoint"] = adjoint_cost(prec)
+        else:
+            out["adjoint"] = adjoint_cost(prec, cfg=cfg, K=1, reps=2)
         print(f"[bench] adjoint: {out['adjoint']}", flush=True)
     if args.copy_calibration > 0:
         copy_calibration(args.copy_calibration)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg)
+        print("[bench] CPU oracle: one full evaluation on every host core", flush=True)
+        out["cpu_baseline"], o = cpu_baseline(cfg)
+        print(f"[bench] cpu_baseline {out['cpu_baseline']}", flush=True)
+        if prec == sph.SPH_PREC_MIXED:
+            out["mixed_error_vs_oracle"] = mixed_vs_oracle(main_run["init"], main_run["dt0"], o,
+                                                           cfg["c_cour"])
     print(json.dumps(out), flush=True)
 
 
