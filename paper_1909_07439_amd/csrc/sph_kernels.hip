@@ -2213,6 +2213,8 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
   // FP32 path: the centre of each flushed leaf relative to the group's centre
   // (folded), added to the candidates' leaf-relative positions
   __shared__ float s_loff[3][kLCap];
+  // one flag per candidate of a tile: a flushed leaf's range starts there
+  __shared__ alignas(4) uint8_t s_start[PER * kWave];
   const int lane = threadIdx.x;
   const int ng = ds->n_groups;
   const int nsg = (ng + kSGL - 1) / kSGL;
@@ -2353,26 +2355,37 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
           }
           __syncthreads();
         }
+        // leaves hold at least one particle each (tree cells are cut from
+        // the sorted keys), so the leaf of candidate c is the number of leaf
+        // ranges starting at or before c, less one
+        int lt = -1;  // leaf of the candidate before the tile
         for (int c0 = 0; c0 < total; c0 += PER * kWave) {
           const int cn = min(PER * kWave, total - c0);
+          // flag the starts of the leaf ranges within the tile
+          static_assert(PER * kWave % (4 * kWave) == 0, "whole dwords per lane");
+#pragma unroll
+          for (int w = 0; w < PER / 4; ++w) reinterpret_cast<int*>(s_start)[lane + w * kWave] = 0;
+          __syncthreads();
+          for (int l = lt + 1 + lane;; l += kWave) {
+            const int o = l < nleaf ? L.loff[l] - c0 : cn;
+            const bool in = o < cn;
+            if (in && o >= 0) s_start[o] = 1;
+            if (ballot64(in) != ~0ull) break;
+          }
+          __syncthreads();
           // resolve this lane's candidates, then issue all their loads
           int jj[PER], ll[PER];
 #pragma unroll
           for (int q = 0; q < PER; ++q) {
             const int t = lane + q * kWave;
+            const int st = t < cn ? (int)s_start[t] : 0;
+            const uint64_t b = ballot64(st != 0);
+            const int lo = rank_below(b, lt + st);
+            lt += popc64(b);
             jj[q] = -1;
             ll[q] = 0;
             if (t < cn) {
-              const int c = c0 + t;
-              int lo = 0, hi = nleaf;
-              while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (L.loff[mid] <= c)
-                  lo = mid;
-                else
-                  hi = mid;
-              }
-              jj[q] = L.lfirst[lo] + (c - L.loff[lo]);
+              jj[q] = L.lfirst[lo] + (c0 + t - L.loff[lo]);
               ll[q] = lo;
             }
           }
