@@ -24,13 +24,23 @@ namespace sph {
 // ============================================================================
 // Wave / block primitives (wave64)
 // ============================================================================
+// v moved across lanes by a DPP control (row_shr:n = 0x110 + n, row_bcast:15
+// = 0x142, row_bcast:31 = 0x143); lanes without a source, or outside the
+// enabled rows, read 0.  Called with every lane of the wavefront active.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+}
+
+// Inclusive prefix sum over the 64 lanes: Hillis-Steele within each row of
+// 16 lanes, then the row totals carried by the two row broadcasts.
 __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    uint32_t t = __shfl_up(v, d, kWave);
-    if (lane >= d) v += t;
-  }
+  v += dpp_u32<0x111, 0xf>(v);
+  v += dpp_u32<0x112, 0xf>(v);
+  v += dpp_u32<0x114, 0xf>(v);
+  v += dpp_u32<0x118, 0xf>(v);
+  v += dpp_u32<0x142, 0xa>(v);
+  v += dpp_u32<0x143, 0xc>(v);
   return v;
 }
 
