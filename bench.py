@@ -334,6 +334,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-group", type=int, default=None, help="particles per walk group")
     ap.add_argument("--n-leaf", type=int, default=None, help="particles per tree leaf")
+    ap.add_argument("--h-margin", type=float, default=None,
+                    help="neighbour-list reach in units of the support (default 1.1)")
     ap.add_argument("--kernel", default="m4", choices=["m4", "m6", "wc6"],
                     help="smoothing kernel (M4 cubic, M6 quintic, Wendland C6)")
     ap.add_argument("--no-adjoint", action="store_true",
@@ -365,6 +367,8 @@ def main():
         cfg["n_group"] = args.n_group
     if args.n_leaf:
         cfg["n_leaf"] = args.n_leaf
+    if args.h_margin:
+        cfg["h_margin"] = args.h_margin
     prec = sph.SPH_PREC_MIXED if args.precision == "mixed" else sph.SPH_PREC_FP64
     print(f"[bench] workload {cfg['workload']} n={cfg['n']} precision={args.precision} "
           f"steps={args.steps} warmup={args.warmup}", flush=True)
@@ -421,7 +425,8 @@ def main():
                    "precision": args.precision,
                    "kernel": {"m4": "M4", "m6": "M6", "wc6": "Wendland C6"}[args.kernel],
                    "hfact": cfg["hfact"],
-                   "n_leaf": cfg["n_leaf"], "n_group": cfg["n_group"]},
+                   "n_leaf": cfg["n_leaf"], "n_group": cfg["n_group"],
+                   "h_margin": cfg.get("h_margin", 1.1)},
         "roofline": roof,
         "other_kernel_rooflines": others,
         "phase_ms": {k: round(v, 5) for k, v in tim.items()},

@@ -287,37 +287,54 @@ int64_t orc_tree(int64_t n, const uint64_t* skeys, int n_leaf, int64_t cap,
 }
 
 /* Particle groups (Sect. 3.1): chop the curve until each section holds at   */
-/* most n_group particles.  A group is a maximal cell with <= n_group        */
-/* particles; a level-21 cell that is still larger (identical keys) is cut   */
-/* into consecutive chunks of n_group.  Emitted in key order.                */
+/* most n_group particles.  The chopped cells with <= n_group particles are  */
+/* the group cells; consecutive group cells that are children of the same    */
+/* parent are then packed, in curve order and greedily, into sections of at  */
+/* most n_group particles (a child that is chopped further ends a pack).  A   */
+/* level-21 cell that is still larger (identical keys) is cut into            */
+/* consecutive chunks of n_group.  Emitted in key order.                     */
+static int64_t emit_group(int64_t a, int64_t c, int64_t cap, int64_t nn, int64_t* first,
+                          int64_t* count) {
+  if (nn < 0) return nn;
+  if (nn >= cap) return ORC_E_OVERFLOW;
+  first[nn] = a;
+  count[nn] = c;
+  return nn + 1;
+}
+
 static int64_t groups_rec(const uint64_t* skeys, int64_t a, int64_t c, int l,
                           int n_group, int64_t cap, int64_t nn, int64_t* first,
                           int64_t* count) {
   if (nn < 0) return nn;
-  if (c <= n_group) {
-    if (nn >= cap) return ORC_E_OVERFLOW;
-    first[nn] = a;
-    count[nn] = c;
-    return nn + 1;
-  }
+  if (c <= n_group) return emit_group(a, c, cap, nn, first, count);
   if (l == ORC_KEY_LEVELS) {
-    for (int64_t s = a; s < a + c; s += n_group) {
-      if (nn >= cap) return ORC_E_OVERFLOW;
-      first[nn] = s;
-      count[nn] = (a + c - s < n_group) ? (a + c - s) : n_group;
-      ++nn;
-    }
+    for (int64_t s = a; s < a + c; s += n_group)
+      nn = emit_group(s, (a + c - s < n_group) ? (a + c - s) : n_group, cap, nn, first, count);
     return nn;
   }
   int64_t e = a + c;
+  int64_t pa = a, pc = 0; /* the open pack of group cells (pc == 0: none) */
   while (a < e) {
     int d = digit_at(skeys[a], l + 1);
     int64_t b = a;
     while (b < e && digit_at(skeys[b], l + 1) == d) ++b;
-    nn = groups_rec(skeys, a, b - a, l + 1, n_group, cap, nn, first, count);
+    if (b - a <= n_group) {
+      if (pc > 0 && pc + (b - a) <= n_group) {
+        pc += b - a;
+      } else {
+        if (pc > 0) nn = emit_group(pa, pc, cap, nn, first, count);
+        pa = a;
+        pc = b - a;
+      }
+    } else {
+      if (pc > 0) nn = emit_group(pa, pc, cap, nn, first, count);
+      pc = 0;
+      nn = groups_rec(skeys, a, b - a, l + 1, n_group, cap, nn, first, count);
+    }
     if (nn < 0) return nn;
     a = b;
   }
+  if (pc > 0) nn = emit_group(pa, pc, cap, nn, first, count);
   return nn;
 }
 

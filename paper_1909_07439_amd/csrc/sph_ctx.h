@@ -64,7 +64,7 @@ struct sph_ctx {
   // tree
   uint8_t* dlev = nullptr;
   uint8_t* lleaf = nullptr;
-  uint8_t* lgrp = nullptr;
+  uint8_t* gsize = nullptr;  // particles of the group starting at each particle (0 elsewhere)
   uint8_t* gstart = nullptr;
   uint32_t* tree_cnt = nullptr;  // kLevels * blocks (level-major), scanned in place
   uint32_t* grp_cnt = nullptr;   // blocks

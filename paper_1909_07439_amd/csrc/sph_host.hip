@@ -255,7 +255,7 @@ sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ct
   ALLOC(c->xyzm, N);
   ALLOC(c->dlev, N);
   ALLOC(c->lleaf, N);
-  ALLOC(c->lgrp, N);
+  ALLOC(c->gsize, N);
   ALLOC(c->gstart, N);
   ALLOC(c->tree_cnt, sph::kLevels * nblk_tree);
   ALLOC(c->grp_cnt, nblk_tree);
@@ -342,7 +342,7 @@ void sph_destroy(sph_ctx* c) {
   }
   void* ptrs[] = {c->keys[0],   c->keys[1],     c->vals[0],      c->vals[1],     c->radix_cnt,
                   c->scan_part, c->scan_total,  c->gtmp,         c->gtmp_id,     c->dlev,
-                  c->lleaf,     c->lgrp,        c->gstart,       c->tree_cnt,    c->grp_cnt,
+                  c->lleaf,     c->gsize,        c->gstart,       c->tree_cnt,    c->grp_cnt,
                   c->node_level, c->node_first, c->node_count,   c->node_parent, c->node_child,
                   c->node_nchild, c->chunk_box, c->wnode,       c->grp_first,
                   c->grp_count, c->ginfo,       c->frec,         c->a1,          c->nb_cnt,

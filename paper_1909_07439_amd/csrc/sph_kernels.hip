@@ -578,11 +578,109 @@ __device__ __forceinline__ int window_level(const uint8_t* d, int idx, int s, in
   return best;
 }
 
+// First index > s whose key leaves the level-l cell of s (galloping search).
+__device__ __forceinline__ int cell_end(const uint64_t* __restrict__ keys, int n, int s, int l) {
+  if (l == 0) return n;
+  const int sh = 3 * (kKeyLevels - l);
+  const uint64_t pre = keys[s] >> sh;
+  int lo = s, step = 1;
+  while (lo + step < n && (keys[lo + step] >> sh) == pre) {
+    lo += step;
+    step <<= 1;
+  }
+  int hi = min(lo + step, n);
+  while (hi - lo > 1) {
+    const int mid = lo + ((hi - lo) >> 1);
+    if ((keys[mid] >> sh) == pre)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return hi;
+}
+
+// End (exclusive) of the level-l cell that starts at c, if that cell holds at
+// most lim particles; -1 if it holds more.
+__device__ __forceinline__ int small_cell_end(const uint64_t* __restrict__ keys, int n, int c,
+                                              int l, int lim) {
+  const int sh = 3 * (kKeyLevels - l);
+  const uint64_t pre = keys[c] >> sh;
+  if (c + lim < n && (keys[c + lim] >> sh) == pre) return -1;
+  int lo = c, hi = min(c + lim, n);  // keys[lo] inside; hi outside the cell (or n)
+  while (hi - lo > 1) {
+    const int mid = lo + ((hi - lo) >> 1);
+    if ((keys[mid] >> sh) == pre)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return hi;
+}
+
+// Start of the level-l cell that ends (exclusive) at e > 0, if that cell
+// holds at most lim particles; -1 if it holds more.
+__device__ __forceinline__ int small_cell_begin(const uint64_t* __restrict__ keys, int e, int l,
+                                                int lim) {
+  const int sh = 3 * (kKeyLevels - l);
+  const uint64_t pre = keys[e - 1] >> sh;
+  if (e - 1 - lim >= 0 && (keys[e - 1 - lim] >> sh) == pre) return -1;
+  int lo = max(e - 1 - lim, -1), hi = e - 1;  // keys[hi] inside; lo outside (or -1)
+  while (hi - lo > 1) {
+    const int mid = lo + ((hi - lo) >> 1);
+    if ((keys[mid] >> sh) == pre)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return hi;
+}
+
+// Groups (Sect. 3.1): the group cells are the chopped cells of at most
+// n_group particles (level lg >= 1, so their parent P holds more).
+// Consecutive children of P that are group cells are packed, in curve order
+// and greedily, into groups of at most n_group particles; a child that is
+// chopped further ends a pack.  For the group cell starting at s: whether a
+// group starts there, and its particle count.  The run of group-cell
+// siblings around s is found from s outwards (at most eight children, each
+// of at most n_group particles), then packed from its first cell.
+__device__ void group_pack(const uint64_t* __restrict__ keys, int n, int s, int lg, int n_group,
+                           bool& start, int& count) {
+  const int shp = 3 * (kKeyLevels - (lg - 1));
+  const uint64_t pp = keys[s] >> shp;
+  int rs = s;  // first particle of the run
+  for (int k = 0; k < 7 && rs > 0 && (keys[rs - 1] >> shp) == pp; ++k) {
+    const int b = small_cell_begin(keys, rs, lg, n_group);
+    if (b < 0) break;  // a chopped sibling
+    rs = b;
+  }
+  int acc = 0;      // particles of the open pack
+  int pstart = -1;  // its first particle
+  start = false;
+  count = 0;
+  for (int c0 = rs; c0 < n && (keys[c0] >> shp) == pp;) {
+    const int c1 = small_cell_end(keys, n, c0, lg, n_group);
+    if (c1 < 0) break;  // a chopped sibling ends the run
+    const int cc = c1 - c0;
+    const bool joins = acc > 0 && acc + cc <= n_group;
+    if (pstart == s && !joins) break;  // the pack that starts at s is complete
+    if (joins) {
+      acc += cc;
+    } else {
+      acc = cc;
+      pstart = c0;
+    }
+    if (c0 == s && pstart != s) return;  // s's cell joined an earlier pack
+    c0 = c1;
+  }
+  start = pstart == s;
+  count = start ? acc : 0;
+}
+
 __global__ __launch_bounds__(256) void k_tree_levels(const uint64_t* __restrict__ keys, int n,
                                                       int n_leaf, int n_group,
                                                       uint8_t* __restrict__ dlev,
                                                       uint8_t* __restrict__ lleaf,
-                                                      uint8_t* __restrict__ lgrp,
+                                                      uint8_t* __restrict__ gsize,
                                                       uint8_t* __restrict__ gstart,
                                                       uint32_t* __restrict__ tree_cnt,
                                                       uint32_t* __restrict__ grp_cnt, int nblk,
@@ -610,16 +708,22 @@ __global__ __launch_bounds__(256) void k_tree_levels(const uint64_t* __restrict_
     const int ll = min(window_level(d, idx, s, n, n_leaf), kKeyLevels);
     const int lg_raw = window_level(d, idx, s, n, n_group);
     bool start;
+    int gcount = 0;
     if (lg_raw <= kKeyLevels) {
-      start = ds <= lg_raw;
+      start = ds <= lg_raw;  // s begins its group cell
+      if (start && lg_raw == 0)
+        gcount = n;  // the whole set is one group
+      else if (start)
+        group_pack(keys, n, s, lg_raw, n_group, start, gcount);
     } else {  // level-21 cell with more than n_group identical keys: cut in chunks
       int a = s;
       while (a > 0 && keys[a - 1] == keys[a]) --a;
       start = ((s - a) % n_group) == 0;
+      if (start) gcount = min(n_group, cell_end(keys, n, s, kKeyLevels) - s);
     }
     dlev[s] = (uint8_t)ds;
     lleaf[s] = (uint8_t)ll;
-    lgrp[s] = (uint8_t)lg_raw;
+    gsize[s] = (uint8_t)gcount;
     gstart[s] = start ? 1 : 0;
     for (int l = ds; l <= ll; ++l) atomicAdd(&lc[l], 1u);
     if (start) atomicAdd(&gc, 1u);
@@ -629,30 +733,9 @@ __global__ __launch_bounds__(256) void k_tree_levels(const uint64_t* __restrict_
   if (threadIdx.x == 0) grp_cnt[blockIdx.x] = gc;
 }
 
-// First index > s whose key leaves the level-l cell of s (galloping search).
-__device__ __forceinline__ int cell_end(const uint64_t* __restrict__ keys, int n, int s, int l) {
-  if (l == 0) return n;
-  const int sh = 3 * (kKeyLevels - l);
-  const uint64_t pre = keys[s] >> sh;
-  int lo = s, step = 1;
-  while (lo + step < n && (keys[lo + step] >> sh) == pre) {
-    lo += step;
-    step <<= 1;
-  }
-  int hi = min(lo + step, n);
-  while (hi - lo > 1) {
-    const int mid = lo + ((hi - lo) >> 1);
-    if ((keys[mid] >> sh) == pre)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return hi;
-}
-
 __global__ __launch_bounds__(256) void k_tree_emit(
     const uint64_t* __restrict__ keys, int n, int n_group, const uint8_t* __restrict__ dlev,
-    const uint8_t* __restrict__ lleaf, const uint8_t* __restrict__ lgrp,
+    const uint8_t* __restrict__ lleaf, const uint8_t* __restrict__ gsize,
     const uint8_t* __restrict__ gstart, const uint32_t* __restrict__ tree_off,
     const uint32_t* __restrict__ grp_off, int nblk, int64_t node_cap,
     int32_t* __restrict__ nlevel, int32_t* __restrict__ nfirst, int32_t* __restrict__ ncount,
@@ -703,15 +786,8 @@ __global__ __launch_bounds__(256) void k_tree_emit(
   for (int q = 0; q < w; ++q) rg += gw[q];
   if (gs) {
     const int g = (int)(grp_off[blockIdx.x] + rg);
-    const int lg = lgrp[s];
-    int cnt;
-    if (lg <= kKeyLevels) {
-      cnt = cell_end(keys, n, s, lg) - s;
-    } else {
-      cnt = min(n_group, cell_end(keys, n, s, kKeyLevels) - s);
-    }
     gfirst[g] = s;
-    gcount[g] = cnt;
+    gcount[g] = gsize[s];
   }
 }
 
@@ -2240,6 +2316,11 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
   const double margin = kp.h_margin;
   const R supr = (R)kp.support, marginr = (R)margin;
   const int cap = kp.nl_cap;
+  float lpf[3], ilpf[3];  // periodic lengths and their inverses in FP32 (0 on open axes)
+  for (int a = 0; a < 3; ++a) {
+    lpf[a] = kp.periodic[a] ? (float)kp.len[a] : 0.f;
+    ilpf[a] = kp.periodic[a] ? (float)kp.inv_len[a] : 0.f;
+  }
   bool flagged = false;
   int nflag = 0;
   unsigned long long cands = 0;
@@ -2356,13 +2437,26 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
       auto flush = [&](int nleaf) {
         const int total = leaf_offsets(L, nleaf);
         if (lane == 0) cands += (unsigned long long)total * (unsigned)cnt;
+        // FP32 path: a candidate's offset from the group centre is its
+        // leaf-relative position plus its leaf's centre offset, folded once
+        // per leaf.  That is the nearest image of every pair unless the
+        // group box, the leaf box and the search radius together reach half
+        // a periodic length on some axis (tiny periodic boxes); then this
+        // flush folds every pair separation instead.
+        bool amb = false;
         if constexpr (MIXED) {
           for (int l = lane; l < nleaf; l += kWave) {
             const WalkNode& nd = nodes[L.lnode[l]];
+            const double rl = radius(nd);
 #pragma unroll
-            for (int a = 0; a < 3; ++a)
-              s_loff[a][l] = (float)fold(nd.c[a] - G.c[a], kp.len[a], kp.half[a], kp.periodic[a]);
+            for (int a = 0; a < 3; ++a) {
+              const double d = fold(nd.c[a] - G.c[a], kp.len[a], kp.half[a], kp.periodic[a]);
+              s_loff[a][l] = (float)d;
+              if (kp.periodic[a] && fabs(d) + (double)nd.w[a] + G.w[a] + rl >= kp.half[a])
+                amb = true;
+            }
           }
+          amb = ballot64(amb) != 0ull;
           __syncthreads();
         }
         // leaves hold at least one particle each (tree cells are cut from
@@ -2437,8 +2531,9 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
           for (int q = 0; q < PER; ++q) vm[q] = ballot64(jj[q] >= 0);
           // particle-major: each particle's values are read from its lane once
           // per tile; its row gets the tile's candidates in order
-          for (int s = 0; s < cnt; ++s) {
-            {
+          auto particles = [&](auto fold_pairs) {
+            constexpr bool FOLD = decltype(fold_pairs)::value;
+            for (int s = 0; s < cnt; ++s) {
               const int ls = l0 + s;
               const R px = lane_val(xq, ls), py = lane_val(yq, ls), pz = lane_val(zq, ls);
               const R pt = lane_val(tq, ls);
@@ -2451,7 +2546,12 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
                   // are masked out afterwards (scalar AND)
                   bool hit;
                   if constexpr (MIXED) {
-                    const float dx = px - cx[q], dy = py - cy[q], dz = pz - cz[q];
+                    float dx = px - cx[q], dy = py - cy[q], dz = pz - cz[q];
+                    if constexpr (FOLD) {
+                      dx = fmaf(-lpf[0], rintf(dx * ilpf[0]), dx);
+                      dy = fmaf(-lpf[1], rintf(dy * ilpf[1]), dy);
+                      dz = fmaf(-lpf[2], rintf(dz * ilpf[2]), dz);
+                    }
                     const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
                     // r2 and the radii are >= 0: their bit patterns order
                     // like their values (an integer max needs no NaN care)
@@ -2472,7 +2572,11 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
               }
               npv = lane == ls ? n : npv;
             }
-          }
+          };
+          if (MIXED && amb)
+            particles(std::true_type{});
+          else
+            particles(std::false_type{});
         }
         __syncthreads();  // L is refilled next
       };
@@ -2567,6 +2671,16 @@ __device__ __forceinline__ GroupRange xcd_groups(int ng) {
 // neighbours) is flagged (gflag = 2) for the walking kernel, and the force
 // pass then walks for every group (leaf_state 2).
 // ============================================================================
+// LDS slot of row entry k of particle slot s in the list density kernel's
+// entry arrays (GS slots per entry).  A lane reads entries k = sub + LPI t, so
+// the 32 lanes of a half-wavefront span 32 / GS consecutive values of sub;
+// flipping the slot's top bit on every other run of 32 / GS entries puts
+// them in 32 distinct banks.
+template <int GS>
+__device__ __forceinline__ int ent_idx(int k, int s) {
+  return k * GS + (s ^ ((GS / 2) * ((k * GS / 32) & 1)));
+}
+
 template <bool MIXED, int LPI, int CAP, int KIND>
 __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
                                                       const GroupInfo* __restrict__ groups,
@@ -2581,7 +2695,7 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
   using R = typename std::conditional<MIXED, float, double>::type;
   constexpr int E = CAP / LPI;  // row entries per lane (CAP = kp.nl_cap)
   constexpr int GS = kWave / LPI;
-  __shared__ R s_r[CAP * GS];  // separation and mass of row entry k of slot s at [k * GS + s]
+  __shared__ R s_r[CAP * GS];  // separation and mass of row entry k of slot s at ent_idx(k, s)
   __shared__ R s_m[CAP * GS];
   const int lane = threadIdx.x;
   const int slot = lane / LPI, sub = lane % LPI;
@@ -2661,11 +2775,11 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
         }
         if constexpr (MIXED) {
           const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-          s_r[k * GS + slot] = fast_sqrt(fmaf(fz, fz, fmaf(fy, fy, fx * fx)));
-          s_m[k * GS + slot] = (float)gm[q];
+          s_r[ent_idx<GS>(k, slot)] = fast_sqrt(fmaf(fz, fz, fmaf(fy, fy, fx * fx)));
+          s_m[ent_idx<GS>(k, slot)] = (float)gm[q];
         } else {
-          s_r[k * GS + slot] = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
-          s_m[k * GS + slot] = gm[q];
+          s_r[ent_idx<GS>(k, slot)] = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
+          s_m[ent_idx<GS>(k, slot)] = gm[q];
         }
       }
     }
@@ -2684,7 +2798,7 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
         const float hinvf = (float)hinv, twohf = (float)(kp.support * h);
         float s0 = 0.f, s1 = 0.f;
         for (int k = sub; k < len; k += LPI) {
-          const float r = s_r[k * GS + slot], m = s_m[k * GS + slot];
+          const float r = s_r[ent_idx<GS>(k, slot)], m = s_m[ent_idx<GS>(k, slot)];
           const float q = r * hinvf;
           float f, df;
           kf_df<KIND, float>(q, f, df);
@@ -2697,7 +2811,7 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
       } else {
         const double twoh = kp.support * h;
         for (int k = sub; k < len; k += LPI) {
-          const double r = s_r[k * GS + slot], m = s_m[k * GS + slot];
+          const double r = s_r[ent_idx<GS>(k, slot)], m = s_m[ent_idx<GS>(k, slot)];
           const double q = r * hinv;
           double f, df;
           kf_df<KIND, double>(q, f, df);
@@ -3389,14 +3503,14 @@ hipError_t launch_tree(sph_ctx* c) {
   const int n = c->n;
   const int nblk = (n + kTreeTile - 1) / kTreeTile;
   hipLaunchKernelGGL(k_tree_levels, dim3(nblk), dim3(256), 0, c->stream, c->keys[0], n,
-                     c->kp.n_leaf, c->kp.n_group, c->dlev, c->lleaf, c->lgrp, c->gstart,
+                     c->kp.n_leaf, c->kp.n_group, c->dlev, c->lleaf, c->gsize, c->gstart,
                      c->tree_cnt, c->grp_cnt, nblk, c->node_nchild, c->node_cap);
   hipError_t e = scan_u32(c, c->tree_cnt, (int64_t)kLevels * nblk, nullptr, &c->ds->n_nodes);
   if (e != hipSuccess) return e;
   e = scan_u32(c, c->grp_cnt, nblk, nullptr, &c->ds->n_groups);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_tree_emit, dim3(nblk), dim3(256), 0, c->stream, c->keys[0], n,
-                     c->kp.n_group, c->dlev, c->lleaf, c->lgrp, c->gstart, c->tree_cnt,
+                     c->kp.n_group, c->dlev, c->lleaf, c->gsize, c->gstart, c->tree_cnt,
                      c->grp_cnt, nblk, c->node_cap, c->node_level, c->node_first,
                      c->node_count, c->node_parent, c->node_child, c->node_nchild,
                      c->grp_first, c->grp_count, c->ds);

@@ -69,6 +69,20 @@ def test_list_pairs_small(cfg, precision):
 
 
 @pytest.mark.parametrize("precision", PREC, ids=PREC_IDS)
+@pytest.mark.parametrize("kind", [1, 0], ids=["m6", "m4"])
+def test_list_pairs_tiny_periodic_box(kind, precision):
+    """A 10^3 periodic lattice with the M6 kernel: a group's box, a leaf's
+    box and the list radius together exceed half the box, so one periodic
+    image per leaf does not serve every pair (the list kernel folds each
+    pair there)."""
+    cfg = inputs.with_kernel(inputs.lattice(10, jitter=0.3, velocities=True, seed_variant=6),
+                             kind)
+    say(f"[sets] {cfg['workload']} kernel {kind} n={cfg['n']} precision={precision}")
+    ctx, parts = run_eval(cfg, precision)
+    compare_sets(ctx, parts, cfg)
+
+
+@pytest.mark.parametrize("precision", PREC, ids=PREC_IDS)
 def test_list_pairs_after_steps(precision):
     """Sets after a few leapfrog steps (disordered positions, h changed
     between the list pass and the force)."""

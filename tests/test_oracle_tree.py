@@ -137,13 +137,37 @@ def test_tree_matches_definition(n, thr, seed, dup):
 
 
 def expected_groups(skeys, thr):
+    """Group cells: the nodes of the chopped tree with <= thr particles;
+    consecutive group cells under one parent are packed greedily into groups
+    of <= thr particles, a child with more particles ending a pack; level-21
+    cells with more (identical keys) are cut into chunks of thr."""
     nodes = expected_tree(skeys, thr)
+    if nodes[0][3] <= thr:
+        return [(0, nodes[0][3])]
+    children = {}
+    for lev, pp, f, c in nodes:
+        if lev > 0:
+            children.setdefault((lev - 1, pp >> 3), []).append((f, c))
     out = []
     for lev, pp, f, c in nodes:
-        if c <= thr:
-            out.append((f, c))
-        elif lev == 21:
+        if c > thr and lev == 21:
             out.extend((s, min(thr, f + c - s)) for s in range(f, f + c, thr))
+        if c <= thr or lev == 21:
+            continue
+        pack = None
+        for cf, cc in sorted(children[(lev, pp)]):
+            if cc > thr:
+                if pack:
+                    out.append(tuple(pack))
+                pack = None
+            elif pack and pack[1] + cc <= thr:
+                pack[1] += cc
+            else:
+                if pack:
+                    out.append(tuple(pack))
+                pack = [cf, cc]
+        if pack:
+            out.append(tuple(pack))
     return sorted(out)
 
 
