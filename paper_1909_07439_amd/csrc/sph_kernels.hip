@@ -599,67 +599,33 @@ __device__ __forceinline__ int cell_end(const uint64_t* __restrict__ keys, int n
   return hi;
 }
 
-// End (exclusive) of the level-l cell that starts at c, if that cell holds at
-// most lim particles; -1 if it holds more.
-__device__ __forceinline__ int small_cell_end(const uint64_t* __restrict__ keys, int n, int c,
-                                              int l, int lim) {
-  const int sh = 3 * (kKeyLevels - l);
-  const uint64_t pre = keys[c] >> sh;
-  if (c + lim < n && (keys[c + lim] >> sh) == pre) return -1;
-  int lo = c, hi = min(c + lim, n);  // keys[lo] inside; hi outside the cell (or n)
-  while (hi - lo > 1) {
-    const int mid = lo + ((hi - lo) >> 1);
-    if ((keys[mid] >> sh) == pre)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return hi;
-}
-
-// Start of the level-l cell that ends (exclusive) at e > 0, if that cell
-// holds at most lim particles; -1 if it holds more.
-__device__ __forceinline__ int small_cell_begin(const uint64_t* __restrict__ keys, int e, int l,
-                                                int lim) {
-  const int sh = 3 * (kKeyLevels - l);
-  const uint64_t pre = keys[e - 1] >> sh;
-  if (e - 1 - lim >= 0 && (keys[e - 1 - lim] >> sh) == pre) return -1;
-  int lo = max(e - 1 - lim, -1), hi = e - 1;  // keys[hi] inside; lo outside (or -1)
-  while (hi - lo > 1) {
-    const int mid = lo + ((hi - lo) >> 1);
-    if ((keys[mid] >> sh) == pre)
-      hi = mid;
-    else
-      lo = mid;
-  }
-  return hi;
-}
-
 // Groups (Sect. 3.1): the group cells are the chopped cells of at most
 // n_group particles (level lg >= 1, so their parent P holds more).
 // Consecutive children of P that are group cells are packed, in curve order
 // and greedily, into groups of at most n_group particles; a child that is
 // chopped further ends a pack.  For the group cell starting at s: whether a
-// group starts there, and its particle count.  The run of group-cell
-// siblings around s is found from s outwards (at most eight children, each
-// of at most n_group particles), then packed from its first cell.
-__device__ void group_pack(const uint64_t* __restrict__ keys, int n, int s, int lg, int n_group,
-                           bool& start, int& count) {
-  const int shp = 3 * (kKeyLevels - (lg - 1));
-  const uint64_t pp = keys[s] >> shp;
+// group starts there, and its particle count.  D(j) is the level at which
+// keys j-1 and j first differ (0 at j <= 0 and j >= n), so j begins a new
+// level-l cell iff D(j) <= l.  The run of group-cell siblings around s is
+// found from s outwards (at most eight children, each of at most n_group
+// particles), then packed from its first cell.
+template <typename DFn>
+__device__ void group_pack(DFn D, int n, int s, int lg, int n_group, bool& start, int& count) {
   int rs = s;  // first particle of the run
-  for (int k = 0; k < 7 && rs > 0 && (keys[rs - 1] >> shp) == pp; ++k) {
-    const int b = small_cell_begin(keys, rs, lg, n_group);
-    if (b < 0) break;  // a chopped sibling
-    rs = b;
+  for (int k = 0; k < 7 && D(rs) > lg - 1; ++k) {
+    int j = rs - 1;  // the previous sibling starts at the last boundary before rs
+    while (j > rs - n_group && D(j) > lg) --j;
+    if (D(j) > lg) break;  // that sibling holds more than n_group particles
+    rs = j;
   }
   int acc = 0;      // particles of the open pack
   int pstart = -1;  // its first particle
   start = false;
   count = 0;
-  for (int c0 = rs; c0 < n && (keys[c0] >> shp) == pp;) {
-    const int c1 = small_cell_end(keys, n, c0, lg, n_group);
-    if (c1 < 0) break;  // a chopped sibling ends the run
+  for (int c0 = rs;;) {
+    int c1 = c0 + 1;
+    while (c1 < n && c1 <= c0 + n_group && D(c1) > lg) ++c1;
+    if (c1 > c0 + n_group) break;  // a chopped sibling ends the run
     const int cc = c1 - c0;
     const bool joins = acc > 0 && acc + cc <= n_group;
     if (pstart == s && !joins) break;  // the pack that starts at s is complete
@@ -671,8 +637,63 @@ __device__ void group_pack(const uint64_t* __restrict__ keys, int n, int s, int 
     }
     if (c0 == s && pstart != s) return;  // s's cell joined an earlier pack
     c0 = c1;
+    if (c0 >= n || D(c0) <= lg - 1) break;  // P ends
   }
   start = pstart == s;
+  count = start ? acc : 0;
+}
+
+// The same packing from 192-bit boundary masks over particles [w0, w0 + 192)
+// (bit p: particle w0 + p begins a cell at the group level, bc, or at the
+// parent level, bp); s sits at bit ps.  For n_group <= 8 every cell the
+// packing of s inspects lies within 64 particles of s.
+__device__ __forceinline__ bool bit3(const uint64_t (&m)[3], int p) {
+  return (m[p >> 6] >> (p & 63)) & 1ull;
+}
+__device__ __forceinline__ int hi_below(const uint64_t (&m)[3], int p) {  // or -1
+  for (int w = p >> 6; w >= 0; --w) {
+    uint64_t v = m[w];
+    if (w == (p >> 6)) v &= (p & 63) ? (~0ull >> (64 - (p & 63))) : 0ull;
+    if (v != 0ull) return w * 64 + 63 - __builtin_clzll(v);
+  }
+  return -1;
+}
+__device__ __forceinline__ int lo_above(const uint64_t (&m)[3], int p) {  // or 192
+  for (int w = (p + 1) >> 6; w < 3; ++w) {
+    uint64_t v = m[w];
+    if (w == ((p + 1) >> 6)) v &= ~0ull << ((p + 1) & 63);
+    if (v != 0ull) return w * 64 + __builtin_ctzll(v);
+  }
+  return 192;
+}
+__device__ void group_pack_masks(const uint64_t (&bc)[3], const uint64_t (&bp)[3], int ps,
+                                 int n_group, bool& start, int& count) {
+  int rs = ps;
+  for (int k = 0; k < 7 && !bit3(bp, rs); ++k) {
+    const int pb = hi_below(bc, rs);
+    if (pb < rs - n_group) break;  // that sibling holds more than n_group particles
+    rs = pb;
+  }
+  int acc = 0, pstart = -1;
+  start = false;
+  count = 0;
+  for (int c0 = rs;;) {
+    const int c1 = lo_above(bc, c0);
+    if (c1 - c0 > n_group) break;  // a chopped sibling ends the run
+    const int cc = c1 - c0;
+    const bool joins = acc > 0 && acc + cc <= n_group;
+    if (pstart == ps && !joins) break;
+    if (joins) {
+      acc += cc;
+    } else {
+      acc = cc;
+      pstart = c0;
+    }
+    if (c0 == ps && pstart != ps) return;
+    c0 = c1;
+    if (bit3(bp, c0)) break;  // P ends
+  }
+  start = pstart == ps;
   count = start ? acc : 0;
 }
 
@@ -702,25 +723,58 @@ __global__ __launch_bounds__(256) void k_tree_levels(const uint64_t* __restrict_
   if (threadIdx.x == 0) gc = 0;
   __syncthreads();
   const int s = base + threadIdx.x;
-  if (s < n) {
-    const int idx = kHalo + threadIdx.x;
-    const int ds = d[idx];
-    const int ll = min(window_level(d, idx, s, n, n_leaf), kKeyLevels);
-    const int lg_raw = window_level(d, idx, s, n, n_group);
-    bool start;
-    int gcount = 0;
-    if (lg_raw <= kKeyLevels) {
-      start = ds <= lg_raw;  // s begins its group cell
-      if (start && lg_raw == 0)
-        gcount = n;  // the whole set is one group
-      else if (start)
-        group_pack(keys, n, s, lg_raw, n_group, start, gcount);
-    } else {  // level-21 cell with more than n_group identical keys: cut in chunks
-      int a = s;
-      while (a > 0 && keys[a - 1] == keys[a]) --a;
-      start = ((s - a) % n_group) == 0;
-      if (start) gcount = min(n_group, cell_end(keys, n, s, kKeyLevels) - s);
+  const bool valid = s < n;
+  const int idx = kHalo + threadIdx.x;
+  int ds = 0, ll = 0, lg_raw = kLevels;
+  if (valid) {
+    ds = d[idx];
+    ll = min(window_level(d, idx, s, n, n_leaf), kKeyLevels);
+    lg_raw = window_level(d, idx, s, n, n_group);
+  }
+  bool start = false;
+  int gcount = 0;
+  const bool cell = valid && lg_raw <= kKeyLevels && ds <= lg_raw;  // s begins its group cell
+  if (cell && lg_raw == 0) {
+    start = true;
+    gcount = n;  // the whole set is one group
+  }
+  if (n_group <= 8) {
+    // per wavefront and group level L: boundary masks over the 192
+    // particles around the wavefront's 64, from the LDS window
+    const int lane = threadIdx.x & (kWave - 1);
+    const int t0 = threadIdx.x - lane;  // window index of particle s - lane - 64
+    uint64_t todo = ballot64(cell && lg_raw >= 1);
+    while (todo != 0ull) {
+      const int L = __builtin_amdgcn_readlane(lg_raw, __builtin_ctzll(todo));
+      uint64_t bc[3], bp[3];
+#pragma unroll
+      for (int w = 0; w < 3; ++w) {
+        const int dj = d[t0 + kWave * w + lane];
+        bc[w] = ballot64(dj <= L);
+        bp[w] = ballot64(dj <= L - 1);
+      }
+      const bool mine = cell && lg_raw == L;
+      if (mine) group_pack_masks(bc, bp, lane + kWave, n_group, start, gcount);
+      todo &= ~ballot64(mine);
     }
+  } else if (cell && lg_raw >= 1) {
+    // diff levels from the block's LDS window (it reaches kHalo particles
+    // past the tile on both sides), else from the keys
+    auto D = [&](int j) -> int {
+      const int t = j - base + kHalo;
+      if (t >= 0 && t < kTreeTile + 2 * kHalo + 1) return d[t];
+      return (j <= 0 || j >= n) ? 0 : diff_level(keys[j - 1], keys[j]);
+    };
+    group_pack(D, n, s, lg_raw, n_group, start, gcount);
+  }
+  if (valid && lg_raw > kKeyLevels) {
+    // level-21 cell with more than n_group identical keys: cut in chunks
+    int a = s;
+    while (a > 0 && keys[a - 1] == keys[a]) --a;
+    start = ((s - a) % n_group) == 0;
+    if (start) gcount = min(n_group, cell_end(keys, n, s, kKeyLevels) - s);
+  }
+  if (valid) {
     dlev[s] = (uint8_t)ds;
     lleaf[s] = (uint8_t)ll;
     gsize[s] = (uint8_t)gcount;
@@ -951,39 +1005,59 @@ __global__ __launch_bounds__(256) void k_range_boxes(
   const int do_bb = mode == 1 ? 1 : 0;
   const int nn = ds->n_nodes, ng = ds->n_groups;
   if ((int)blockIdx.x < nb_small) {
-    for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < nn + ng;
-         it += nb_small * blockDim.x) {
+    // the trip count is uniform over each wavefront (the leaf records below
+    // are written by whole wavefronts)
+    for (int base = blockIdx.x * blockDim.x; base < nn + ng; base += nb_small * blockDim.x) {
+      const int it = base + (int)threadIdx.x;
       const bool is_node = it < nn;
-      if (is_node && nnchild[it] != 0) continue;
-      const int f = is_node ? nfirst[it] : gfirst[it - nn];
-      const int e = f + (is_node ? ncount[it] : gcount[it - nn]);
-      Box7 b;
-      box_empty(b);
+      const bool item = it < nn + ng && !(is_node && nnchild[it] != 0);
+      int f = 0, e = 0;
+      double c[3] = {0.0, 0.0, 0.0};
+      if (item) {
+        f = is_node ? nfirst[it] : gfirst[it - nn];
+        e = f + (is_node ? ncount[it] : gcount[it - nn]);
+        Box7 b;
+        box_empty(b);
 #pragma unroll 4
-      for (int s = f; s < e; ++s) {
-        if (do_bb) {
-          const double px = x[s], py = y[s], pz = z[s];
-          b.lo[0] = fmin(b.lo[0], px);
-          b.hi[0] = fmax(b.hi[0], px);
-          b.lo[1] = fmin(b.lo[1], py);
-          b.hi[1] = fmax(b.hi[1], py);
-          b.lo[2] = fmin(b.lo[2], pz);
-          b.hi[2] = fmax(b.hi[2], pz);
+        for (int s = f; s < e; ++s) {
+          if (do_bb) {
+            const double px = x[s], py = y[s], pz = z[s];
+            b.lo[0] = fmin(b.lo[0], px);
+            b.hi[0] = fmax(b.hi[0], px);
+            b.lo[1] = fmin(b.lo[1], py);
+            b.hi[1] = fmax(b.hi[1], py);
+            b.lo[2] = fmin(b.lo[2], pz);
+            b.hi[2] = fmax(b.hi[2], pz);
+          }
+          b.hm = fmax(b.hm, h[s]);
         }
-        b.hm = fmax(b.hm, h[s]);
+        if (is_node) {
+          write_node_box(b, it, f, e, 0, nchild, wn, do_bb);
+          for (int a = 0; a < 3; ++a) c[a] = wn[it].c[a];
+        } else {
+          write_group_box(b, it - nn, f, e, gi, do_bb);
+        }
       }
-      if (is_node) {
-        write_node_box(b, it, f, e, 0, nchild, wn, do_bb);
-        // each particle relative to its leaf's centre, and h, in FP32: the
-        // mixed list kernel's candidate loads (before a density pass)
-        if (mode != 0) {
-          const double c0 = wn[it].c[0], c1 = wn[it].c[1], c2 = wn[it].c[2];
-          for (int s = f; s < e; ++s)
-            lrec[s] = make_float4((float)(x[s] - c0), (float)(y[s] - c1), (float)(z[s] - c2),
-                                  (float)h[s]);
+      // each particle relative to its leaf's centre, and h, in FP32: the
+      // mixed list kernel's candidate loads (before a density pass); one
+      // leaf at a time over the wavefront's lanes, so the stores coalesce
+      if (mode != 0) {
+        uint64_t m = ballot64(item && is_node);
+        while (m != 0ull) {
+          const int src = __builtin_ctzll(m);
+          m &= m - 1ull;
+          const int lf = __builtin_amdgcn_readlane(f, src), le = __builtin_amdgcn_readlane(e, src);
+          double cc[3];
+          for (int a = 0; a < 3; ++a) {
+            const unsigned long long v = (unsigned long long)__double_as_longlong(c[a]);
+            const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, src);
+            const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), src);
+            cc[a] = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+          }
+          for (int q = lf + lane_id(); q < le; q += kWave)
+            lrec[q] = make_float4((float)(x[q] - cc[0]), (float)(y[q] - cc[1]),
+                                  (float)(z[q] - cc[2]), (float)h[q]);
         }
-      } else {
-        write_group_box(b, it - nn, f, e, gi, do_bb);
       }
     }
     return;
