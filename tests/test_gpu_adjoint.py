@@ -10,10 +10,15 @@ central finite differences of the GPU's own FP64 forward.
 * At the full size of the adjoint workload (64^3 = 262,144 particles, K = 8
   steps of fixed dt): central finite differences (eps = 1e-6) of the FP64
   forward on 64 seeded particles x 6 components and along a random
-  direction, without viscosity and conductivity (smooth loss), with every
-  term over one step, and with every term over 8 steps (where the viscosity
-  switch makes a few components kink-limited); the mixed-precision gradient
-  against the FP64 one.
+  direction, without viscosity and conductivity (smooth loss: every
+  component), and with every term over one step and over 8 steps: there
+  each +-eps pair of runs is checked pair by pair for a kink between them
+  (a sign change of w or of P_i - P_j, or P_i - P_j next to zero), and
+  every component without one must agree.  The mixed-precision gradient
+  against the FP64 one: without viscosity and conductivity every component;
+  with them over one step every particle more than two pair hops from a
+  pair whose kink the two trajectories see on different sides; over 8
+  steps in L2 and the 99.9th percentile.
 * The forward part of sph_step_adjoint leaves exactly what sph_step leaves;
   rows are rebuilt when h outgrew them; argument errors.
 
@@ -226,37 +231,119 @@ def adjoint_workload():
     return inputs.adjoint_lattice()
 
 
-def gpu_rollout_terms(ctx, base, m, h, dt, K):
+def by_id(t, v):
+    out = torch.empty_like(v)
+    out[t["id"]] = v
+    return out
+
+
+def eval_state(t, a0=None, dt=0.0):
+    """Positions, the velocities the force used, P and a of the last force
+    evaluation, indexed by particle id.  After sph_step the force used the
+    predicted velocities v_p = v1 - (a1 - a0) dt / 2 (the corrector's
+    inverse, eq:correct_vel)."""
+    x = [by_id(t, t[k]) for k in ("x", "y", "z")]
+    acc = [by_id(t, t[k]) for k in ("ax", "ay", "az")]
+    v = [by_id(t, t[k]) for k in ("vx", "vy", "vz")]
+    if a0 is not None:
+        v = [v[a] - 0.5 * dt * (acc[a] - a0[a]) for a in range(3)]
+    return x, v, by_id(t, t["P"]), acc
+
+
+def pair_signs(pairs, x, v, P):
+    """For the pairs (I, J) of particle ids: w_IJ < 0 (the viscosity acts,
+    Sect. 2.5) and P_I - P_J (the conductivity's sqrt|P_I - P_J|, Sect.
+    2.6), on the periodic unit box."""
+    I, J = pairs
+    dot = torch.zeros(I.shape[0], dtype=torch.float64, device=I.device)
+    for a in range(3):
+        d = x[a][I] - x[a][J]
+        d = d - torch.round(d)
+        dot += (v[a][I] - v[a][J]) * d
+    return dot < 0, P[I] - P[J]
+
+
+def gpu_rollout_terms(ctx, base, m, h, dt, K, pairs=None):
     """Per-particle terms m (|a|^2 + |v|^2 / 2) of the loss after the rollout,
     in the original particle order.  A difference of two rollouts is taken
     term by term: the loss of one particle is ~1/N of the total, and the
-    rounding of a total would swamp a finite difference of one particle."""
+    rounding of a total would swamp a finite difference of one particle.
+    With ``pairs`` (per force evaluation, ids of the base run's force pairs)
+    also the signs of w and P_i - P_j of those pairs at every evaluation."""
     st = dict(base)
     st["m"], st["h"] = m, h
     p = sph.Particles.from_tensors(st)
     sph.sph_build_tree(ctx, p)
     sph.sph_density(ctx, p)
     sph.sph_force(ctx, p)
-    for _ in range(K):
+    signs = []
+    x, v, P, acc = eval_state(p.t)
+    if pairs is not None:
+        signs.append(pair_signs(pairs[0], x, v, P))
+    for s in range(K):
         sph.sph_step(ctx, p, dt)
+        if pairs is not None:
+            x, v, P, acc = eval_state(p.t, acc, dt)
+            signs.append(pair_signs(pairs[s + 1], x, v, P))
     t = p.t
     terms = t["m"] * (t["ax"] ** 2 + t["ay"] ** 2 + t["az"] ** 2) + \
         0.5 * t["m"] * (t["vx"] ** 2 + t["vy"] ** 2 + t["vz"] ** 2)
     out = torch.empty_like(terms)
     out[t["id"]] = terms
+    return (out, signs) if pairs is not None else out
+
+
+def force_pairs_by_evaluation(ctx, base, m, h, dt, K):
+    """The force pairs (as particle ids) of every force evaluation of the
+    unperturbed rollout."""
+    st = dict(base)
+    st["m"], st["h"] = m, h
+    p = sph.Particles.from_tensors(st)
+    sph.sph_build_tree(ctx, p)
+    sph.sph_density(ctx, p)
+    sph.sph_force(ctx, p)
+    out = []
+    for s in range(K + 1):
+        if s > 0:
+            sph.sph_step(ctx, p, dt)
+        off, idx = sph.sph_list_pairs(ctx, p, 1)
+        ids = p.t["id"]
+        rows = torch.repeat_interleave(torch.arange(p.n, device=ids.device),
+                                       torch.as_tensor(np.diff(off), device=ids.device))
+        out.append((ids[rows], ids[torch.as_tensor(idx, dtype=torch.int64, device=ids.device)]))
     return out
 
 
-def central_difference(ctx, base, m, h, dt, K, eps, plus, minus):
-    tp = gpu_rollout_terms(ctx, plus, m, h, dt, K)
-    tm = gpu_rollout_terms(ctx, minus, m, h, dt, K)
-    return float(torch.sum(tp - tm)) / (2 * eps)
+# A central difference of step 2 eps through sqrt|x| at distance x0 from its
+# kink is off by about (delta / x0)^2 of the slope, delta the change of x
+# between the two runs: a pair whose P_i - P_j stays within NEAR_KINK times
+# that change of zero makes the component kink-limited.
+NEAR_KINK = 30.0
+
+
+def central_difference(ctx, base, m, h, dt, K, eps, plus, minus, pairs=None):
+    """(FD, whether a kink of the loss lies between or next to the two runs:
+    some pair's w has opposite signs in them at some force evaluation, or its
+    P_i - P_j changes sign or stays within NEAR_KINK times its change of
+    zero)."""
+    if pairs is None:
+        tp = gpu_rollout_terms(ctx, plus, m, h, dt, K)
+        tm = gpu_rollout_terms(ctx, minus, m, h, dt, K)
+        return float(torch.sum(tp - tm)) / (2 * eps), False
+    tp, sp = gpu_rollout_terms(ctx, plus, m, h, dt, K, pairs)
+    tm, sm = gpu_rollout_terms(ctx, minus, m, h, dt, K, pairs)
+    kink = any(bool(torch.any(a[0] != b[0])) or
+               bool(torch.any(torch.abs(a[1] + b[1]) < 2 * NEAR_KINK * torch.abs(a[1] - b[1])))
+               for a, b in zip(sp, sm))
+    return float(torch.sum(tp - tm)) / (2 * eps), kink
 
 
 def full_size_case(terms, K):
     c = adjoint_workload()
     if terms == "pressure":
         c.update(alpha_av=0.0, beta_av=0.0, alpha_u=0.0)
+    elif terms == "av":
+        c.update(alpha_u=0.0)
     p = sph.make_params(c, FP64)
     ctx0 = sph.Context(p, c["n"])
     parts = sph.Particles(c)
@@ -273,11 +360,14 @@ def full_size_case(terms, K):
     return c, dt, g, ctx, base, m, h
 
 
-def per_component_fd(c, dt, K, g, ctx, base, m, h, eps=1e-6, n_sel=64):
-    """|FD - AD| / max|AD| for each of 6 components of n_sel seeded particles."""
+def per_component_fd(c, dt, K, g, ctx, base, m, h, eps=1e-6, n_sel=64, kinks=False):
+    """|FD - AD| / max|AD| for each of 6 components of n_sel seeded particles,
+    and (kinks=True) which components have a kink between their +-eps runs."""
     rng = np.random.default_rng(1909)
     sel = rng.choice(c["n"], n_sel, replace=False)
+    pairs = force_pairs_by_evaluation(ctx, base, m, h, dt, K) if kinks else None
     rel = {k: [] for k in FIELDS[:6]}
+    kink = {k: [] for k in FIELDS[:6]}
     for i in sel:
         for k in FIELDS[:6]:
             pm = []
@@ -289,12 +379,13 @@ def per_component_fd(c, dt, K, g, ctx, base, m, h, eps=1e-6, n_sel=64):
                     t = torch.remainder(t, 1.0)
                 b[k] = t
                 pm.append(b)
-            fd = central_difference(ctx, base, m, h, dt, K, eps, *pm)
+            fd, kk = central_difference(ctx, base, m, h, dt, K, eps, *pm, pairs=pairs)
             rel[k].append(abs(fd - g[k][i]) / np.abs(g[k]).max())
+            kink[k].append(kk)
     say("  per-component |FD - AD| / max|AD|, max: " +
         " ".join(f"{k}={max(v):.2e}" for k, v in rel.items()))
     say("  median: " + " ".join(f"{k}={np.median(v):.2e}" for k, v in rel.items()))
-    return rel
+    return rel, kink
 
 
 def direction_fd(c, dt, K, g, ctx, base, m, h, eps=1e-6):
@@ -308,7 +399,7 @@ def direction_fd(c, dt, K, g, ctx, base, m, h, eps=1e-6):
         for k in ("x", "y", "z"):
             b[k] = torch.remainder(b[k], 1.0)
         pm.append(b)
-    fd = central_difference(ctx, base, m, h, dt, K, eps, *pm)
+    fd, _ = central_difference(ctx, base, m, h, dt, K, eps, *pm)
     ad = sum(float(np.dot(g[k], d[k])) for k in FIELDS)
     mag = sum(float(np.abs(g[k] * d[k]).sum()) for k in FIELDS)
     say(f"  direction: FD {fd:.10e} AD {ad:.10e} rel {abs(fd - ad) / mag:.2e}")
@@ -320,7 +411,7 @@ def test_full_size_pressure_gradient_against_finite_differences():
     """Without viscosity and conductivity the loss is smooth apart from
     neighbour-set changes (where W = F = 0): every component agrees."""
     c, dt, g, ctx, base, m, h = full_size_case("pressure", 8)
-    rel = per_component_fd(c, dt, 8, g, ctx, base, m, h)
+    rel, _ = per_component_fd(c, dt, 8, g, ctx, base, m, h)
     for k, v in rel.items():
         assert max(v) <= FD_BOUND, k
     assert direction_fd(c, dt, 8, g, ctx, base, m, h) <= FD_BOUND
@@ -332,37 +423,47 @@ def test_full_size_pressure_gradient_against_finite_differences():
         assert v <= 1e-5, (k, v)
 
 
-def kink_limited(rel, median_bound, min_frac):
-    allrel = np.concatenate([np.asarray(v) for v in rel.values()])
-    frac = float(np.mean(allrel <= FD_BOUND))
-    say(f"  fraction within {FD_BOUND:g}: {frac:.3f}")
-    assert np.median(allrel) <= median_bound
-    assert frac >= min_frac
+def check_kinks(rel, kink):
+    """Every component whose +-eps runs see the same signs of w for every
+    force pair at every force evaluation, and keep every P_i - P_j well
+    clear of zero, lies on one smooth piece of the loss: its finite
+    difference must agree.  A component with a sign change straddles a kink
+    (the viscosity switch min(w, 0) and |w| of Sect. 2.5, the conductivity's
+    sqrt|P_i - P_j| of Sect. 2.6): the central difference then averages two
+    one-sided slopes, which the adjoint (one of them) need not match, and
+    next to the conductivity's kink its curvature grows without bound; those
+    components are counted, not bounded."""
+    n_kink = 0
+    for k in rel:
+        for r, kk in zip(rel[k], kink[k]):
+            if kk:
+                n_kink += 1
+            else:
+                assert r <= FD_BOUND, (k, r)
+    worst = max((r for k in rel for r, kk in zip(rel[k], kink[k]) if kk), default=0.0)
+    say(f"  components across a kink: {n_kink} of {sum(len(v) for v in rel.values())}"
+        f" (their largest |FD - AD| / max|AD| {worst:.2e}); every other within {FD_BOUND:g}")
+    return n_kink
 
 
-@pytest.mark.timeout(600)
+@pytest.mark.timeout(900)
 def test_full_size_gradient_one_step_against_finite_differences():
-    """Every term, one step: kink-limited as described below, already in
-    the initial evaluation."""
+    """Every term, one step: every component whose +-eps runs stay on one
+    side of every kink agrees within FD_BOUND."""
     c, dt, g, ctx, base, m, h = full_size_case("all", 1)
-    kink_limited(per_component_fd(c, dt, 1, g, ctx, base, m, h), 1e-8, 0.95)
+    check_kinks(*per_component_fd(c, dt, 1, g, ctx, base, m, h, kinks=True))
 
 
-@pytest.mark.timeout(600)
+@pytest.mark.timeout(900)
 def test_full_size_gradient_against_finite_differences():
-    """All terms, 8 steps.  The viscosity acts on approaching pairs only: the
-    loss has a kink wherever some pair's w = v_ij . r_ij / r passes zero
-    during the rollout, and a perturbation of 1e-6 now and then crosses one
-    (the finite difference then averages the two one-sided slopes, which
-    the adjoint does not), and so does the conductivity's sqrt|P_i - P_j|
-    wherever P_i - P_j passes zero.  Over 8 steps a perturbation reaches
-    enough pairs that a quarter of the components are kink-limited; the
-    rest agree as closely as without viscosity.  (The exact comparison of
-    the same terms over several steps is the one against the gradient
+    """All terms, 8 steps.  Over 8 steps a perturbation reaches enough pairs
+    that some components straddle a kink of the viscosity switch or of the
+    conductivity (identified pair by pair from the two runs); every other
+    component agrees as closely as without viscosity.  (The exact comparison
+    of the same terms over several steps is the one against the gradient
     oracle above.)"""
     c, dt, g, ctx, base, m, h = full_size_case("all", 8)
-    # measured: median 1.7e-7, 75% within 2e-6, worst 5e-3
-    kink_limited(per_component_fd(c, dt, 8, g, ctx, base, m, h), 1e-6, 0.6)
+    check_kinks(*per_component_fd(c, dt, 8, g, ctx, base, m, h, kinks=True))
     # the mixed-precision gradient against the FP64 one.  Through the
     # conductivity it is ill-conditioned: its derivative grows as
     # 1/sqrt|P_i - P_j|, and once u has left its two levels some pairs come
@@ -376,3 +477,45 @@ def test_full_size_gradient_against_finite_differences():
         p999 = float(np.quantile(d, 0.999) / np.abs(g[k]).max())
         say(f"  mixed vs FP64 {k}: L2 {l2:.2e} p99.9 {p999:.2e} max {d.max() / np.abs(g[k]).max():.2e}")
         assert l2 <= 0.1 and p999 <= 0.02, k
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("terms", ["av", "all"])
+def test_full_size_mixed_gradient_one_step_per_term(terms):
+    """The mixed-precision gradient of the one-step loss against the FP64
+    one, with the viscosity (av) and with every term (all).  Where the two
+    trajectories disagree on a kink (a pair's w or P_i - P_j of opposite
+    sign in the two runs) the gradients may differ by the slope jump; every
+    particle more than two pair hops from such a pair agrees within the
+    bound (measured p99.9 9e-7 of the largest component over all
+    particles).  With u on two levels, the pairs near P_i = P_j have
+    u_i = u_j at the start, so the conductivity term, which carries
+    u_i - u_j, has not yet turned FP32's rounding of P_i - P_j into an
+    error within one step; over 8 steps it has (the test above)."""
+    K = 1
+    c, dt, g, ctx, base, m, h = full_size_case(terms, K)
+    gm, _, _ = gpu_rollout_grad(c, MIXED, dt, K)
+    pairs = force_pairs_by_evaluation(ctx, base, m, h, dt, K)
+    _, s64 = gpu_rollout_terms(ctx, base, m, h, dt, K, pairs)
+    pm = sph.make_params(c, MIXED)
+    ctxm = sph.Context(pm, c["n"])
+    _, s32 = gpu_rollout_terms(ctxm, base, m, h, dt, K, pairs)
+    bad = torch.zeros(c["n"], dtype=torch.bool, device=base["x"].device)
+    for (I, J), a, b in zip(pairs, s64, s32):
+        flip = (a[0] != b[0]) | ((a[1] > 0) != (b[1] > 0))
+        bad[I[flip]] = True
+        bad[J[flip]] = True
+    I, J = pairs[0]
+    for _ in range(2):  # two pair hops
+        nb = bad.clone()
+        nb[I[bad[J]]] = True
+        bad = nb
+    keep = ~bad.cpu().numpy()
+    say(f"  {terms}: {int((~keep).sum())} of {c['n']} particles within two hops of a kink flip")
+    for k in FIELDS:
+        sc = np.abs(g[k]).max()
+        d = np.abs(gm[k] - g[k]) / sc
+        worst = float(d[keep].max()) if keep.any() else 0.0
+        say(f"  mixed vs FP64 {k}: kept max {worst:.2e}, all max {d.max():.2e}")
+        assert worst <= 5e-6, k  # measured 1.7e-6
+    assert keep.mean() >= 0.5  # the exclusion stays a minority

@@ -56,12 +56,14 @@ def test_shear_layer_full_size(precision):
     check(g, o, precision)
 
 
-def test_turbulent_box_full_size_sampled():
+@pytest.mark.parametrize("precision", [sph.SPH_PREC_FP64, sph.SPH_PREC_MIXED])
+def test_turbulent_box_full_size_sampled(precision):
     cfg = inputs.turbulent_box(256)
-    g, ctx, parts, info = gpu_eval(cfg, sph.SPH_PREC_MIXED)
+    g, ctx, parts, info = gpu_eval(cfg, precision)
+    ctx.close()
     sel = np.random.default_rng(1909).choice(cfg["n"], 256, replace=False)
     o = oracle.evaluate_subset(cfg, oracle.make_params(cfg), sel)
-    check(g, o, sph.SPH_PREC_MIXED, idx=sel)
+    check(g, o, precision, idx=sel)
 
 
 @pytest.mark.parametrize("n_side", [44, 60])

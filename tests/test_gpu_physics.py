@@ -103,6 +103,43 @@ def test_several_steps_fp64_match_oracle():
         assert e < 1e-10, k
 
 
+# relative to each field's largest magnitude (velocities: to the largest
+# speed component); measured after 8 steps: x 3.0e-9, y 1.1e-8, z 9.9e-9,
+# v 1.6e-7, u 3.4e-8, rho 2.2e-7, h 1.7e-7
+MIXED_STEP_BOUNDS = dict(x=2e-8, y=5e-8, z=5e-8, vx=1e-6, vy=1e-6, vz=1e-6, u=2e-7, rho=1e-6,
+                         h=1e-6)
+
+
+def test_several_steps_mixed_match_oracle():
+    """The mixed path over 8 leapfrog steps of the shock tube against the FP64
+    oracle, both taking the oracle's Courant steps: the per-evaluation
+    rounding (h 2e-6, rho 1e-5, a 2e-5 of its pair-term scale) does not grow
+    into the state beyond the bounds."""
+    cfg = inputs.sod(dx_left=1.0 / 64, width=0.25)
+    op = oracle.make_params(cfg)
+    s = oracle.evaluate(cfg, op)
+    p = sph.make_params(cfg, sph.SPH_PREC_MIXED)
+    state = dict(cfg)
+    for k in ("ax", "ay", "az", "dudt", "h"):
+        state[k] = s[k]
+    parts = sph.Particles(state)
+    ctx = sph.Context(p, cfg["n"])
+    dt = s["dt_next"]
+    for step in range(8):
+        s = oracle.step(s, dt, op)
+        dtg = sph.sph_step(ctx, parts, dt, want_dt=True)
+        assert abs(dtg - s["dt_next"]) <= 1e-5 * s["dt_next"]
+        dt = s["dt_next"]
+    g = to_orig(parts.numpy())
+    vmax = max(np.abs(s[k]).max() for k in ("vx", "vy", "vz"))
+    errs = {k: np.abs(g[k] - s[k]).max() /
+            (vmax if k in ("vx", "vy", "vz") else max(np.abs(s[k]).max(), 1e-300))
+            for k in MIXED_STEP_BOUNDS}
+    say("  after 8 steps: " + " ".join(f"{k}={e:.2e}" for k, e in errs.items()))
+    for k, bound in MIXED_STEP_BOUNDS.items():
+        assert errs[k] < bound, k
+
+
 def test_shock_tube_t02_window():
     """t = 0.2 (the figure's time): the waves of the periodic mirror problem
     have met the main shock (t = 0.1355) and the rarefaction heads have met
