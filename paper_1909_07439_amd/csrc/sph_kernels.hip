@@ -3655,7 +3655,9 @@ bool lists_mode(const sph_ctx* c) { return c->kp.n_group == 4 || c->kp.n_group =
 template <bool MIXED>
 static hipError_t density_dispatch(sph_ctx* c, const sph_particles* s, const int32_t* gflag) {
   const Parts p = parts_of(s);
-  const dim3 grid(c->walk_blocks), block(64);
+  // the flagged groups (usually none, at most a few per cent) are striped
+  // over a quarter of the walk grid: an empty launch then costs less
+  const dim3 grid(gflag ? std::max(c->walk_blocks / 4, 8) : c->walk_blocks), block(64);
   SPH_LPI_SWITCH(c->kp.n_group,
                  hipLaunchKernelGGL((k_density<MIXED, LPI>), grid, block, 0, c->stream, c->kp, p,
                                     c->wnode, c->ginfo, c->frec, c->leaf_pool, c->pool_cap,
