@@ -2481,20 +2481,24 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
       // each leaf against every group's box, with that group's radius; a
       // range of 2^24 particles or more (coincident keys, or a whole inner
       // node) does not fit beside the bits: the groups then walk on their own
-      for (int base = 0; base < nsl; base += kWave) {
-        const int k = base + lane;
+      // two leaves per lane per trip, their node loads in flight together
+      for (int base = 0; base < nsl; base += 2 * kWave) {
+        const int ka = base + lane, kb = base + kWave + lane;
+        const WalkNode na = nodes[s_sl[ka < nsl ? ka : 0]];
+        const WalkNode nb = nodes[s_sl[kb < nsl ? kb : 0]];
         bool big = false;
-        if (k < nsl) {
-          const WalkNode nd = nodes[s_sl[k]];
+        auto leaf_bits = [&](const WalkNode& nd, int k) {
           int bits = 0;
           for (int gk = 0; gk < ngs; ++gk) {
             const double rg = kp.support * fmax(s_hm[gk], margin * (double)nd.hmax) * (1.0 + 4e-9);
             if (box_gap2(nd, groups[g0 + gk], kp) < rg * rg) bits |= 1 << gk;
           }
-          big = nd.count >= (1 << 24);
+          big = big || nd.count >= (1 << 24);
           U.sl.first[k] = nd.first;
           U.sl.cntbits[k] = (nd.count & 0xffffff) | (bits << 24);
-        }
+        };
+        if (ka < nsl) leaf_bits(na, ka);
+        if (kb < nsl) leaf_bits(nb, kb);
         if (ballot64(big) != 0ull) sok = false;
       }
       __syncthreads();
@@ -2519,8 +2523,13 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
         // flush folds every pair separation instead.
         bool amb = false;
         if constexpr (MIXED) {
-          for (int l = lane; l < nleaf; l += kWave) {
-            const WalkNode& nd = nodes[L.lnode[l]];
+          // a lane's two leaves (kLCap <= 2 * 64) are loaded before either is
+          // used, so their node loads are in flight together
+          static_assert(kLCap <= 2 * kWave, "two flushed leaves per lane at most");
+          const int la = lane, lb = lane + kWave;
+          const WalkNode na = nodes[L.lnode[la < nleaf ? la : 0]];
+          const WalkNode nb = nodes[L.lnode[lb < nleaf ? lb : 0]];
+          auto offset = [&](const WalkNode& nd, int l) {
             const double rl = radius(nd);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -2529,7 +2538,9 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
               if (kp.periodic[a] && fabs(d) + (double)nd.w[a] + G.w[a] + rl >= kp.half[a])
                 amb = true;
             }
-          }
+          };
+          if (la < nleaf) offset(na, la);
+          if (lb < nleaf) offset(nb, lb);
           amb = ballot64(amb) != 0ull;
           __syncthreads();
         }
