@@ -185,11 +185,15 @@ __global__ __launch_bounds__(64) void k_adj_force(KParams kp, Parts p,
                                                   const int32_t* __restrict__ nl_idx,
                                                   const int32_t* __restrict__ nl_len,
                                                   double* __restrict__ raw, int64_t ns,
-                                                  double2* __restrict__ ab) {
+                                                  double2* __restrict__ ab,
+                                                  const QFrame* __restrict__ qf) {
   using Rec = typename ARecOf<MIXED>::T;
   using CT = typename ARecOf<MIXED>::C;
   using R = typename std::conditional<MIXED, float, double>::type;
   const Rec* __restrict__ rec = reinterpret_cast<const Rec*>(frec_in);
+  float qs[3] = {0.f, 0.f, 0.f};  // code steps of the mixed records' positions
+  if constexpr (MIXED)
+    for (int a = 0; a < 3; ++a) qs[a] = qf->step[a];
   const CT* __restrict__ abar = reinterpret_cast<const CT*>(abar_in);
   const int lane = threadIdx.x;
   const int slot = lane / LPI, sub = lane % LPI;
@@ -204,9 +208,20 @@ __global__ __launch_bounds__(64) void k_adj_force(KParams kp, Parts p,
     const int first = ch * CS, count = min(CS, kp.n - first);
     const bool act = slot < count;
     const int k = first + (act ? slot : 0);
-    const Rec rk = rec[k];
+    const Rec rk = rec_load<Rec>(rec, k);
     const CT ak = abar[k];
-    const double xk = rk.x, yk = rk.y, zk = rk.z;
+    // position: FP64 (folded per pair) or the mixed record's codes
+    double xk = 0.0, yk = 0.0, zk = 0.0;
+    int32_t qxk = 0, qyk = 0, qzk = 0;
+    if constexpr (MIXED) {
+      qxk = rk.qx;
+      qyk = rk.qy;
+      qzk = rk.qz;
+    } else {
+      xk = rk.x;
+      yk = rk.y;
+      zk = rk.z;
+    }
     const R hk = (R)rk.h, hinvk = R(1) / hk, mk = (R)rk.m;
     const R h4k = C * hinvk * hinvk * hinvk * hinvk, h5k = h4k * hinvk;
     const R srk = S * hk, srk2 = srk * srk;
@@ -224,10 +239,17 @@ __global__ __launch_bounds__(64) void k_adj_force(KParams kp, Parts p,
       const int j = jn;
       jn = (t + LPI < len) ? row[t + LPI] : k;
       if (j == k) continue;
-      const Rec rj = rec[j];
-      const R dx = (R)afold(xk - rj.x, kp.len[0], kp.half[0], kp.periodic[0]);
-      const R dy = (R)afold(yk - rj.y, kp.len[1], kp.half[1], kp.periodic[1]);
-      const R dz = (R)afold(zk - rj.z, kp.len[2], kp.half[2], kp.periodic[2]);
+      const Rec rj = rec_load<Rec>(rec, j);
+      R dx, dy, dz;
+      if constexpr (MIXED) {
+        dx = qsep(qxk, rj.qx, qs[0]);
+        dy = qsep(qyk, rj.qy, qs[1]);
+        dz = qsep(qzk, rj.qz, qs[2]);
+      } else {
+        dx = afold(xk - rj.x, kp.len[0], kp.half[0], kp.periodic[0]);
+        dy = afold(yk - rj.y, kp.len[1], kp.half[1], kp.periodic[1]);
+        dz = afold(zk - rj.z, kp.len[2], kp.half[2], kp.periodic[2]);
+      }
       const R r2 = fma(dz, dz, fma(dy, dy, dx * dx));
       const R hj = (R)rj.h;
       const R sr = S * (hk > hj ? hk : hj);
@@ -394,10 +416,14 @@ __global__ __launch_bounds__(64) void k_adj_dens2(KParams kp, Parts p,
                                                   const int32_t* __restrict__ nl_len,
                                                   const double* __restrict__ raw, int64_t ns,
                                                   const double2* __restrict__ ab, Cot g,
-                                                  double dt, int step_mode) {
+                                                  double dt, int step_mode,
+                                                  const QFrame* __restrict__ qf) {
   using Rec = typename ARecOf<MIXED>::T;
   using R = typename std::conditional<MIXED, float, double>::type;
   const Rec* __restrict__ rec = reinterpret_cast<const Rec*>(frec_in);
+  float qs[3] = {0.f, 0.f, 0.f};  // code steps of the mixed records' positions
+  if constexpr (MIXED)
+    for (int a = 0; a < 3; ++a) qs[a] = qf->step[a];
   const int lane = threadIdx.x;
   const int slot = lane / LPI, sub = lane % LPI;
   constexpr int CS = kWave / LPI;
@@ -409,6 +435,13 @@ __global__ __launch_bounds__(64) void k_adj_dens2(KParams kp, Parts p,
     const bool act = slot < count;
     const int k = first + (act ? slot : 0);
     const double xk = p.x[k], yk = p.y[k], zk = p.z[k];
+    // the mixed records hold position codes; k's are those its record holds
+    int32_t qxk = 0, qyk = 0, qzk = 0;
+    if constexpr (MIXED) {
+      qxk = qcode(xk, *qf, 0, kp.periodic[0]);
+      qyk = qcode(yk, *qf, 1, kp.periodic[1]);
+      qzk = qcode(zk, *qf, 2, kp.periodic[2]);
+    }
     const R hk = (R)p.h[k], mk = (R)p.m[k], Cr = (R)C;
     const R hinvk = R(1) / hk, srk = (R)S * hk, srk2 = srk * srk;
     const double2 abk = ab[k];
@@ -422,10 +455,17 @@ __global__ __launch_bounds__(64) void k_adj_dens2(KParams kp, Parts p,
       const int j = jn;
       jn = (t + LPI < len) ? row[t + LPI] : k;
       if (j == k) continue;
-      const Rec& rj = rec[j];
-      const R dx = (R)afold(xk - rj.x, kp.len[0], kp.half[0], kp.periodic[0]);
-      const R dy = (R)afold(yk - rj.y, kp.len[1], kp.half[1], kp.periodic[1]);
-      const R dz = (R)afold(zk - rj.z, kp.len[2], kp.half[2], kp.periodic[2]);
+      const Rec rj = rec_load<Rec>(rec, j);
+      R dx, dy, dz;
+      if constexpr (MIXED) {
+        dx = qsep(qxk, rj.qx, qs[0]);
+        dy = qsep(qyk, rj.qy, qs[1]);
+        dz = qsep(qzk, rj.qz, qs[2]);
+      } else {
+        dx = afold(xk - rj.x, kp.len[0], kp.half[0], kp.periodic[0]);
+        dy = afold(yk - rj.y, kp.len[1], kp.half[1], kp.periodic[1]);
+        dz = afold(zk - rj.z, kp.len[2], kp.half[2], kp.periodic[2]);
+      }
       const R r2 = fma(dz, dz, fma(dy, dy, dx * dx));
       const R hj = (R)rj.h;
       const R srj = (R)S * hj;
@@ -546,18 +586,20 @@ hipError_t launch_adjoint(sph_ctx* c, const sph_particles* s, const sph_cotangen
   } else if (part == 1) {
     if (mixed)
       hipLaunchKernelGGL((k_adj_force<true, LPI>), grid, block, 0, c->stream, c->kp, p, c->frec,
-                         c->adj_abar, c->nl_idx, c->nl_len, c->adj_raw, ns, c->adj_ab);
+                         c->adj_abar, c->nl_idx, c->nl_len, c->adj_raw, ns, c->adj_ab,
+                         &c->ds->qf);
     else
       hipLaunchKernelGGL((k_adj_force<false, LPI>), grid, block, 0, c->stream, c->kp, p, c->frec,
-                         c->adj_abar, c->nl_idx, c->nl_len, c->adj_raw, ns, c->adj_ab);
+                         c->adj_abar, c->nl_idx, c->nl_len, c->adj_raw, ns, c->adj_ab,
+                         &c->ds->qf);
   } else if (mixed) {
     hipLaunchKernelGGL((k_adj_dens2<true, LPI>), dgrid, block, 0, c->stream, c->kp, p, c->frec,
                        c->nl_idx, c->nl_len, c->adj_raw, ns, c->adj_ab, g, dt,
-                       step_mode ? 1 : 0);
+                       step_mode ? 1 : 0, &c->ds->qf);
   } else {
     hipLaunchKernelGGL((k_adj_dens2<false, LPI>), dgrid, block, 0, c->stream, c->kp, p, c->frec,
                        c->nl_idx, c->nl_len, c->adj_raw, ns, c->adj_ab, g, dt,
-                       step_mode ? 1 : 0);
+                       step_mode ? 1 : 0, &c->ds->qf);
   }
   return hipGetLastError();
 }

@@ -284,7 +284,7 @@ sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ct
   ALLOC(c->lrec, N);
   {
     const size_t rec = (P.precision == SPH_PREC_MIXED) ? sizeof(sph::FRec32) : sizeof(sph::FRec64);
-    e = hipMalloc(&c->frec, rec * (size_t)N);
+    e = hipMalloc(&c->frec, rec * (size_t)sph::rec_slots(N));
     if (e != hipSuccess) return bail(e, "frec");
   }
   ALLOC(c->a1, 4 * N);

@@ -27,6 +27,31 @@ enum : uint32_t {
   kErrSort = 512u,           // a radix-sort look-back wait ran out (should not happen)
 };
 
+// Fixed-point frame of the positions in the mixed-precision force records.
+// Axis a maps x to the code floor((x - o[a]) inv[a]): on a periodic axis inv
+// = 2^32 / L and the code is kept modulo 2^32, so the wrapped 32-bit
+// difference of two codes is the nearest periodic image; on an open axis the
+// frame spans the root node's box with 2^31 codes (clamped), so a difference
+// never wraps.  Code difference times step[a] is the separation to within one
+// step (L 2^-32 on a periodic axis), with no FP64 arithmetic and no fold.
+struct QFrame {
+  double o[3];
+  double inv[3];
+  float step[3];
+  int32_t pad;
+};
+
+__device__ __forceinline__ int32_t qcode(double x, const QFrame& f, int a, int periodic) {
+  const double t = floor((x - f.o[a]) * f.inv[a]);
+  if (periodic) return (int32_t)(uint32_t)(uint64_t)(int64_t)t;  // modulo 2^32
+  return (int32_t)fmin(fmax(t, 0.0), 2147483647.0);
+}
+
+// Separation a - b of two codes of one axis (wrapped 32-bit difference).
+__device__ __forceinline__ float qsep(int32_t a, int32_t b, float step) {
+  return (float)(int32_t)((uint32_t)a - (uint32_t)b) * step;
+}
+
 // Device-resident scalars of one context.
 // Every wavefront of the walk kernels adds its counts once; the counters
 // that all of them update sit 256 bytes apart (separate cache lines and L2
@@ -53,6 +78,7 @@ struct DevState {
   alignas(256) unsigned long long tot_sums_density;  // n_sums_density over every launch so far
   alignas(256) unsigned long long tot_pairs_force;   // n_pairs_force over every launch so far
   alignas(256) unsigned long long tot_cand_lists;    // candidate tests of the list kernel so far
+  alignas(256) QFrame qf;  // frame of the mixed force records (set with each tree's node boxes)
 };
 
 // Walk view of a tree node: centre, conservative half-widths, largest h.

@@ -1102,6 +1102,29 @@ __global__ __launch_bounds__(256) void k_range_boxes(
   }
 }
 
+// Fixed-point frame of the mixed force records (QFrame) for the positions of
+// the current tree: the box on periodic axes, the root node's box (a
+// conservative one: its half-widths are rounded up) on open axes.
+__global__ void k_qframe(KParams kp, const WalkNode* __restrict__ nodes,
+                         DevState* __restrict__ ds) {
+  if (threadIdx.x >= 3) return;
+  const int a = threadIdx.x;
+  QFrame& f = ds->qf;
+  if (kp.periodic[a]) {
+    f.o[a] = kp.lo[a];
+    f.inv[a] = 4294967296.0 / kp.len[a];
+    f.step[a] = (float)(kp.len[a] / 4294967296.0);
+  } else {
+    const bool any = ds->n_nodes > 0;
+    const double c = any ? nodes[0].c[a] : 0.0;
+    const double w = any ? (double)nodes[0].w[a] : 0.0;
+    const double ext = w > 0.0 ? 2.0 * w : 1.0;
+    f.o[a] = c - 0.5 * ext;
+    f.inv[a] = 2147483648.0 / ext;
+    f.step[a] = (float)(ext / 2147483648.0);
+  }
+}
+
 // ============================================================================
 // Group tree walk (Sect. 3.2): one wavefront per group, breadth-first.  The
 // frontier lives in LDS; nodes are tested 64 at a time, opened inner nodes
@@ -1572,7 +1595,8 @@ __device__ __forceinline__ void density_outputs(const KParams& kp, const Parts& 
                                                 void* __restrict__ frec_out, int i, double xi,
                                                 double yi, double zi, double mi, double h,
                                                 double S0, double S1, double minhalf,
-                                                uint32_t& err, bool write) {
+                                                uint32_t& err, bool write,
+                                                const DevState* __restrict__ ds) {
   const double rho = S0;
   const double omega = 1.0 + h * S1 / (3.0 * rho);
   const double u = p.u[i];
@@ -1592,9 +1616,10 @@ __device__ __forceinline__ void density_outputs(const KParams& kp, const Parts& 
   const double hinv4pi = hinv * hinv * hinv * hinv * kp.knorm;
   if constexpr (MIXED) {
     FRec32 r;
-    r.x = xi;
-    r.y = yi;
-    r.z = zi;
+    const QFrame& f = ds->qf;
+    r.qx = qcode(xi, f, 0, kp.periodic[0]);
+    r.qy = qcode(yi, f, 1, kp.periodic[1]);
+    r.qz = qcode(zi, f, 2, kp.periodic[2]);
     r.m = (float)mi;
     r.h = (float)h;
     r.vx = (float)p.vx[i];
@@ -1608,8 +1633,7 @@ __device__ __forceinline__ void density_outputs(const KParams& kp, const Parts& 
     r.c = (float)cs;
     r.P = (float)P;
     r.rho = (float)rho;
-    r.pad1 = 0.f;
-    reinterpret_cast<FRec32*>(frec_out)[i] = r;
+    rec_store(frec_out, i, r);
   } else {
     FRec64 r;
     r.x = xi;
@@ -1628,7 +1652,7 @@ __device__ __forceinline__ void density_outputs(const KParams& kp, const Parts& 
     r.P = P;
     r.rho = rho;
     r.h = h;
-    reinterpret_cast<FRec64*>(frec_out)[i] = r;
+    rec_store(frec_out, i, r);
   }
 }
 
@@ -1991,7 +2015,7 @@ __global__ __launch_bounds__(64) void k_density(KParams kp, Parts p,
     if (act && !failed && h > h0 * margin) grew = true;
     if (act && !failed) {
       density_outputs<MIXED>(kp, p, frec_out, i, xi, yi, zi, mi, h, S0, S1, minhalf, err,
-                             sub == 0);
+                             sub == 0, ds);
       if (sub == 0) {
         pairs_final += nnb;
       }
@@ -2087,7 +2111,7 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
     const bool act = slot < G.count;
     const int i = G.first + (act ? slot : 0);
     const double xi = p.x[i], yi = p.y[i], zi = p.z[i], hi = p.h[i];
-    const Rec ri = rec[i];
+    const Rec ri = rec_load<Rec>(rec, i);
     float xr = 0.f, yr = 0.f, zr = 0.f;  // FP32 path: position relative to the group centre
     const float hif = (float)hi;
     if constexpr (MIXED) {
@@ -2104,10 +2128,11 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
         const float vxi = ri.vx, vyi = ri.vy, vzi = ri.vz;
         const float hinvi = ri.hinv, h4i = ri.hinv4pi, gi = ri.g, ki = ri.k, ci = ri.c;
         const float Pi = ri.P, rhoi = ri.rho, ui = ri.u;
+        const float qsx = ds->qf.step[0], qsy = ds->qf.step[1], qsz = ds->qf.step[2];
         auto pair = [&](const Rec& rj) {
-          const float dx = (float)fold(xi - rj.x, kp.len[0], kp.half[0], kp.periodic[0]);
-          const float dy = (float)fold(yi - rj.y, kp.len[1], kp.half[1], kp.periodic[1]);
-          const float dz = (float)fold(zi - rj.z, kp.len[2], kp.half[2], kp.periodic[2]);
+          const float dx = qsep(ri.qx, rj.qx, qsx);
+          const float dy = qsep(ri.qy, rj.qy, qsy);
+          const float dz = qsep(ri.qz, rj.qz, qsz);
           const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
           const float rinv = __builtin_amdgcn_rsqf(r2);
           const float r = r2 * rinv;
@@ -2139,8 +2164,8 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
           const bool two = k2 < npair;
           const int j1 = s_j[k * GS + slot];
           const int j2 = two ? s_j[k2 * GS + slot] : j1;
-          const Rec r1 = rec[j1];
-          const Rec r2 = rec[j2];
+          const Rec r1 = rec_load<Rec>(rec, j1);
+          const Rec r2 = rec_load<Rec>(rec, j2);
           pair(r1);
           if (two) pair(r2);
         }
@@ -2183,8 +2208,8 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
           const bool two = k2 < npair;
           const int j1 = s_j[k * GS + slot];
           const int j2 = two ? s_j[k2 * GS + slot] : j1;
-          const Rec r1 = rec[j1];
-          const Rec r2 = rec[j2];
+          const Rec r1 = rec_load<Rec>(rec, j1);
+          const Rec r2 = rec_load<Rec>(rec, j2);
           pair(r1);
           if (two) pair(r2);
         }
@@ -2976,7 +3001,7 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
     it_max = max(it_max, nit + 1);
     if (act) {
       density_outputs<MIXED>(kp, p, frec_out, i, xi, yi, zi, mi, h, S0, S1, minhalf, err,
-                             sub == 0);
+                             sub == 0, ds);
       if (sub == 0) pairs_final += nnb;
     }
   }
@@ -3037,11 +3062,6 @@ void k_force_lists(KParams kp, Parts p,
   uint32_t err = 0;
   unsigned long long pairs = 0, cands = 0;
   double dtmin = SPH_INF;
-  double lp[3], ilp[3];  // periodic lengths and their inverses (0 on open axes)
-  for (int a = 0; a < 3; ++a) {
-    lp[a] = kp.periodic[a] ? kp.len[a] : 0.0;
-    ilp[a] = kp.periodic[a] ? kp.inv_len[a] : 0.0;
-  }
 
   for (int g = gr.beg; g < gr.end; g += gr.step) {
     const int first = g * CS, count = min(CS, kp.n - first);
@@ -3051,7 +3071,7 @@ void k_force_lists(KParams kp, Parts p,
     const bool act = inr && gflag[grp_of[i]] == 0;
     if (ballot64(act) == 0ull) continue;
     const double xi = p.x[i], yi = p.y[i], zi = p.z[i], hi = p.h[i];
-    const Rec ri = rec[i];
+    const Rec ri = rec_load<Rec>(rec, i);
     const int len = act ? nl_len[i] : 0;
     const int32_t* __restrict__ row = nl_idx + (int64_t)i * kp.nl_cap;
     int lmax = len;
@@ -3076,10 +3096,11 @@ void k_force_lists(KParams kp, Parts p,
       // the viscous heating of an approaching pair is the w_ part of w A_i.
       // The FP32 support test is settled in FP64 near its boundary, so the
       // accepted pairs are those of the FP64 predicate.
+      const float qsx = ds->qf.step[0], qsy = ds->qf.step[1], qsz = ds->qf.step[2];
       auto pair = [&](const Rec& rj, int j) {
-        const float dx = (float)fold_r(xi - rj.x, lp[0], ilp[0]);
-        const float dy = (float)fold_r(yi - rj.y, lp[1], ilp[1]);
-        const float dz = (float)fold_r(zi - rj.z, lp[2], ilp[2]);
+        const float dx = qsep(ri.qx, rj.qx, qsx);
+        const float dy = qsep(ri.qy, rj.qy, qsy);
+        const float dz = qsep(ri.qz, rj.qz, qsz);
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
         const float sr = S * fmaxf(hif, rj.h);
         const float sr2 = sr * sr;
@@ -3116,8 +3137,8 @@ void k_force_lists(KParams kp, Parts p,
       int j2 = (sub + LPI < len) ? row[sub + LPI] : i;
       for (int k = sub; k < lmax; k += 2 * LPI) {
         const bool v1 = k < len, v2 = k + LPI < len;
-        const Rec r1 = rec[j1];
-        const Rec r2 = rec[j2];
+        const Rec r1 = rec_load<Rec>(rec, j1);
+        const Rec r2 = rec_load<Rec>(rec, j2);
         const int kn = k + 2 * LPI;
         const int jn1 = (kn < len) ? row[kn] : i;
         const int jn2 = (kn + LPI < len) ? row[kn + LPI] : i;
@@ -3174,7 +3195,7 @@ void k_force_lists(KParams kp, Parts p,
       int j = (sub < len) ? row[sub] : i;
       for (int k = sub; k < lmax; k += LPI) {
         const bool v = k < len;
-        const Rec rj = rec[j];
+        const Rec rj = rec_load<Rec>(rec, j);
         const int jn = (k + LPI < len) ? row[k + LPI] : i;
         if (v && j != i) pair(rj);
         j = jn;
@@ -3625,7 +3646,12 @@ static hipError_t node_props(sph_ctx* c, const sph_particles* s, int mode) {
 hipError_t launch_node_h(sph_ctx* c, const sph_particles* s, bool always) {
   return node_props(c, s, always ? 2 : 0);
 }
-hipError_t launch_node_boxes(sph_ctx* c, const sph_particles* s) { return node_props(c, s, 1); }
+hipError_t launch_node_boxes(sph_ctx* c, const sph_particles* s) {
+  const hipError_t e = node_props(c, s, 1);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_qframe, dim3(1), dim3(64), 0, c->stream, c->kp, c->wnode, c->ds);
+  return hipGetLastError();
+}
 
 // Density and force of groups of 4 or 8 particles go through the neighbour
 // lists; larger groups (and flagged groups) through the walking kernels.
