@@ -208,7 +208,7 @@ __global__ __launch_bounds__(64) void k_adj_force(KParams kp, Parts p,
     const int first = ch * CS, count = min(CS, kp.n - first);
     const bool act = slot < count;
     const int k = first + (act ? slot : 0);
-    const Rec rk = rec_load<Rec>(rec, k);
+    const Rec rk = rec[k];
     const CT ak = abar[k];
     // position: FP64 (folded per pair) or the mixed record's codes
     double xk = 0.0, yk = 0.0, zk = 0.0;
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(64) void k_adj_force(KParams kp, Parts p,
       const int j = jn;
       jn = (t + LPI < len) ? row[t + LPI] : k;
       if (j == k) continue;
-      const Rec rj = rec_load<Rec>(rec, j);
+      const Rec rj = rec[j];
       R dx, dy, dz;
       if constexpr (MIXED) {
         dx = qsep(qxk, rj.qx, qs[0]);
@@ -455,7 +455,7 @@ __global__ __launch_bounds__(64) void k_adj_dens2(KParams kp, Parts p,
       const int j = jn;
       jn = (t + LPI < len) ? row[t + LPI] : k;
       if (j == k) continue;
-      const Rec rj = rec_load<Rec>(rec, j);
+      const Rec rj = rec[j];
       R dx, dy, dz;
       if constexpr (MIXED) {
         dx = qsep(qxk, rj.qx, qs[0]);

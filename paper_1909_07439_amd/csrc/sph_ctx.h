@@ -32,41 +32,6 @@ struct alignas(16) FRec32 {
 static_assert(sizeof(FRec64) == 128, "FRec64");
 static_assert(sizeof(FRec32) == 64, "FRec32");
 
-// Force records are stored in tiles of kRecTile particles: tile t holds the
-// 16-byte column c of its records side by side (one 128-byte line per
-// column), the columns one after another.  The lanes that gather the records
-// of consecutive particles (a neighbour-list row runs along the curve) then
-// touch about one line per column between them, where whole records side by
-// side put each lane's column in a line of its own; the gathers are bound by
-// the lines they touch, not by their bytes.
-constexpr int kRecTile = 8;
-inline int64_t rec_slots(int64_t n) { return (n + kRecTile - 1) / kRecTile * kRecTile; }
-
-template <typename Rec>
-__device__ __forceinline__ Rec rec_load(const void* __restrict__ base, int j) {
-  constexpr int C = sizeof(Rec) / 16;
-  const float4* __restrict__ t =
-      reinterpret_cast<const float4*>(base) + (int64_t)(j / kRecTile) * (C * kRecTile) +
-      (j % kRecTile);
-  float4 v[C];
-#pragma unroll
-  for (int c = 0; c < C; ++c) v[c] = t[c * kRecTile];
-  Rec r;
-  __builtin_memcpy(&r, v, sizeof(Rec));
-  return r;
-}
-
-template <typename Rec>
-__device__ __forceinline__ void rec_store(void* __restrict__ base, int j, const Rec& r) {
-  constexpr int C = sizeof(Rec) / 16;
-  float4* __restrict__ t = reinterpret_cast<float4*>(base) +
-                           (int64_t)(j / kRecTile) * (C * kRecTile) + (j % kRecTile);
-  float4 v[C];
-  __builtin_memcpy(v, &r, sizeof(Rec));
-#pragma unroll
-  for (int c = 0; c < C; ++c) t[c * kRecTile] = v[c];
-}
-
 // Raw pointers of an sph_particles, as kernels take them.
 struct Parts {
   int64_t* id;
@@ -94,7 +59,8 @@ struct sph_ctx {
   uint32_t* scan_total = nullptr; // scratch totals (several slots)
   // permute
   double* gtmp = nullptr;  // kMaxFields * n_max
-  double4* xyzm = nullptr; // packed x, y, z, m in key order (written by the permute)
+  double4* xyzm = nullptr; // FP64: packed x, y, z, m in key order (written by the permute)
+  int4* qxyzm = nullptr;    // mixed: position codes (DevState::qf) and m as FP32, key order
   int64_t* gtmp_id = nullptr;
   // tree
   uint8_t* dlev = nullptr;
@@ -127,7 +93,7 @@ struct sph_ctx {
   int32_t* grp_of = nullptr;     // group of each particle (neighbour-list kernel)
   float4* lrec = nullptr;        // per particle: position relative to its leaf's centre, h (FP32)
   // density / force
-  void* frec = nullptr;        // FRec64 or FRec32 per particle, in tiles of kRecTile (rec_load)
+  void* frec = nullptr;        // FRec64 or FRec32 per particle
   double* a1 = nullptr;        // 4 * n_max: new ax, ay, az, dudt inside sph_step
   // adjoint workspace (allocated by the first adjoint call)
   void* adj_abar = nullptr;    // cotangents of a, du/dt in key order (double4 or float4)

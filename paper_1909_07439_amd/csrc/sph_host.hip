@@ -252,7 +252,10 @@ sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ct
   ALLOC(c->scan_total, 16);
   ALLOC(c->gtmp, (int64_t)sph::kMaxFields * N);
   ALLOC(c->gtmp_id, N);
-  ALLOC(c->xyzm, N);
+  if (P.precision == SPH_PREC_MIXED)
+    ALLOC(c->qxyzm, N);
+  else
+    ALLOC(c->xyzm, N);
   ALLOC(c->dlev, N);
   ALLOC(c->lleaf, N);
   ALLOC(c->gsize, N);
@@ -284,7 +287,7 @@ sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ct
   ALLOC(c->lrec, N);
   {
     const size_t rec = (P.precision == SPH_PREC_MIXED) ? sizeof(sph::FRec32) : sizeof(sph::FRec64);
-    e = hipMalloc(&c->frec, rec * (size_t)sph::rec_slots(N));
+    e = hipMalloc(&c->frec, rec * (size_t)N);
     if (e != hipSuccess) return bail(e, "frec");
   }
   ALLOC(c->a1, 4 * N);
@@ -349,7 +352,8 @@ void sph_destroy(sph_ctx* c) {
                   c->nb_off,    c->red_part,    c->red_out,      c->ds,
                   c->leaf_pool, c->gl_off,      c->gl_cnt,       c->nl_idx,      c->nl_len,
                   c->gflag,     c->flag_list,   c->walk_spill,   c->grp_of,    c->lrec,
-                  c->adj_abar,  c->adj_raw,     c->adj_ab,       c->xyzm};
+                  c->adj_abar,  c->adj_raw,     c->adj_ab,       c->xyzm,
+                  c->qxyzm};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->hs) (void)hipHostFree(c->hs);

@@ -516,7 +516,7 @@ struct FieldSet {
   int64_t* id;
   int nf;
   int im;           // index of m in f (x, y, z are f[0..2])
-  double4* xyzm;    // packed x, y, z, m in the new order (the density kernel's gathers)
+  double4* xyzm;    // packed x, y, z, m in the new order (FP64 density gathers), or null
 };
 
 __global__ __launch_bounds__(256) void k_gather(FieldSet fs, const uint32_t* __restrict__ perm,
@@ -536,7 +536,9 @@ __global__ __launch_bounds__(256) void k_copy_back(FieldSet fs, const double* __
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
     for (int f = 0; f < fs.nf; ++f) fs.f[f][k] = tmp[f * stride + k];
     if (fs.id) fs.id[k] = tmp_id[k];
-    fs.xyzm[k] = make_double4(tmp[k], tmp[stride + k], tmp[2 * stride + k], tmp[fs.im * stride + k]);
+    if (fs.xyzm)
+      fs.xyzm[k] =
+          make_double4(tmp[k], tmp[stride + k], tmp[2 * stride + k], tmp[fs.im * stride + k]);
   }
 }
 
@@ -545,6 +547,17 @@ __global__ __launch_bounds__(256) void k_copy_back(FieldSet fs, const double* __
 __global__ __launch_bounds__(256) void k_pack_xyzm(Parts p, int n, double4* __restrict__ xyzm) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
     xyzm[k] = make_double4(p.x[k], p.y[k], p.z[k], p.m[k]);
+}
+
+// The mixed density gather's 16-byte records: position codes in the tree's
+// frame (DevState::qf, set with the node boxes) and m in FP32.
+__global__ __launch_bounds__(256) void k_pack_q(KParams kp, Parts p, int n,
+                                                const DevState* __restrict__ ds,
+                                                int4* __restrict__ q) {
+  const QFrame f = ds->qf;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
+    q[k] = make_int4(qcode(p.x[k], f, 0, kp.periodic[0]), qcode(p.y[k], f, 1, kp.periodic[1]),
+                     qcode(p.z[k], f, 2, kp.periodic[2]), __float_as_int((float)p.m[k]));
 }
 
 // ============================================================================
@@ -1633,7 +1646,7 @@ __device__ __forceinline__ void density_outputs(const KParams& kp, const Parts& 
     r.c = (float)cs;
     r.P = (float)P;
     r.rho = (float)rho;
-    rec_store(frec_out, i, r);
+    reinterpret_cast<FRec32*>(frec_out)[i] = r;
   } else {
     FRec64 r;
     r.x = xi;
@@ -1652,7 +1665,7 @@ __device__ __forceinline__ void density_outputs(const KParams& kp, const Parts& 
     r.P = P;
     r.rho = rho;
     r.h = h;
-    rec_store(frec_out, i, r);
+    reinterpret_cast<FRec64*>(frec_out)[i] = r;
   }
 }
 
@@ -2111,7 +2124,7 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
     const bool act = slot < G.count;
     const int i = G.first + (act ? slot : 0);
     const double xi = p.x[i], yi = p.y[i], zi = p.z[i], hi = p.h[i];
-    const Rec ri = rec_load<Rec>(rec, i);
+    const Rec ri = rec[i];
     float xr = 0.f, yr = 0.f, zr = 0.f;  // FP32 path: position relative to the group centre
     const float hif = (float)hi;
     if constexpr (MIXED) {
@@ -2164,8 +2177,8 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
           const bool two = k2 < npair;
           const int j1 = s_j[k * GS + slot];
           const int j2 = two ? s_j[k2 * GS + slot] : j1;
-          const Rec r1 = rec_load<Rec>(rec, j1);
-          const Rec r2 = rec_load<Rec>(rec, j2);
+          const Rec r1 = rec[j1];
+          const Rec r2 = rec[j2];
           pair(r1);
           if (two) pair(r2);
         }
@@ -2208,8 +2221,8 @@ __global__ __launch_bounds__(64) void k_force(KParams kp, Parts p,
           const bool two = k2 < npair;
           const int j1 = s_j[k * GS + slot];
           const int j2 = two ? s_j[k2 * GS + slot] : j1;
-          const Rec r1 = rec_load<Rec>(rec, j1);
-          const Rec r2 = rec_load<Rec>(rec, j2);
+          const Rec r1 = rec[j1];
+          const Rec r2 = rec[j2];
           pair(r1);
           if (two) pair(r2);
         }
@@ -2799,7 +2812,7 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
                                                       int32_t* __restrict__ gflag,
                                                       int32_t* __restrict__ flag_list,
                                                       const int32_t* __restrict__ grp_of,
-                                                      const double4* __restrict__ xyzm,
+                                                      const void* __restrict__ pos,
                                                       void* __restrict__ frec_out,
                                                       DevState* __restrict__ ds) {
   using R = typename std::conditional<MIXED, float, double>::type;
@@ -2821,11 +2834,10 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
   unsigned long long pairs_final = 0, sums = 0;
   bool outgrew_any = false;
   int ngrew = 0;
-  double lp[3], ilp[3];  // periodic lengths and their inverses (0 on open axes)
-  for (int a = 0; a < 3; ++a) {
-    lp[a] = kp.periodic[a] ? kp.len[a] : 0.0;
-    ilp[a] = kp.periodic[a] ? kp.inv_len[a] : 0.0;
-  }
+  // gathered per row entry: x, y, z, m (FP64), or position codes and m (mixed)
+  const double4* __restrict__ xyzm = reinterpret_cast<const double4*>(pos);
+  const int4* __restrict__ qpos = reinterpret_cast<const int4*>(pos);
+  const QFrame& qf = ds->qf;
 
   for (int g = gr.beg; g < gr.end; g += gr.step) {
     const int first = g * CS, count = min(CS, kp.n - first);
@@ -2836,6 +2848,12 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
     const bool act = inr && gflag[gi] == 0;
     if (ballot64(act) == 0ull) continue;
     const double xi = p.x[i], yi = p.y[i], zi = p.z[i], mi = p.m[i];
+    int32_t qxi = 0, qyi = 0, qzi = 0;  // mixed: i's position codes
+    if constexpr (MIXED) {
+      qxi = qcode(xi, qf, 0, kp.periodic[0]);
+      qyi = qcode(yi, qf, 1, kp.periodic[1]);
+      qzi = qcode(zi, qf, 2, kp.periodic[2]);
+    }
     double h = p.h[i];
     if (!(h > 0.0) || !isfinite(h)) {
       err |= kErrNonFinite;
@@ -2858,36 +2876,38 @@ __global__ __launch_bounds__(64) void k_density_lists(KParams kp, Parts p,
         vv[q] = k < len;
         jj[q] = vv[q] ? row[k] : i;
       }
-      double gx[4], gy[4], gz[4], gm[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const double4 v = xyzm[jj[q]];
-        gx[q] = v.x;
-        gy[q] = v.y;
-        gz[q] = v.z;
-        gm[q] = v.w;
-      }
       // every slot is computed and stored (entries past the row's length sit
       // below CAP and are never read): a conditional use would let the
       // compiler sink each load into it and serialise the four gathers
+      if constexpr (MIXED) {
+        int4 v[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int k = sub + LPI * (t0 + q);
-        double dx, dy, dz;
-        if constexpr (MIXED) {
-          dx = fold_r(xi - gx[q], lp[0], ilp[0]);
-          dy = fold_r(yi - gy[q], lp[1], ilp[1]);
-          dz = fold_r(zi - gz[q], lp[2], ilp[2]);
-        } else {
-          dx = fold(xi - gx[q], kp.len[0], kp.half[0], kp.periodic[0]);
-          dy = fold(yi - gy[q], kp.len[1], kp.half[1], kp.periodic[1]);
-          dz = fold(zi - gz[q], kp.len[2], kp.half[2], kp.periodic[2]);
-        }
-        if constexpr (MIXED) {
-          const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+        for (int q = 0; q < 4; ++q) v[q] = qpos[jj[q]];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int k = sub + LPI * (t0 + q);
+          const float fx = qsep(qxi, v[q].x, qf.step[0]);
+          const float fy = qsep(qyi, v[q].y, qf.step[1]);
+          const float fz = qsep(qzi, v[q].z, qf.step[2]);
           s_r[ent_idx<GS>(k, slot)] = fast_sqrt(fmaf(fz, fz, fmaf(fy, fy, fx * fx)));
-          s_m[ent_idx<GS>(k, slot)] = (float)gm[q];
-        } else {
+          s_m[ent_idx<GS>(k, slot)] = __int_as_float(v[q].w);
+        }
+      } else {
+        double gx[4], gy[4], gz[4], gm[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double4 v = xyzm[jj[q]];
+          gx[q] = v.x;
+          gy[q] = v.y;
+          gz[q] = v.z;
+          gm[q] = v.w;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int k = sub + LPI * (t0 + q);
+          const double dx = fold(xi - gx[q], kp.len[0], kp.half[0], kp.periodic[0]);
+          const double dy = fold(yi - gy[q], kp.len[1], kp.half[1], kp.periodic[1]);
+          const double dz = fold(zi - gz[q], kp.len[2], kp.half[2], kp.periodic[2]);
           s_r[ent_idx<GS>(k, slot)] = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
           s_m[ent_idx<GS>(k, slot)] = gm[q];
         }
@@ -3071,7 +3091,7 @@ void k_force_lists(KParams kp, Parts p,
     const bool act = inr && gflag[grp_of[i]] == 0;
     if (ballot64(act) == 0ull) continue;
     const double xi = p.x[i], yi = p.y[i], zi = p.z[i], hi = p.h[i];
-    const Rec ri = rec_load<Rec>(rec, i);
+    const Rec ri = rec[i];
     const int len = act ? nl_len[i] : 0;
     const int32_t* __restrict__ row = nl_idx + (int64_t)i * kp.nl_cap;
     int lmax = len;
@@ -3137,8 +3157,8 @@ void k_force_lists(KParams kp, Parts p,
       int j2 = (sub + LPI < len) ? row[sub + LPI] : i;
       for (int k = sub; k < lmax; k += 2 * LPI) {
         const bool v1 = k < len, v2 = k + LPI < len;
-        const Rec r1 = rec_load<Rec>(rec, j1);
-        const Rec r2 = rec_load<Rec>(rec, j2);
+        const Rec r1 = rec[j1];
+        const Rec r2 = rec[j2];
         const int kn = k + 2 * LPI;
         const int jn1 = (kn < len) ? row[kn] : i;
         const int jn2 = (kn + LPI < len) ? row[kn + LPI] : i;
@@ -3195,7 +3215,7 @@ void k_force_lists(KParams kp, Parts p,
       int j = (sub < len) ? row[sub] : i;
       for (int k = sub; k < lmax; k += LPI) {
         const bool v = k < len;
-        const Rec rj = rec_load<Rec>(rec, j);
+        const Rec rj = rec[j];
         const int jn = (k + LPI < len) ? row[k + LPI] : i;
         if (v && j != i) pair(rj);
         j = jn;
@@ -3589,7 +3609,7 @@ hipError_t launch_permute(sph_ctx* c, const sph_particles* s, bool outputs_too) 
     if (all[k] == s->m) fs.im = fs.nf;
     fs.f[fs.nf++] = all[k];
   }
-  fs.xyzm = c->xyzm;
+  fs.xyzm = c->kp.precision == SPH_PREC_MIXED ? nullptr : c->xyzm;
   fs.id = s->id;
   const int nb = stream_blocks(c->n);
   hipLaunchKernelGGL(k_gather, dim3(nb), dim3(256), 0, c->stream, fs, c->vals[0], c->gtmp,
@@ -3600,8 +3620,12 @@ hipError_t launch_permute(sph_ctx* c, const sph_particles* s, bool outputs_too) 
 }
 
 hipError_t launch_pack_xyzm(sph_ctx* c, const sph_particles* s) {
-  hipLaunchKernelGGL(k_pack_xyzm, dim3(stream_blocks(c->n)), dim3(256), 0, c->stream,
-                     parts_of(s), c->n, c->xyzm);
+  if (c->kp.precision == SPH_PREC_MIXED)
+    hipLaunchKernelGGL(k_pack_q, dim3(stream_blocks(c->n)), dim3(256), 0, c->stream, c->kp,
+                       parts_of(s), c->n, c->ds, c->qxyzm);
+  else
+    hipLaunchKernelGGL(k_pack_xyzm, dim3(stream_blocks(c->n)), dim3(256), 0, c->stream,
+                       parts_of(s), c->n, c->xyzm);
   return hipGetLastError();
 }
 
@@ -3650,7 +3674,9 @@ hipError_t launch_node_boxes(sph_ctx* c, const sph_particles* s) {
   const hipError_t e = node_props(c, s, 1);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_qframe, dim3(1), dim3(64), 0, c->stream, c->kp, c->wnode, c->ds);
-  return hipGetLastError();
+  // the mixed density gather's records need the frame (the FP64 ones were
+  // packed by the permute)
+  return c->kp.precision == SPH_PREC_MIXED ? launch_pack_xyzm(c, s) : hipGetLastError();
 }
 
 // Density and force of groups of 4 or 8 particles go through the neighbour
@@ -3752,8 +3778,9 @@ static void density_lists_kind(sph_ctx* c, const Parts& p) {
   SPH_LPI_SWITCH_LISTS(c->kp.n_group,
                        hipLaunchKernelGGL((k_density_lists<MIXED, LPI, CAP, KIND>), grid, block,
                                           0, c->stream, c->kp, p, c->ginfo, c->nl_idx, c->nl_len,
-                                          c->gflag, c->flag_list, c->grp_of, c->xyzm, c->frec,
-                                          c->ds));
+                                          c->gflag, c->flag_list, c->grp_of,
+                                          MIXED ? (const void*)c->qxyzm : (const void*)c->xyzm,
+                                          c->frec, c->ds));
 }
 
 template <bool MIXED, int CAP>
