@@ -91,7 +91,7 @@ struct sph_ctx {
   int32_t* flag_list = nullptr;  // indices of the flagged groups (DevState::n_flagged of them)
   int32_t* walk_spill = nullptr; // 2 * kSpill frontier entries per walk wavefront
   int32_t* grp_of = nullptr;     // group of each particle (neighbour-list kernel)
-  float4* lrec = nullptr;        // per particle: position relative to its leaf's centre, h (FP32)
+  int4* qrec = nullptr;          // mixed: position codes (DevState::qf) and h as FP32, key order
   // density / force
   void* frec = nullptr;        // FRec64 or FRec32 per particle
   double* a1 = nullptr;        // 4 * n_max: new ax, ay, az, dudt inside sph_step

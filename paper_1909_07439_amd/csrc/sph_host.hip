@@ -284,7 +284,7 @@ sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ct
   ALLOC(c->flag_list, N);
   ALLOC(c->walk_spill, (int64_t)2 * sph::kSpill * c->walk_blocks);
   ALLOC(c->grp_of, N);
-  ALLOC(c->lrec, N);
+  if (P.precision == SPH_PREC_MIXED) ALLOC(c->qrec, N);
   {
     const size_t rec = (P.precision == SPH_PREC_MIXED) ? sizeof(sph::FRec32) : sizeof(sph::FRec64);
     e = hipMalloc(&c->frec, rec * (size_t)N);
@@ -351,7 +351,7 @@ void sph_destroy(sph_ctx* c) {
                   c->grp_count, c->ginfo,       c->frec,         c->a1,          c->nb_cnt,
                   c->nb_off,    c->red_part,    c->red_out,      c->ds,
                   c->leaf_pool, c->gl_off,      c->gl_cnt,       c->nl_idx,      c->nl_len,
-                  c->gflag,     c->flag_list,   c->walk_spill,   c->grp_of,    c->lrec,
+                  c->gflag,     c->flag_list,   c->walk_spill,   c->grp_of,    c->qrec,
                   c->adj_abar,  c->adj_raw,     c->adj_ab,       c->xyzm,
                   c->qxyzm};
   for (void* p : ptrs)

@@ -549,15 +549,20 @@ __global__ __launch_bounds__(256) void k_pack_xyzm(Parts p, int n, double4* __re
     xyzm[k] = make_double4(p.x[k], p.y[k], p.z[k], p.m[k]);
 }
 
-// The mixed density gather's 16-byte records: position codes in the tree's
-// frame (DevState::qf, set with the node boxes) and m in FP32.
+// The mixed kernels' 16-byte gather records: position codes in the tree's
+// frame (DevState::qf, set with the node boxes) and m (the density gather)
+// or h (the list kernel's candidates) in FP32.
 __global__ __launch_bounds__(256) void k_pack_q(KParams kp, Parts p, int n,
                                                 const DevState* __restrict__ ds,
-                                                int4* __restrict__ q) {
+                                                int4* __restrict__ qm, int4* __restrict__ qh) {
   const QFrame f = ds->qf;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
-    q[k] = make_int4(qcode(p.x[k], f, 0, kp.periodic[0]), qcode(p.y[k], f, 1, kp.periodic[1]),
-                     qcode(p.z[k], f, 2, kp.periodic[2]), __float_as_int((float)p.m[k]));
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const int32_t qx = qcode(p.x[k], f, 0, kp.periodic[0]);
+    const int32_t qy = qcode(p.y[k], f, 1, kp.periodic[1]);
+    const int32_t qz = qcode(p.z[k], f, 2, kp.periodic[2]);
+    qm[k] = make_int4(qx, qy, qz, __float_as_int((float)p.m[k]));
+    qh[k] = make_int4(qx, qy, qz, __float_as_int((float)p.h[k]));
+  }
 }
 
 // ============================================================================
@@ -1012,20 +1017,16 @@ __global__ __launch_bounds__(256) void k_range_boxes(
     const int32_t* __restrict__ nparent, const int32_t* __restrict__ nchild,
     const int32_t* __restrict__ nnchild, WalkNode* __restrict__ wn,
     const int32_t* __restrict__ gfirst, const int32_t* __restrict__ gcount,
-    GroupInfo* __restrict__ gi, float4* __restrict__ lrec, const DevState* __restrict__ ds,
-    int mode, int nb_small) {
+    GroupInfo* __restrict__ gi, const DevState* __restrict__ ds, int mode, int nb_small) {
   if (!h_refresh_needed(ds, mode)) return;
   const int do_bb = mode == 1 ? 1 : 0;
   const int nn = ds->n_nodes, ng = ds->n_groups;
   if ((int)blockIdx.x < nb_small) {
-    // the trip count is uniform over each wavefront (the leaf records below
-    // are written by whole wavefronts)
-    for (int base = blockIdx.x * blockDim.x; base < nn + ng; base += nb_small * blockDim.x) {
-      const int it = base + (int)threadIdx.x;
+    for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < nn + ng;
+         it += nb_small * blockDim.x) {
       const bool is_node = it < nn;
-      const bool item = it < nn + ng && !(is_node && nnchild[it] != 0);
+      const bool item = !(is_node && nnchild[it] != 0);
       int f = 0, e = 0;
-      double c[3] = {0.0, 0.0, 0.0};
       if (item) {
         f = is_node ? nfirst[it] : gfirst[it - nn];
         e = f + (is_node ? ncount[it] : gcount[it - nn]);
@@ -1044,33 +1045,10 @@ __global__ __launch_bounds__(256) void k_range_boxes(
           }
           b.hm = fmax(b.hm, h[s]);
         }
-        if (is_node) {
+        if (is_node)
           write_node_box(b, it, f, e, 0, nchild, wn, do_bb);
-          for (int a = 0; a < 3; ++a) c[a] = wn[it].c[a];
-        } else {
+        else
           write_group_box(b, it - nn, f, e, gi, do_bb);
-        }
-      }
-      // each particle relative to its leaf's centre, and h, in FP32: the
-      // mixed list kernel's candidate loads (before a density pass); one
-      // leaf at a time over the wavefront's lanes, so the stores coalesce
-      if (mode != 0) {
-        uint64_t m = ballot64(item && is_node);
-        while (m != 0ull) {
-          const int src = __builtin_ctzll(m);
-          m &= m - 1ull;
-          const int lf = __builtin_amdgcn_readlane(f, src), le = __builtin_amdgcn_readlane(e, src);
-          double cc[3];
-          for (int a = 0; a < 3; ++a) {
-            const unsigned long long v = (unsigned long long)__double_as_longlong(c[a]);
-            const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, src);
-            const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), src);
-            cc[a] = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-          }
-          for (int q = lf + lane_id(); q < le; q += kWave)
-            lrec[q] = make_float4((float)(x[q] - cc[0]), (float)(y[q] - cc[1]),
-                                  (float)(z[q] - cc[2]), (float)h[q]);
-        }
       }
     }
     return;
@@ -2388,7 +2366,7 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
              const GroupInfo* __restrict__ groups, int32_t* __restrict__ nl_idx,
              int32_t* __restrict__ nl_len, int32_t* __restrict__ gflag,
              int32_t* __restrict__ flag_list, int32_t* __restrict__ grp_of,
-             const float4* __restrict__ lrec, int32_t* __restrict__ walk_spill,
+             const int4* __restrict__ qrec, int32_t* __restrict__ walk_spill,
              DevState* __restrict__ ds) {
   int* __restrict__ spill = walk_spill + (int64_t)blockIdx.x * 2 * kSpill;
   using R = typename std::conditional<MIXED, float, double>::type;
@@ -2408,9 +2386,6 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
   } U;
   __shared__ int s_sl[kSLCapL];  // leaf node ids of the walk
   __shared__ double s_hm[kSGL];  // largest hl of each group
-  // FP32 path: the centre of each flushed leaf relative to the group's centre
-  // (folded), added to the candidates' leaf-relative positions
-  __shared__ float s_loff[3][kLCap];
   // one flag per candidate of a tile: a flushed leaf's range starts there
   __shared__ alignas(4) uint8_t s_start[PER * kWave];
   const int lane = threadIdx.x;
@@ -2433,6 +2408,11 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
     lpf[a] = kp.periodic[a] ? (float)kp.len[a] : 0.f;
     ilpf[a] = kp.periodic[a] ? (float)kp.inv_len[a] : 0.f;
   }
+  // FP32 path: positions are code differences (the tree's fixed-point frame)
+  // from the group's centre; reach bounds the list radius of every pair
+  const QFrame& qf = ds->qf;
+  const double reach =
+      kp.support * margin * (ds->n_nodes > 0 ? (double)nodes[0].hmax : 0.0) * (1.0 + 1e-4);
   bool flagged = false;
   int nflag = 0;
   unsigned long long cands = 0;
@@ -2479,9 +2459,12 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
         pi = Gp.first + (pact ? psl : 0);
         const double xi = p.x[pi], yi = p.y[pi], zi = p.z[pi], hi = p.h[pi];
         if constexpr (MIXED) {
-          xq = (float)fold(xi - Gp.c[0], kp.len[0], kp.half[0], kp.periodic[0]);
-          yq = (float)fold(yi - Gp.c[1], kp.len[1], kp.half[1], kp.periodic[1]);
-          zq = (float)fold(zi - Gp.c[2], kp.len[2], kp.half[2], kp.periodic[2]);
+          xq = qsep(qcode(xi, qf, 0, kp.periodic[0]), qcode(Gp.c[0], qf, 0, kp.periodic[0]),
+                    qf.step[0]);
+          yq = qsep(qcode(yi, qf, 1, kp.periodic[1]), qcode(Gp.c[1], qf, 1, kp.periodic[1]),
+                    qf.step[1]);
+          zq = qsep(qcode(zi, qf, 2, kp.periodic[2]), qcode(Gp.c[2], qf, 2, kp.periodic[2]),
+                    qf.step[2]);
         } else {
           xq = xi;
           yq = yi;
@@ -2550,38 +2533,24 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
       auto radius = [&](const WalkNode& nd) {
         return kp.support * fmax(hm, margin * (double)nd.hmax) * (1.0 + 4e-9);
       };
+      // FP32 path: the group centre's codes; a candidate's offset from the
+      // centre is the wrapped code difference, its nearest image.  A pair's
+      // difference of offsets is then the pair's nearest image whenever it
+      // lies within reach, unless the group's half-width and the reach
+      // together come to half a periodic length on some axis (tiny periodic
+      // boxes): that group folds every pair separation instead.
+      int32_t qgx = 0, qgy = 0, qgz = 0;
+      bool amb = false;
+      if constexpr (MIXED) {
+        qgx = qcode(G.c[0], qf, 0, kp.periodic[0]);
+        qgy = qcode(G.c[1], qf, 1, kp.periodic[1]);
+        qgz = qcode(G.c[2], qf, 2, kp.periodic[2]);
+        for (int a = 0; a < 3; ++a)
+          if (kp.periodic[a] && G.w[a] + reach >= kp.half[a]) amb = true;
+      }
       auto flush = [&](int nleaf) {
         const int total = leaf_offsets(L, nleaf);
         if (lane == 0) cands += (unsigned long long)total * (unsigned)cnt;
-        // FP32 path: a candidate's offset from the group centre is its
-        // leaf-relative position plus its leaf's centre offset, folded once
-        // per leaf.  That is the nearest image of every pair unless the
-        // group box, the leaf box and the search radius together reach half
-        // a periodic length on some axis (tiny periodic boxes); then this
-        // flush folds every pair separation instead.
-        bool amb = false;
-        if constexpr (MIXED) {
-          // a lane's two leaves (kLCap <= 2 * 64) are loaded before either is
-          // used, so their node loads are in flight together
-          static_assert(kLCap <= 2 * kWave, "two flushed leaves per lane at most");
-          const int la = lane, lb = lane + kWave;
-          const WalkNode na = nodes[L.lnode[la < nleaf ? la : 0]];
-          const WalkNode nb = nodes[L.lnode[lb < nleaf ? lb : 0]];
-          auto offset = [&](const WalkNode& nd, int l) {
-            const double rl = radius(nd);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              const double d = fold(nd.c[a] - G.c[a], kp.len[a], kp.half[a], kp.periodic[a]);
-              s_loff[a][l] = (float)d;
-              if (kp.periodic[a] && fabs(d) + (double)nd.w[a] + G.w[a] + rl >= kp.half[a])
-                amb = true;
-            }
-          };
-          if (la < nleaf) offset(na, la);
-          if (lb < nleaf) offset(nb, lb);
-          amb = ballot64(amb) != 0ull;
-          __syncthreads();
-        }
         // leaves hold at least one particle each (tree cells are cut from
         // the sorted keys), so the leaf of candidate c is the number of leaf
         // ranges starting at or before c, less one
@@ -2601,7 +2570,7 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
           }
           __syncthreads();
           // resolve this lane's candidates, then issue all their loads
-          int jj[PER], ll[PER];
+          int jj[PER];
 #pragma unroll
           for (int q = 0; q < PER; ++q) {
             const int t = lane + q * kWave;
@@ -2609,27 +2578,20 @@ void k_lists(KParams kp, Parts p, const WalkNode* __restrict__ nodes,
             const uint64_t b = ballot64(st != 0);
             const int lo = rank_below(b, lt + st);
             lt += popc64(b);
-            jj[q] = -1;
-            ll[q] = 0;
-            if (t < cn) {
-              jj[q] = L.lfirst[lo] + (c0 + t - L.loff[lo]);
-              ll[q] = lo;
-            }
+            jj[q] = t < cn ? L.lfirst[lo] + (c0 + t - L.loff[lo]) : -1;
           }
           R cx[PER], cy[PER], cz[PER], ct[PER];
           if constexpr (MIXED) {
-            // one 16-byte load per candidate: its position relative to its
-            // leaf's centre and its h; the leaf's offset from the group's
-            // centre comes from LDS
-            float4 v[PER];
+            // one 16-byte load per candidate: its position codes and its h
+            int4 v[PER];
 #pragma unroll
-            for (int q = 0; q < PER; ++q) v[q] = lrec[jj[q] >= 0 ? jj[q] : 0];
+            for (int q = 0; q < PER; ++q) v[q] = qrec[jj[q] >= 0 ? jj[q] : 0];
 #pragma unroll
             for (int q = 0; q < PER; ++q) {
-              cx[q] = v[q].x + s_loff[0][ll[q]];
-              cy[q] = v[q].y + s_loff[1][ll[q]];
-              cz[q] = v[q].z + s_loff[2][ll[q]];
-              ct[q] = list_thr(supr, marginr * v[q].w);
+              cx[q] = qsep(v[q].x, qgx, qf.step[0]);
+              cy[q] = qsep(v[q].y, qgy, qf.step[1]);
+              cz[q] = qsep(v[q].z, qgz, qf.step[2]);
+              ct[q] = list_thr(supr, marginr * __int_as_float(v[q].w));
             }
           } else {
             double vx[PER], vy[PER], vz[PER], vh[PER];
@@ -3622,7 +3584,7 @@ hipError_t launch_permute(sph_ctx* c, const sph_particles* s, bool outputs_too) 
 hipError_t launch_pack_xyzm(sph_ctx* c, const sph_particles* s) {
   if (c->kp.precision == SPH_PREC_MIXED)
     hipLaunchKernelGGL(k_pack_q, dim3(stream_blocks(c->n)), dim3(256), 0, c->stream, c->kp,
-                       parts_of(s), c->n, c->ds, c->qxyzm);
+                       parts_of(s), c->n, c->ds, c->qxyzm, c->qrec);
   else
     hipLaunchKernelGGL(k_pack_xyzm, dim3(stream_blocks(c->n)), dim3(256), 0, c->stream,
                        parts_of(s), c->n, c->xyzm);
@@ -3663,7 +3625,7 @@ static hipError_t node_props(sph_ctx* c, const sph_particles* s, int mode) {
   hipLaunchKernelGGL(k_range_boxes, dim3(nb_small + nb_inner), dim3(256), 0, c->stream, s->x,
                      s->y, s->z, s->h, n, c->chunk_box, c->node_first, c->node_count,
                      c->node_parent, c->node_child, c->node_nchild, c->wnode, c->grp_first,
-                     c->grp_count, c->ginfo, c->lrec, c->ds, flag, nb_small);
+                     c->grp_count, c->ginfo, c->ds, flag, nb_small);
   return hipGetLastError();
 }
 
@@ -3743,13 +3705,13 @@ hipError_t launch_lists(sph_ctx* c, const sph_particles* s) {
     SPH_LPI_SWITCH_LISTS(c->kp.n_group,
                          hipLaunchKernelGGL((k_lists<true, LPI>), grid, block, 0, c->stream,
                                             c->kp, p, c->wnode, c->ginfo, c->nl_idx, c->nl_len,
-                                            c->gflag, c->flag_list, c->grp_of, c->lrec,
+                                            c->gflag, c->flag_list, c->grp_of, c->qrec,
                                             c->walk_spill, c->ds));
   } else {
     SPH_LPI_SWITCH_LISTS(c->kp.n_group,
                          hipLaunchKernelGGL((k_lists<false, LPI>), grid, block, 0, c->stream,
                                             c->kp, p, c->wnode, c->ginfo, c->nl_idx, c->nl_len,
-                                            c->gflag, c->flag_list, c->grp_of, c->lrec,
+                                            c->gflag, c->flag_list, c->grp_of, c->qrec,
                                             c->walk_spill, c->ds));
   }
   return hipGetLastError();
