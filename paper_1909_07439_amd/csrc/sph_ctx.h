@@ -10,7 +10,6 @@ constexpr int kMaxFields = 20;
 constexpr int kSortTile = 2048;  // keys per radix-sort block (256 threads x 8)
 constexpr int kTreeTile = 256;   // particles per tree block
 constexpr int kScanTile = 2048;  // elements per scan block
-constexpr int kChunk = 256;     // particles per chunk box of the node-box reduction
 constexpr int kNLCapMax = 256;  // largest neighbour-list row (entries)
 constexpr int kSpill = 4096;    // walk frontier entries per level beyond LDS, per wavefront
 
@@ -76,7 +75,6 @@ struct sph_ctx {
   int32_t* node_parent = nullptr;
   int32_t* node_child = nullptr;
   int32_t* node_nchild = nullptr;
-  double* chunk_box = nullptr;  // 8 per chunk of 256 sorted particles: lo xyz, hi xyz, h_max
   sph::WalkNode* wnode = nullptr;
   int32_t* grp_first = nullptr;
   int32_t* grp_count = nullptr;

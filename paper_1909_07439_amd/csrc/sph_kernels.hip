@@ -875,17 +875,15 @@ __device__ __forceinline__ void tree_guard(DevState* ds, int64_t node_cap) {
 }
 
 // ---- node and group boxes and largest h -----------------------------------
-// Every node and group covers a contiguous range of the sorted particles.
-// k_chunk_boxes reduces fixed chunks of kChunk particles; k_range_boxes then
-// gives each node or group to one wavefront, which reduces the particles of
-// its range directly and takes every whole chunk inside the range from the
-// chunk boxes.  No atomics; min/max are exact, so the boxes are exactly the
-// tight boxes of the particles.
-//
-// mode 1: boxes and h_max; mode 0: the h-only refresh after the density,
-// skipped (the kernels return at once) while the force will use complete
-// neighbour lists or replay stored leaf lists, which need neither node nor
-// group h_max; mode 2: the h-only refresh, always.
+// Every leaf and group covers a contiguous range of the sorted particles:
+// k_range_boxes reduces each one's particles (four per wavefront, 16 lanes
+// each, so the particle loads coalesce).  Inner nodes then take the union of
+// their children's boxes and the largest of their h_max, one launch per
+// level from the deepest up (k_level_boxes).  No atomics.  A leaf's or
+// group's box is exactly the range's; an inner node's holds its children's
+// conservative (rounded-up) boxes, so every box contains its particles.
+// mode 1: boxes and h_max of a new tree; 0: h_max only, skipped on the device
+// while the neighbour lists of the tree are valid; 2: h_max only, always.
 __device__ __forceinline__ bool h_refresh_needed(const DevState* ds, int mode) {
   return mode != 0 || ds->leaf_state != 1 || ds->lists_missing != 0;
 }
@@ -900,66 +898,6 @@ __device__ __forceinline__ void box_empty(Box7& b) {
     b.hi[a] = -SPH_INF;
   }
   b.hm = 0.0;
-}
-
-__device__ __forceinline__ void wave_box(Box7& b, int do_bb) {
-  if (do_bb)
-    for (int a = 0; a < 3; ++a) {
-      b.lo[a] = wave_min_f64(b.lo[a]);
-      b.hi[a] = wave_max_f64(b.hi[a]);
-    }
-  b.hm = wave_max_f64(b.hm);
-}
-
-// Lane-partial box of particles [a, e), lanes striding by 64.
-__device__ __forceinline__ void add_particles(Box7& b, int a, int e, const double* __restrict__ x,
-                                              const double* __restrict__ y,
-                                              const double* __restrict__ z,
-                                              const double* __restrict__ h, int do_bb) {
-#pragma unroll 4
-  for (int s = a + lane_id(); s < e; s += kWave) {
-    if (do_bb) {
-      const double px = x[s], py = y[s], pz = z[s];
-      b.lo[0] = fmin(b.lo[0], px);
-      b.hi[0] = fmax(b.hi[0], px);
-      b.lo[1] = fmin(b.lo[1], py);
-      b.hi[1] = fmax(b.hi[1], py);
-      b.lo[2] = fmin(b.lo[2], pz);
-      b.hi[2] = fmax(b.hi[2], pz);
-    }
-    b.hm = fmax(b.hm, h[s]);
-  }
-}
-
-// cb: 8 doubles per chunk (lo xyz, hi xyz, h_max, unused).
-__global__ __launch_bounds__(256) void k_chunk_boxes(const double* __restrict__ x,
-                                                      const double* __restrict__ y,
-                                                      const double* __restrict__ z,
-                                                      const double* __restrict__ h, int n,
-                                                      double* __restrict__ cb,
-                                                      DevState* __restrict__ ds, int mode,
-                                                      int64_t node_cap) {
-  // boxes of a new tree: its node count is checked before k_range_boxes reads it
-  if (mode == 1 && blockIdx.x == 0 && threadIdx.x == 0) tree_guard(ds, node_cap);
-  if (!h_refresh_needed(ds, mode)) return;
-  const int do_bb = mode == 1 ? 1 : 0;
-  const int nch = (n + kChunk - 1) / kChunk;
-  const int wpb = blockDim.x / kWave;
-  for (int c = blockIdx.x * wpb + (int)(threadIdx.x / kWave); c < nch; c += gridDim.x * wpb) {
-    Box7 b;
-    box_empty(b);
-    add_particles(b, c * kChunk, min(n, (c + 1) * kChunk), x, y, z, h, do_bb);
-    wave_box(b, do_bb);
-    if (lane_id() == 0) {
-      double* o = cb + 8 * (int64_t)c;
-      if (do_bb)
-        for (int a = 0; a < 3; ++a) {
-          o[a] = b.lo[a];
-          o[3 + a] = b.hi[a];
-        }
-      o[6] = b.hm;
-    }
-  }
 }
 
 __device__ __forceinline__ float f32_up(double v) {
@@ -1006,90 +944,112 @@ __device__ __forceinline__ void write_group_box(const Box7& b, int g, int f, int
   }
 }
 
-// Blocks [0, nb_small): one thread per leaf or group (at most 64 particles
-// each; items 0..n_nodes-1 are nodes, the rest groups).  The other blocks:
-// one wavefront per inner node, whose range ends where its next sibling
-// starts, or, for a last child, where its parent's range ends.
+__global__ void k_tree_guard_once(DevState* __restrict__ ds, int64_t node_cap) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) tree_guard(ds, node_cap);
+}
+
 __global__ __launch_bounds__(256) void k_range_boxes(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
-    const double* __restrict__ h, int n, const double* __restrict__ cb,
-    const int32_t* __restrict__ nfirst, const int32_t* __restrict__ ncount,
-    const int32_t* __restrict__ nparent, const int32_t* __restrict__ nchild,
+    const double* __restrict__ h, const int32_t* __restrict__ nfirst,
+    const int32_t* __restrict__ ncount, const int32_t* __restrict__ nchild,
     const int32_t* __restrict__ nnchild, WalkNode* __restrict__ wn,
     const int32_t* __restrict__ gfirst, const int32_t* __restrict__ gcount,
-    GroupInfo* __restrict__ gi, const DevState* __restrict__ ds, int mode, int nb_small) {
+    GroupInfo* __restrict__ gi, const DevState* __restrict__ ds, int mode) {
   if (!h_refresh_needed(ds, mode)) return;
   const int do_bb = mode == 1 ? 1 : 0;
   const int nn = ds->n_nodes, ng = ds->n_groups;
-  if ((int)blockIdx.x < nb_small) {
-    for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < nn + ng;
-         it += nb_small * blockDim.x) {
-      const bool is_node = it < nn;
-      const bool item = !(is_node && nnchild[it] != 0);
-      int f = 0, e = 0;
-      if (item) {
-        f = is_node ? nfirst[it] : gfirst[it - nn];
-        e = f + (is_node ? ncount[it] : gcount[it - nn]);
-        Box7 b;
-        box_empty(b);
-#pragma unroll 4
-        for (int s = f; s < e; ++s) {
-          if (do_bb) {
-            const double px = x[s], py = y[s], pz = z[s];
-            b.lo[0] = fmin(b.lo[0], px);
-            b.hi[0] = fmax(b.hi[0], px);
-            b.lo[1] = fmin(b.lo[1], py);
-            b.hi[1] = fmax(b.hi[1], py);
-            b.lo[2] = fmin(b.lo[2], pz);
-            b.hi[2] = fmax(b.hi[2], pz);
-          }
-          b.hm = fmax(b.hm, h[s]);
-        }
-        if (is_node)
-          write_node_box(b, it, f, e, 0, nchild, wn, do_bb);
-        else
-          write_group_box(b, it - nn, f, e, gi, do_bb);
-      }
-    }
-    return;
-  }
+  // items 0..nn-1 are nodes (inner ones are left to k_level_boxes), the rest
+  // groups; the trip count is uniform over the wavefront (its shuffles)
+  const int seg = lane_id() >> 4, sub = lane_id() & 15;
   const int wpb = blockDim.x / kWave;
-  const int nw = (gridDim.x - nb_small) * wpb;
-  for (int it = (blockIdx.x - nb_small) * wpb + (int)(threadIdx.x / kWave); it < nn; it += nw) {
-    const int nc = nnchild[it];
-    if (nc == 0) continue;
-    const int f = nfirst[it];
-    int e = n;
-    int k = it;
-    while (k > 0) {
-      const int p = nparent[k];
-      if (p < 0) break;
-      if (k + 1 < nchild[p] + nnchild[p]) {
-        e = nfirst[k + 1];
-        break;
-      }
-      k = p;
+  const int nwv = gridDim.x * wpb;
+  for (int base = (blockIdx.x * wpb + (int)(threadIdx.x / kWave)) * 4; base < nn + ng;
+       base += nwv * 4) {
+    const int it = base + seg;
+    const bool is_node = it < nn;
+    const bool item = it < nn + ng && !(is_node && nnchild[it] != 0);
+    int f = 0, e = 0;
+    if (item) {
+      f = is_node ? nfirst[it] : gfirst[it - nn];
+      e = f + (is_node ? ncount[it] : gcount[it - nn]);
     }
     Box7 b;
     box_empty(b);
-    const int c0 = (f + kChunk - 1) / kChunk, c1 = e / kChunk;
-    if (c1 > c0) {
-      add_particles(b, f, c0 * kChunk, x, y, z, h, do_bb);
-      for (int c = c0 + lane_id(); c < c1; c += kWave) {
-        const double* q = cb + 8 * (int64_t)c;
-        if (do_bb)
-          for (int a = 0; a < 3; ++a) {
-            b.lo[a] = fmin(b.lo[a], q[a]);
-            b.hi[a] = fmax(b.hi[a], q[3 + a]);
-          }
-        b.hm = fmax(b.hm, q[6]);
+    for (int s = f + sub; s < e; s += 16) {
+      if (do_bb) {
+        const double px = x[s], py = y[s], pz = z[s];
+        b.lo[0] = fmin(b.lo[0], px);
+        b.hi[0] = fmax(b.hi[0], px);
+        b.lo[1] = fmin(b.lo[1], py);
+        b.hi[1] = fmax(b.hi[1], py);
+        b.lo[2] = fmin(b.lo[2], pz);
+        b.hi[2] = fmax(b.hi[2], pz);
       }
-      add_particles(b, c1 * kChunk, e, x, y, z, h, do_bb);
-    } else {
-      add_particles(b, f, e, x, y, z, h, do_bb);
+      b.hm = fmax(b.hm, h[s]);
     }
-    wave_box(b, do_bb);
-    if (lane_id() == 0) write_node_box(b, it, f, e, nc, nchild, wn, do_bb);
+    for (int d = 8; d > 0; d >>= 1) {
+      if (do_bb)
+        for (int a = 0; a < 3; ++a) {
+          b.lo[a] = fmin(b.lo[a], __shfl_xor(b.lo[a], d, 16));
+          b.hi[a] = fmax(b.hi[a], __shfl_xor(b.hi[a], d, 16));
+        }
+      b.hm = fmax(b.hm, __shfl_xor(b.hm, d, 16));
+    }
+    if (item && sub == 0) {
+      if (is_node)
+        write_node_box(b, it, f, e, 0, nchild, wn, do_bb);
+      else
+        write_group_box(b, it - nn, f, e, gi, do_bb);
+    }
+  }
+}
+
+// Inner nodes of one level (nodes are numbered level by level): the union of
+// their children's boxes and the largest of their h_max; the range ends where
+// the last child's ends.
+__global__ __launch_bounds__(256) void k_level_boxes(int level, const uint32_t* __restrict__ level_off,
+                                                      int nblk, const int32_t* __restrict__ nfirst,
+                                                      const int32_t* __restrict__ nchild,
+                                                      const int32_t* __restrict__ nnchild,
+                                                      WalkNode* __restrict__ wn,
+                                                      const DevState* __restrict__ ds, int mode) {
+  if (!h_refresh_needed(ds, mode)) return;
+  const int nn = ds->n_nodes;
+  const int beg = (int)level_off[level * nblk];
+  const int end = min(level + 1 < kLevels ? (int)level_off[(level + 1) * nblk] : nn, nn);
+  for (int it = beg + blockIdx.x * blockDim.x + threadIdx.x; it < end;
+       it += gridDim.x * blockDim.x) {
+    const int nc = nnchild[it];
+    if (nc == 0) continue;
+    const int c0 = nchild[it];
+    double lo[3] = {SPH_INF, SPH_INF, SPH_INF}, hi[3] = {-SPH_INF, -SPH_INF, -SPH_INF};
+    float hm = 0.f;
+    int last_end = 0;
+    for (int q = 0; q < nc; ++q) {
+      const WalkNode w = wn[c0 + q];
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = fmin(lo[a], w.c[a] - (double)w.w[a]);
+        hi[a] = fmax(hi[a], w.c[a] + (double)w.w[a]);
+      }
+      hm = fmaxf(hm, w.hmax);
+      last_end = w.first + w.count;
+    }
+    if (mode == 1) {
+      WalkNode w;
+      for (int a = 0; a < 3; ++a) {
+        const double c = 0.5 * (lo[a] + hi[a]);
+        w.c[a] = c;
+        w.w[a] = f32_up(fmax(hi[a] - c, c - lo[a]));
+      }
+      w.hmax = hm;
+      w.first = nfirst[it];
+      w.count = last_end - w.first;
+      w.child = c0;
+      w.nchild = nc;
+      wn[it] = w;
+    } else {
+      wn[it].hmax = hm;
+    }
   }
 }
 
@@ -3613,19 +3573,22 @@ hipError_t launch_tree(sph_ctx* c) {
 // current (sorted) ones; h may be the start value or the converged one.
 static hipError_t node_props(sph_ctx* c, const sph_particles* s, int mode) {
   const int n = c->n;
-  const int nch = (n + kChunk - 1) / kChunk;
-  const int flag = mode;
-  hipLaunchKernelGGL(k_chunk_boxes, dim3((nch + 3) / 4), dim3(256), 0, c->stream, s->x, s->y,
-                     s->z, s->h, n, c->chunk_box, c->ds, flag, c->node_cap);
-  // leaves and groups: about one per thread; inner nodes (about a seventh of
-  // the nodes): about two per wavefront
+  // a new tree's node count is checked before the box kernels read it
+  if (mode == 1)
+    hipLaunchKernelGGL(k_tree_guard_once, dim3(1), dim3(64), 0, c->stream, c->ds, c->node_cap);
+  // leaves and groups, four per wavefront
   const int64_t items = c->node_cap + (int64_t)n;
-  const int nb_small = (int)std::min<int64_t>(std::max<int64_t>((items / 2 + 255) / 256, 16), 4096);
-  const int nb_inner = (int)std::min<int64_t>(std::max<int64_t>((items / 2 + 63) / 64, 16), 4096);
-  hipLaunchKernelGGL(k_range_boxes, dim3(nb_small + nb_inner), dim3(256), 0, c->stream, s->x,
-                     s->y, s->z, s->h, n, c->chunk_box, c->node_first, c->node_count,
-                     c->node_parent, c->node_child, c->node_nchild, c->wnode, c->grp_first,
-                     c->grp_count, c->ginfo, c->ds, flag, nb_small);
+  const int nb = (int)std::min<int64_t>(std::max<int64_t>((items / 4 + 15) / 16, 16), 4096);
+  hipLaunchKernelGGL(k_range_boxes, dim3(nb), dim3(256), 0, c->stream, s->x, s->y, s->z, s->h,
+                     c->node_first, c->node_count, c->node_child, c->node_nchild, c->wnode,
+                     c->grp_first, c->grp_count, c->ginfo, c->ds, mode);
+  // inner nodes level by level, the deepest first (the last level holds
+  // leaves only); the level offsets are the scanned per-level node counts
+  const int nblk = (n + kTreeTile - 1) / kTreeTile;
+  const int lb = (int)std::min<int64_t>(std::max<int64_t>((c->node_cap / 4 + 255) / 256, 1), 1024);
+  for (int l = kLevels - 2; l >= 0; --l)
+    hipLaunchKernelGGL(k_level_boxes, dim3(lb), dim3(256), 0, c->stream, l, c->tree_cnt, nblk,
+                       c->node_first, c->node_child, c->node_nchild, c->wnode, c->ds, mode);
   return hipGetLastError();
 }
 
