@@ -944,7 +944,7 @@ __device__ __forceinline__ void write_group_box(const Box7& b, int g, int f, int
   }
 }
 
-__global__ void k_tree_guard_once(DevState* __restrict__ ds, int64_t node_cap) {
+__global__ void k_tree_guard(DevState* __restrict__ ds, int64_t node_cap) {
   if (blockIdx.x == 0 && threadIdx.x == 0) tree_guard(ds, node_cap);
 }
 
@@ -3575,7 +3575,7 @@ static hipError_t node_props(sph_ctx* c, const sph_particles* s, int mode) {
   const int n = c->n;
   // a new tree's node count is checked before the box kernels read it
   if (mode == 1)
-    hipLaunchKernelGGL(k_tree_guard_once, dim3(1), dim3(64), 0, c->stream, c->ds, c->node_cap);
+    hipLaunchKernelGGL(k_tree_guard, dim3(1), dim3(64), 0, c->stream, c->ds, c->node_cap);
   // leaves and groups, four per wavefront
   const int64_t items = c->node_cap + (int64_t)n;
   const int nb = (int)std::min<int64_t>(std::max<int64_t>((items / 4 + 15) / 16, 16), 4096);
