@@ -400,8 +400,14 @@ __global__ __launch_bounds__(256) void k_radix_pass(const uint64_t* __restrict__
   constexpr int NS = PER * 4;  // (key slice, wavefront) sets of 64 keys, in key order
   // wc[d * NS + s]: keys of digit d in set s, then the tile's keys of digit d
   // before set s (at most kSortTile: 16 bits suffice)
-  __shared__ uint16_t wc[256 * NS];
+  // the digit counts (16 KB), then the tile in digit order (24 KB)
+  __shared__ alignas(16) unsigned char s_buf[kSortTile * 12];
+  static_assert(256 * NS * 2 <= kSortTile * 12, "digit counts fit the tile buffer");
+  uint16_t* wc = reinterpret_cast<uint16_t*>(s_buf);
+  uint64_t* s_key = reinterpret_cast<uint64_t*>(s_buf);
+  uint32_t* s_val = reinterpret_cast<uint32_t*>(s_buf + kSortTile * 8);
   __shared__ uint32_t run[256];
+  __shared__ uint32_t lst[256];
   __shared__ uint32_t lds4[4];
   __shared__ int s_tile;
   static_assert(kSortTile <= 65535, "16-bit tile offsets");
@@ -493,17 +499,38 @@ __global__ __launch_bounds__(256) void k_radix_pass(const uint64_t* __restrict__
     __hip_atomic_store(&st[(int64_t)tile * 256 + tid], kStPre | (excl + mine), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
   }
-  // + this digit in earlier tiles
-  run[tid] = gofs + excl;
+  // the tile's keys in digit order in LDS first, so that each digit's run is
+  // stored by consecutive lanes to consecutive addresses
+  uint32_t tot2;
+  const uint32_t ls = block256_excl_scan(mine, lds4, &tot2);  // tile-local start of digit tid
+  lst[tid] = ls;
+  run[tid] = gofs + excl - ls;  // global position of local position 0, for digit tid
   __syncthreads();
+  uint32_t lp[PER];
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
-    const int i = base + k * 256 + tid;
-    if (i < n) {
-      const uint32_t d = (uint32_t)((key[k] >> shift) & 255ull);
-      const uint32_t pos = run[d] + (uint32_t)wc[d * NS + k * 4 + w] + rank[k];
-      kout[pos] = key[k];
-      vout[pos] = val[k];
+    const uint32_t d = (uint32_t)((key[k] >> shift) & 255ull);
+    lp[k] = lst[d] + (uint32_t)wc[d * NS + k * 4 + w] + rank[k];
+  }
+  __syncthreads();  // the counts are overwritten by the sorted tile
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    if (base + k * 256 + tid < n) {
+      s_key[lp[k]] = key[k];
+      s_val[lp[k]] = val[k];
+    }
+  }
+  __syncthreads();
+  const int cnt = min(kSortTile, n - base);
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int q = k * 256 + tid;
+    if (q < cnt) {
+      const uint64_t kk = s_key[q];
+      const uint32_t d = (uint32_t)((kk >> shift) & 255ull);
+      const uint32_t pos = run[d] + (uint32_t)q;
+      kout[pos] = kk;
+      vout[pos] = s_val[q];
     }
   }
 }
