@@ -434,7 +434,8 @@ sph_status sph_density(sph_ctx* c, sph_particles* p, int32_t* iters_out) {
   if (st != SPH_OK) return st;
   if (p->n != c->n) return fail(c, SPH_E_ARG, "n differs from the last sph_build_tree");
   // the packed positions and masses the list and density kernels gather are
-  // taken from the arrays as they are now (m may have changed since the build)
+  // taken from the arrays as they are now (m may have changed since the build;
+  // the mixed code records are packed with the h_max refresh below)
   HIPCHK(c, sph::launch_pack_xyzm(c, p));
   // the node and group h_max are brought up to the h in p->h first (the
   // caller may have changed h since the build, and a later pass on the same

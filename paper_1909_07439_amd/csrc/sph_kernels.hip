@@ -576,12 +576,21 @@ __global__ __launch_bounds__(256) void k_pack_xyzm(Parts p, int n, double4* __re
     xyzm[k] = make_double4(p.x[k], p.y[k], p.z[k], p.m[k]);
 }
 
+// Node h_max refresh modes: 1 a new tree (boxes too), 2 always, 0 only while
+// the neighbour lists of the tree are not valid for the force.
+__device__ __forceinline__ bool h_refresh_needed(const DevState* ds, int mode) {
+  return mode != 0 || ds->leaf_state != 1 || ds->lists_missing != 0;
+}
+
 // The mixed kernels' 16-byte gather records: position codes in the tree's
 // frame (DevState::qf, set with the node boxes) and m (the density gather)
-// or h (the list kernel's candidates) in FP32.
+// or h (the list kernel's candidates) in FP32.  Rewritten with every refresh
+// of the nodes' h_max (mode as there), so that a list pass sees the h the
+// walk's radii were sized for.
 __global__ __launch_bounds__(256) void k_pack_q(KParams kp, Parts p, int n,
-                                                const DevState* __restrict__ ds,
+                                                const DevState* __restrict__ ds, int mode,
                                                 int4* __restrict__ qm, int4* __restrict__ qh) {
+  if (!h_refresh_needed(ds, mode)) return;
   const QFrame f = ds->qf;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
     const int32_t qx = qcode(p.x[k], f, 0, kp.periodic[0]);
@@ -911,10 +920,6 @@ __device__ __forceinline__ void tree_guard(DevState* ds, int64_t node_cap) {
 // conservative (rounded-up) boxes, so every box contains its particles.
 // mode 1: boxes and h_max of a new tree; 0: h_max only, skipped on the device
 // while the neighbour lists of the tree are valid; 2: h_max only, always.
-__device__ __forceinline__ bool h_refresh_needed(const DevState* ds, int mode) {
-  return mode != 0 || ds->leaf_state != 1 || ds->lists_missing != 0;
-}
-
 struct Box7 {
   double lo[3], hi[3], hm;
 };
@@ -3106,8 +3111,9 @@ void k_force_lists(KParams kp, Parts p,
       int j2 = (sub + LPI < len) ? row[sub + LPI] : i;
       for (int k = sub; k < lmax; k += 2 * LPI) {
         const bool v1 = k < len, v2 = k + LPI < len;
-        const Rec r1 = rec[j1];
-        const Rec r2 = rec[j2];
+        Rec r1, r2;
+        if (v1) r1 = rec[j1];
+        if (v2) r2 = rec[j2];
         const int kn = k + 2 * LPI;
         const int jn1 = (kn < len) ? row[kn] : i;
         const int jn2 = (kn + LPI < len) ? row[kn + LPI] : i;
@@ -3568,14 +3574,18 @@ hipError_t launch_permute(sph_ctx* c, const sph_particles* s, bool outputs_too) 
   return hipGetLastError();
 }
 
+// FP64 contexts: x, y, z, m packed for the density gather (the mixed code
+// records are packed with each refresh of the nodes' h_max, node_props)
 hipError_t launch_pack_xyzm(sph_ctx* c, const sph_particles* s) {
-  if (c->kp.precision == SPH_PREC_MIXED)
-    hipLaunchKernelGGL(k_pack_q, dim3(stream_blocks(c->n)), dim3(256), 0, c->stream, c->kp,
-                       parts_of(s), c->n, c->ds, c->qxyzm, c->qrec);
-  else
+  if (c->kp.precision != SPH_PREC_MIXED)
     hipLaunchKernelGGL(k_pack_xyzm, dim3(stream_blocks(c->n)), dim3(256), 0, c->stream,
                        parts_of(s), c->n, c->xyzm);
   return hipGetLastError();
+}
+
+static void pack_q(sph_ctx* c, const sph_particles* s, int mode) {
+  hipLaunchKernelGGL(k_pack_q, dim3(stream_blocks(c->n)), dim3(256), 0, c->stream, c->kp,
+                     parts_of(s), c->n, c->ds, mode, c->qxyzm, c->qrec);
 }
 
 hipError_t launch_tree(sph_ctx* c) {
@@ -3616,6 +3626,9 @@ static hipError_t node_props(sph_ctx* c, const sph_particles* s, int mode) {
   for (int l = kLevels - 2; l >= 0; --l)
     hipLaunchKernelGGL(k_level_boxes, dim3(lb), dim3(256), 0, c->stream, l, c->tree_cnt, nblk,
                        c->node_first, c->node_child, c->node_nchild, c->wnode, c->ds, mode);
+  // mixed: the code records with the current h and m (a new tree's after its
+  // frame, below)
+  if (mode != 1 && c->kp.precision == SPH_PREC_MIXED) pack_q(c, s, mode);
   return hipGetLastError();
 }
 
@@ -3626,9 +3639,10 @@ hipError_t launch_node_boxes(sph_ctx* c, const sph_particles* s) {
   const hipError_t e = node_props(c, s, 1);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_qframe, dim3(1), dim3(64), 0, c->stream, c->kp, c->wnode, c->ds);
-  // the mixed density gather's records need the frame (the FP64 ones were
-  // packed by the permute)
-  return c->kp.precision == SPH_PREC_MIXED ? launch_pack_xyzm(c, s) : hipGetLastError();
+  // the mixed code records need the frame (the FP64 packed positions come
+  // from the permute)
+  if (c->kp.precision == SPH_PREC_MIXED) pack_q(c, s, 1);
+  return hipGetLastError();
 }
 
 // Density and force of groups of 4 or 8 particles go through the neighbour

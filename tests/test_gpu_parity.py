@@ -198,8 +198,11 @@ def boundary_particles(cfg, o, delta=1e-5):
 
 @pytest.mark.parametrize("cfg", WL, ids=WL_IDS)
 def test_mixed_precision_bounds(cfg):
+    check_mixed_bounds(cfg, oracle.evaluate(cfg, oracle.make_params(cfg)))
+
+
+def check_mixed_bounds(cfg, o):
     g, ctx, parts, info = gpu_eval(cfg, sph.SPH_PREC_MIXED)
-    o = oracle.evaluate(cfg, oracle.make_params(cfg))
     eh = rel_err(g["h"], o["h"]).max()
     er = rel_err(g["rho"], o["rho"]).max()
     eo = rel_err(g["omega"], o["omega"]).max()
@@ -219,6 +222,27 @@ def test_mixed_precision_bounds(cfg):
     assert ev < 1e-5
     if not edge[amin]:
         assert edt < 1e-5
+
+
+def open_axes_slab():
+    """A jittered 12^3 lattice with velocities whose x and y axes are open (the
+    particles fill the middle half of a box twice their extent, so the
+    slab has free surfaces) and whose z axis is periodic: the mixed path's
+    position codes then span the root node's box on x and y and the periodic
+    length on z."""
+    c = inputs.lattice(12, jitter=0.2, velocities=True)
+    c.update(periodic=(0, 0, 1), box_lo=(-0.5, -0.5, 0.0), box_len=(2.0, 2.0, 1.0),
+             workload="lattice12v_open_xy")
+    return c
+
+
+def test_open_axes_fp64_parity_and_mixed_bounds():
+    cfg = open_axes_slab()
+    o = oracle.evaluate(cfg, oracle.make_params(cfg))
+    g, ctx, parts, info = gpu_eval(cfg)
+    compare_fp64(g, o)
+    assert info["stats"]["force_pairs"] == int(o["nneigh_force"].sum())
+    check_mixed_bounds(cfg, o)
 
 
 def test_step_fp64_matches_oracle_step():

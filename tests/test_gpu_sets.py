@@ -83,6 +83,19 @@ def test_list_pairs_tiny_periodic_box(kind, precision):
 
 
 @pytest.mark.parametrize("precision", PREC, ids=PREC_IDS)
+def test_list_pairs_open_axes(precision):
+    """A slab with open x and y axes (free surfaces, larger h there) and a
+    periodic z axis: the mixed list kernel's position codes span the root
+    node's box on the open axes."""
+    cfg = inputs.lattice(12, jitter=0.2, velocities=True)
+    cfg.update(periodic=(0, 0, 1), box_lo=(-0.5, -0.5, 0.0), box_len=(2.0, 2.0, 1.0),
+               workload="lattice12v_open_xy")
+    say(f"[sets] {cfg['workload']} n={cfg['n']} precision={precision}")
+    ctx, parts = run_eval(cfg, precision)
+    compare_sets(ctx, parts, cfg)
+
+
+@pytest.mark.parametrize("precision", PREC, ids=PREC_IDS)
 def test_list_pairs_after_steps(precision):
     """Sets after a few leapfrog steps (disordered positions, h changed
     between the list pass and the force)."""
