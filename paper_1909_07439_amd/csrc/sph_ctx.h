@@ -11,6 +11,8 @@ constexpr int kSortTile = 2048;  // keys per radix-sort block (256 threads x 8)
 constexpr int kTreeTile = 256;   // particles per tree block
 constexpr int kScanTile = 2048;  // elements per scan block
 constexpr int kNLCapMax = 256;  // largest neighbour-list row (entries)
+constexpr int kChunk = 256;     // particles per chunk box (inner-node boxes of small trees)
+constexpr int kSmallTree = 1 << 21;  // particles up to which inner nodes take one launch
 constexpr int kSpill = 4096;    // walk frontier entries per level beyond LDS, per wavefront
 
 // Per-particle data the force loop reads for a neighbour j (written by the
@@ -75,6 +77,7 @@ struct sph_ctx {
   int32_t* node_parent = nullptr;
   int32_t* node_child = nullptr;
   int32_t* node_nchild = nullptr;
+  double* chunk_box = nullptr;  // 8 per chunk of kChunk sorted particles: lo xyz, hi xyz, h_max
   sph::WalkNode* wnode = nullptr;
   int32_t* grp_first = nullptr;
   int32_t* grp_count = nullptr;

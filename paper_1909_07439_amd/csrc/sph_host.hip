@@ -270,6 +270,7 @@ sph_status sph_create(const sph_params* prm, int64_t n_max, void* stream, sph_ct
   ALLOC(c->node_child, c->node_cap);
   ALLOC(c->node_nchild, c->node_cap);
   ALLOC(c->wnode, c->node_cap);
+  ALLOC(c->chunk_box, 8 * ((N + sph::kChunk - 1) / sph::kChunk));
   ALLOC(c->grp_first, N);
   ALLOC(c->grp_count, N);
   ALLOC(c->ginfo, N);
@@ -346,7 +347,7 @@ void sph_destroy(sph_ctx* c) {
                   c->scan_part, c->scan_total,  c->gtmp,         c->gtmp_id,     c->dlev,
                   c->lleaf,     c->gsize,        c->gstart,       c->tree_cnt,    c->grp_cnt,
                   c->node_level, c->node_first, c->node_count,   c->node_parent, c->node_child,
-                  c->node_nchild, c->wnode,       c->grp_first,
+                  c->node_nchild, c->chunk_box, c->wnode,       c->grp_first,
                   c->grp_count, c->ginfo,       c->frec,         c->a1,          c->nb_cnt,
                   c->nb_off,    c->red_part,    c->red_out,      c->ds,
                   c->leaf_pool, c->gl_off,      c->gl_cnt,       c->nl_idx,      c->nl_len,
