@@ -980,21 +980,141 @@ __global__ void k_tree_guard(DevState* __restrict__ ds, int64_t node_cap) {
   if (blockIdx.x == 0 && threadIdx.x == 0) tree_guard(ds, node_cap);
 }
 
+// Small trees: every inner node by one wavefront, in the launch of the leaves
+// and groups, from the particles of its range and the boxes of the whole
+// kChunk-particle chunks inside it (k_chunk_boxes); its range ends where its
+// next sibling starts, or, for a last child, where its parent's range ends.
+// One launch instead of one per level; on large trees the chunks' particles
+// are read by many nodes of the lower levels, and the per-level launches win.
+__device__ __forceinline__ void wave_box(Box7& b, int do_bb) {
+  if (do_bb)
+    for (int a = 0; a < 3; ++a) {
+      b.lo[a] = wave_min_f64(b.lo[a]);
+      b.hi[a] = wave_max_f64(b.hi[a]);
+    }
+  b.hm = wave_max_f64(b.hm);
+}
+
+// Lane-partial box of particles [a, e), lanes striding by 64.
+__device__ __forceinline__ void add_particles(Box7& b, int a, int e, const double* __restrict__ x,
+                                              const double* __restrict__ y,
+                                              const double* __restrict__ z,
+                                              const double* __restrict__ h, int do_bb) {
+#pragma unroll 4
+  for (int s = a + lane_id(); s < e; s += kWave) {
+    if (do_bb) {
+      const double px = x[s], py = y[s], pz = z[s];
+      b.lo[0] = fmin(b.lo[0], px);
+      b.hi[0] = fmax(b.hi[0], px);
+      b.lo[1] = fmin(b.lo[1], py);
+      b.hi[1] = fmax(b.hi[1], py);
+      b.lo[2] = fmin(b.lo[2], pz);
+      b.hi[2] = fmax(b.hi[2], pz);
+    }
+    b.hm = fmax(b.hm, h[s]);
+  }
+}
+
+// cb: 8 doubles per chunk (lo xyz, hi xyz, h_max, unused).
+__global__ __launch_bounds__(256) void k_chunk_boxes(const double* __restrict__ x,
+                                                      const double* __restrict__ y,
+                                                      const double* __restrict__ z,
+                                                      const double* __restrict__ h, int n,
+                                                      double* __restrict__ cb,
+                                                      DevState* __restrict__ ds, int mode,
+                                                      int64_t node_cap) {
+  // boxes of a new tree: its node count is checked before k_range_boxes reads it
+  if (mode == 1 && blockIdx.x == 0 && threadIdx.x == 0) tree_guard(ds, node_cap);
+  if (!h_refresh_needed(ds, mode)) return;
+  const int do_bb = mode == 1 ? 1 : 0;
+  const int nch = (n + kChunk - 1) / kChunk;
+  const int wpb = blockDim.x / kWave;
+  for (int c = blockIdx.x * wpb + (int)(threadIdx.x / kWave); c < nch; c += gridDim.x * wpb) {
+    Box7 b;
+    box_empty(b);
+    add_particles(b, c * kChunk, min(n, (c + 1) * kChunk), x, y, z, h, do_bb);
+    wave_box(b, do_bb);
+    if (lane_id() == 0) {
+      double* o = cb + 8 * (int64_t)c;
+      if (do_bb)
+        for (int a = 0; a < 3; ++a) {
+          o[a] = b.lo[a];
+          o[3 + a] = b.hi[a];
+        }
+      o[6] = b.hm;
+    }
+  }
+}
+
+__device__ void inner_ranges(int blk, int nblocks, const double* __restrict__ x,
+                             const double* __restrict__ y, const double* __restrict__ z,
+                             const double* __restrict__ h, int n, const double* __restrict__ cb,
+                             const int32_t* __restrict__ nfirst,
+                             const int32_t* __restrict__ nparent,
+                             const int32_t* __restrict__ nchild,
+                             const int32_t* __restrict__ nnchild, WalkNode* __restrict__ wn,
+                             int nn, int do_bb) {
+  const int wpb = blockDim.x / kWave;
+  const int nw = nblocks * wpb;
+  for (int it = blk * wpb + (int)(threadIdx.x / kWave); it < nn; it += nw) {
+    const int nc = nnchild[it];
+    if (nc == 0) continue;
+    const int f = nfirst[it];
+    int e = n;
+    int k = it;
+    while (k > 0) {
+      const int p = nparent[k];
+      if (p < 0) break;
+      if (k + 1 < nchild[p] + nnchild[p]) {
+        e = nfirst[k + 1];
+        break;
+      }
+      k = p;
+    }
+    Box7 b;
+    box_empty(b);
+    const int c0 = (f + kChunk - 1) / kChunk, c1 = e / kChunk;
+    if (c1 > c0) {
+      add_particles(b, f, c0 * kChunk, x, y, z, h, do_bb);
+      for (int c = c0 + lane_id(); c < c1; c += kWave) {
+        const double* q = cb + 8 * (int64_t)c;
+        if (do_bb)
+          for (int a = 0; a < 3; ++a) {
+            b.lo[a] = fmin(b.lo[a], q[a]);
+            b.hi[a] = fmax(b.hi[a], q[3 + a]);
+          }
+        b.hm = fmax(b.hm, q[6]);
+      }
+      add_particles(b, c1 * kChunk, e, x, y, z, h, do_bb);
+    } else {
+      add_particles(b, f, e, x, y, z, h, do_bb);
+    }
+    wave_box(b, do_bb);
+    if (lane_id() == 0) write_node_box(b, it, f, e, nc, nchild, wn, do_bb);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_range_boxes(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
     const double* __restrict__ h, const int32_t* __restrict__ nfirst,
     const int32_t* __restrict__ ncount, const int32_t* __restrict__ nchild,
     const int32_t* __restrict__ nnchild, WalkNode* __restrict__ wn,
     const int32_t* __restrict__ gfirst, const int32_t* __restrict__ gcount,
-    GroupInfo* __restrict__ gi, const DevState* __restrict__ ds, int mode) {
+    GroupInfo* __restrict__ gi, const DevState* __restrict__ ds, int mode, int nb_items, int n,
+    const double* __restrict__ cb, const int32_t* __restrict__ nparent) {
   if (!h_refresh_needed(ds, mode)) return;
   const int do_bb = mode == 1 ? 1 : 0;
   const int nn = ds->n_nodes, ng = ds->n_groups;
+  if ((int)blockIdx.x >= nb_items) {  // small trees: the inner nodes
+    inner_ranges((int)blockIdx.x - nb_items, (int)gridDim.x - nb_items, x, y, z, h, n, cb,
+                 nfirst, nparent, nchild, nnchild, wn, nn, do_bb);
+    return;
+  }
   // items 0..nn-1 are nodes (inner ones are left to k_level_boxes), the rest
   // groups; the trip count is uniform over the wavefront (its shuffles)
   const int seg = lane_id() >> 4, sub = lane_id() & 15;
   const int wpb = blockDim.x / kWave;
-  const int nwv = gridDim.x * wpb;
+  const int nwv = nb_items * wpb;
   for (int base = (blockIdx.x * wpb + (int)(threadIdx.x / kWave)) * 4; base < nn + ng;
        base += nwv * 4) {
     const int it = base + seg;
@@ -1095,141 +1215,6 @@ __global__ __launch_bounds__(256) void k_level_boxes(int level, const uint32_t* 
   for (int it = beg + blockIdx.x * blockDim.x + threadIdx.x; it < end;
        it += gridDim.x * blockDim.x)
     inner_node(it, nfirst, nchild, nnchild, wn, mode);
-}
-
-// Small trees: every inner node by one wavefront in one launch, from the
-// particles of its range and the boxes of the whole kChunk-particle chunks
-// inside it (k_chunk_boxes); its range ends where its next sibling starts,
-// or, for a last child, where its parent's range ends.  One launch instead of
-// one per level; on large trees the chunks' particles are read by many nodes
-// of the lower levels, and the per-level launches win.
-__device__ __forceinline__ void wave_box(Box7& b, int do_bb) {
-  if (do_bb)
-    for (int a = 0; a < 3; ++a) {
-      b.lo[a] = wave_min_f64(b.lo[a]);
-      b.hi[a] = wave_max_f64(b.hi[a]);
-    }
-  b.hm = wave_max_f64(b.hm);
-}
-
-// Lane-partial box of particles [a, e), lanes striding by 64.
-__device__ __forceinline__ void add_particles(Box7& b, int a, int e, const double* __restrict__ x,
-                                              const double* __restrict__ y,
-                                              const double* __restrict__ z,
-                                              const double* __restrict__ h, int do_bb) {
-#pragma unroll 4
-  for (int s = a + lane_id(); s < e; s += kWave) {
-    if (do_bb) {
-      const double px = x[s], py = y[s], pz = z[s];
-      b.lo[0] = fmin(b.lo[0], px);
-      b.hi[0] = fmax(b.hi[0], px);
-      b.lo[1] = fmin(b.lo[1], py);
-      b.hi[1] = fmax(b.hi[1], py);
-      b.lo[2] = fmin(b.lo[2], pz);
-      b.hi[2] = fmax(b.hi[2], pz);
-    }
-    b.hm = fmax(b.hm, h[s]);
-  }
-}
-
-// cb: 8 doubles per chunk (lo xyz, hi xyz, h_max, unused).
-__global__ __launch_bounds__(256) void k_chunk_boxes(const double* __restrict__ x,
-                                                      const double* __restrict__ y,
-                                                      const double* __restrict__ z,
-                                                      const double* __restrict__ h, int n,
-                                                      double* __restrict__ cb,
-                                                      const DevState* __restrict__ ds, int mode) {
-  if (!h_refresh_needed(ds, mode)) return;
-  const int do_bb = mode == 1 ? 1 : 0;
-  const int nch = (n + kChunk - 1) / kChunk;
-  const int wpb = blockDim.x / kWave;
-  for (int c = blockIdx.x * wpb + (int)(threadIdx.x / kWave); c < nch; c += gridDim.x * wpb) {
-    Box7 b;
-    box_empty(b);
-    add_particles(b, c * kChunk, min(n, (c + 1) * kChunk), x, y, z, h, do_bb);
-    wave_box(b, do_bb);
-    if (lane_id() == 0) {
-      double* o = cb + 8 * (int64_t)c;
-      if (do_bb)
-        for (int a = 0; a < 3; ++a) {
-          o[a] = b.lo[a];
-          o[3 + a] = b.hi[a];
-        }
-      o[6] = b.hm;
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void k_inner_ranges(
-    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
-    const double* __restrict__ h, int n, const double* __restrict__ cb,
-    const int32_t* __restrict__ nfirst, const int32_t* __restrict__ nparent,
-    const int32_t* __restrict__ nchild, const int32_t* __restrict__ nnchild,
-    WalkNode* __restrict__ wn, const DevState* __restrict__ ds, int mode) {
-  if (!h_refresh_needed(ds, mode)) return;
-  const int do_bb = mode == 1 ? 1 : 0;
-  const int nn = ds->n_nodes;
-  const int wpb = blockDim.x / kWave;
-  const int nw = gridDim.x * wpb;
-  for (int it = blockIdx.x * wpb + (int)(threadIdx.x / kWave); it < nn; it += nw) {
-    const int nc = nnchild[it];
-    if (nc == 0) continue;
-    const int f = nfirst[it];
-    int e = n;
-    int k = it;
-    while (k > 0) {
-      const int p = nparent[k];
-      if (p < 0) break;
-      if (k + 1 < nchild[p] + nnchild[p]) {
-        e = nfirst[k + 1];
-        break;
-      }
-      k = p;
-    }
-    Box7 b;
-    box_empty(b);
-    const int c0 = (f + kChunk - 1) / kChunk, c1 = e / kChunk;
-    if (c1 > c0) {
-      add_particles(b, f, c0 * kChunk, x, y, z, h, do_bb);
-      for (int c = c0 + lane_id(); c < c1; c += kWave) {
-        const double* q = cb + 8 * (int64_t)c;
-        if (do_bb)
-          for (int a = 0; a < 3; ++a) {
-            b.lo[a] = fmin(b.lo[a], q[a]);
-            b.hi[a] = fmax(b.hi[a], q[3 + a]);
-          }
-        b.hm = fmax(b.hm, q[6]);
-      }
-      add_particles(b, c1 * kChunk, e, x, y, z, h, do_bb);
-    } else {
-      add_particles(b, f, e, x, y, z, h, do_bb);
-    }
-    wave_box(b, do_bb);
-    if (lane_id() == 0) write_node_box(b, it, f, e, nc, nchild, wn, do_bb);
-  }
-}
-
-// Every inner level in one launch of one block, the deepest first: small
-// trees, and the conditional h_max refresh of the step (mode 0, needed only
-// when some group's rows fell short), where the common case (nothing to do)
-// then costs one launch rather than one per level.
-__global__ __launch_bounds__(1024) void k_levels_one_block(const uint32_t* __restrict__ level_off,
-                                                            int nblk,
-                                                            const int32_t* __restrict__ nfirst,
-                                                            const int32_t* __restrict__ nchild,
-                                                            const int32_t* __restrict__ nnchild,
-                                                            WalkNode* __restrict__ wn,
-                                                            const DevState* __restrict__ ds,
-                                                            int mode) {
-  if (!h_refresh_needed(ds, mode)) return;
-  const int nn = ds->n_nodes;
-  for (int level = kLevels - 2; level >= 0; --level) {
-    int beg, end;
-    level_range(level, level_off, nblk, nn, beg, end);
-    for (int it = beg + (int)threadIdx.x; it < end; it += blockDim.x)
-      inner_node(it, nfirst, nchild, nnchild, wn, mode);
-    __syncthreads();  // this level's nodes before their parents read them
-  }
 }
 
 // Fixed-point frame of the mixed force records (QFrame) for the positions of
@@ -3757,34 +3742,29 @@ hipError_t launch_tree(sph_ctx* c) {
 // current (sorted) ones; h may be the start value or the converged one.
 static hipError_t node_props(sph_ctx* c, const sph_particles* s, int mode) {
   const int n = c->n;
-  // a new tree's node count is checked before the box kernels read it
-  if (mode == 1)
-    hipLaunchKernelGGL(k_tree_guard, dim3(1), dim3(64), 0, c->stream, c->ds, c->node_cap);
-  // leaves and groups, four per wavefront
-  const int64_t items = c->node_cap + (int64_t)n;
-  const int nb = (int)std::min<int64_t>(std::max<int64_t>((items / 4 + 15) / 16, 16), 4096);
-  hipLaunchKernelGGL(k_range_boxes, dim3(nb), dim3(256), 0, c->stream, s->x, s->y, s->z, s->h,
-                     c->node_first, c->node_count, c->node_child, c->node_nchild, c->wnode,
-                     c->grp_first, c->grp_count, c->ginfo, c->ds, mode);
-  // inner nodes: one block over all levels for the step's conditional
-  // refresh, one wavefront per node from chunk boxes on small trees, one
-  // launch per level (the deepest first; the last level holds leaves only)
-  // on large ones; the level offsets are the scanned per-level node counts
-  const int nblk = (n + kTreeTile - 1) / kTreeTile;
-  if (mode == 0) {
-    // the step's conditional refresh (rarely needed): one launch
-    hipLaunchKernelGGL(k_levels_one_block, dim3(1), dim3(1024), 0, c->stream, c->tree_cnt, nblk,
-                       c->node_first, c->node_child, c->node_nchild, c->wnode, c->ds, mode);
-  } else if (n <= kSmallTree) {
+  const bool small = n <= kSmallTree;
+  // leaves and groups four per wavefront; small trees: their inner nodes one
+  // per wavefront in the same launch (from chunk boxes), large trees: one
+  // launch per level afterwards (the deepest first; the last level holds
+  // leaves only; the level offsets are the scanned per-level node counts).
+  // A new tree's node count is checked before the box kernels read it.
+  if (small) {
     const int nch = (n + kChunk - 1) / kChunk;
     hipLaunchKernelGGL(k_chunk_boxes, dim3((nch + 3) / 4), dim3(256), 0, c->stream, s->x, s->y,
-                       s->z, s->h, n, c->chunk_box, c->ds, mode);
-    const int nbi =
-        (int)std::min<int64_t>(std::max<int64_t>((c->node_cap / 8 + 63) / 64, 16), 4096);
-    hipLaunchKernelGGL(k_inner_ranges, dim3(nbi), dim3(256), 0, c->stream, s->x, s->y, s->z,
-                       s->h, n, c->chunk_box, c->node_first, c->node_parent, c->node_child,
-                       c->node_nchild, c->wnode, c->ds, mode);
-  } else {
+                       s->z, s->h, n, c->chunk_box, c->ds, mode, c->node_cap);
+  } else if (mode == 1) {
+    hipLaunchKernelGGL(k_tree_guard, dim3(1), dim3(64), 0, c->stream, c->ds, c->node_cap);
+  }
+  const int64_t items = c->node_cap + (int64_t)n;
+  const int nb = (int)std::min<int64_t>(std::max<int64_t>((items / 4 + 15) / 16, 16), 4096);
+  const int nbi =
+      small ? (int)std::min<int64_t>(std::max<int64_t>((c->node_cap / 8 + 63) / 64, 16), 4096) : 0;
+  hipLaunchKernelGGL(k_range_boxes, dim3(nb + nbi), dim3(256), 0, c->stream, s->x, s->y, s->z,
+                     s->h, c->node_first, c->node_count, c->node_child, c->node_nchild, c->wnode,
+                     c->grp_first, c->grp_count, c->ginfo, c->ds, mode, nb, n, c->chunk_box,
+                     c->node_parent);
+  if (!small) {
+    const int nblk = (n + kTreeTile - 1) / kTreeTile;
     const int lb =
         (int)std::min<int64_t>(std::max<int64_t>((c->node_cap / 4 + 255) / 256, 1), 1024);
     for (int l = kLevels - 2; l >= 0; --l)
