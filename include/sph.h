@@ -67,7 +67,10 @@ typedef struct {
                            1 = M6 quintic spline (support 3h), 2 = Wendland C6 (support 2h) */
   int32_t n_leaf;       /* max particles per tree leaf (Sect. 3.1); 1..64 */
   int32_t n_group;      /* max particles per walk group (Sect. 3.1); one of 4,8,16,32 */
-  int32_t precision;    /* sph_precision: pair arithmetic in FP64 or FP32 */
+  int32_t precision;    /* sph_precision: pair arithmetic in FP64, or in FP32 on separations
+                           formed from 32-bit fixed-point position codes (2^32 per periodic
+                           length; 2^31 over the tree's root box on an open axis) with
+                           positions, h, the integration and the reductions in FP64 */
   double h_tol;         /* h is converged when |S0(h) - m (hfact/h)^3| <= 3 h_tol m (hfact/h)^3,
                            i.e. a Newton step would move it by <= ~h_tol*h; 0 selects the
                            default (1e-14 FP64, 2e-7 mixed); < 0: three fixed passes */
