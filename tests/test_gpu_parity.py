@@ -245,6 +245,28 @@ def test_open_axes_fp64_parity_and_mixed_bounds():
     check_mixed_bounds(cfg, o)
 
 
+def odd_box():
+    """A jittered 12^3 lattice stretched into a periodic box of side lengths
+    1.3, 0.9 and 1.1 (not powers of two, unequal spacings) whose corner is
+    off the origin: the mixed path's code steps L 2^-32 are then inexact in
+    FP32 and differ per axis."""
+    c = inputs.lattice(12, jitter=0.2, velocities=True, seed_variant=3)
+    side = (1.3, 0.9, 1.1)
+    for a, k in enumerate("xyz"):
+        c[k] = c[k] * side[a] - 0.4
+    c.update(box_lo=(-0.4, -0.4, -0.4), box_len=side, workload="lattice12v_box_1.3x0.9x1.1")
+    c["h"] = c["h"] * (side[0] * side[1] * side[2]) ** (1.0 / 3.0)
+    return c
+
+
+def test_odd_box_fp64_parity_and_mixed_bounds():
+    cfg = odd_box()
+    o = oracle.evaluate(cfg, oracle.make_params(cfg))
+    g, ctx, parts, info = gpu_eval(cfg)
+    compare_fp64(g, o)
+    check_mixed_bounds(cfg, o)
+
+
 def test_step_fp64_matches_oracle_step():
     cfg = inputs.lattice(16, jitter=0.1, velocities=True)
     op = oracle.make_params(cfg)

@@ -96,6 +96,21 @@ def test_list_pairs_open_axes(precision):
 
 
 @pytest.mark.parametrize("precision", PREC, ids=PREC_IDS)
+def test_list_pairs_odd_box(precision):
+    """A periodic box of side lengths 1.3, 0.9 and 1.1 off the origin: code
+    steps inexact in FP32 and different per axis."""
+    cfg = inputs.lattice(12, jitter=0.2, velocities=True, seed_variant=3)
+    side = (1.3, 0.9, 1.1)
+    for a, k in enumerate("xyz"):
+        cfg[k] = cfg[k] * side[a] - 0.4
+    cfg.update(box_lo=(-0.4, -0.4, -0.4), box_len=side, workload="lattice12v_box_1.3x0.9x1.1")
+    cfg["h"] = cfg["h"] * (side[0] * side[1] * side[2]) ** (1.0 / 3.0)
+    say(f"[sets] {cfg['workload']} n={cfg['n']} precision={precision}")
+    ctx, parts = run_eval(cfg, precision)
+    compare_sets(ctx, parts, cfg)
+
+
+@pytest.mark.parametrize("precision", PREC, ids=PREC_IDS)
 def test_list_pairs_after_steps(precision):
     """Sets after a few leapfrog steps (disordered positions, h changed
     between the list pass and the force)."""
